@@ -1,0 +1,149 @@
+/*
+ * df.h -- C ABI of libdfmesh, an MI355X (gfx950) library that advances a
+ * uniform gas streaming past a massive, optionally luminous point perturber on
+ * nested, x2-refined Cartesian meshes and reduces the gravitational force the
+ * gas exerts on the perturber.  The method is that of Velasco Romero & Masset
+ * (2018), "Numerical study of dynamical friction with thermal effects -- I",
+ * Sects. 2.1 and 3: the governing equations (eqs. 1-3), the split source /
+ * transport step S(dt/2) T(dt) S(dt/2) (eq. 15), thermal diffusion (eqs.
+ * 19-22), heat release at the perturber's vertex, nested meshes with CommUp /
+ * CommMean / CommFlux and recursive sub-cycling (Sects. 3.1-3.3), and the force
+ * monitor (eq. 18).
+ *
+ * Conventions (code units G = rho0 = c_s = 1 unless set otherwise):
+ *  - the perturber sits at the origin, which is the central vertex of every
+ *    level; level l+1 covers the central half of level l in each dimension,
+ *    with the same number of cells and half the cell size;
+ *  - the gas enters through the x_max face with velocity (-mach c_s, 0, 0);
+ *    every other outer face of level 0 is a zero-gradient outflow boundary;
+ *  - fields: DF_RHO density, DF_E internal energy per unit volume, and the
+ *    face-centred velocities DF_VX, DF_VY, DF_VZ (v_x on the faces normal to
+ *    x, ...);
+ *  - the force is reported as (Fx, Fy, Fz); Fx is the component along the
+ *    perturber's motion through the gas (+x): drag < 0, thrust > 0.
+ *
+ * Memory and streams: the caller owns a device arena (for instance a uint8
+ * tensor) and a HIP stream; the library carves every buffer out of the arena
+ * and launches every kernel on that stream.  Both must outlive the run.  The
+ * library owns the opaque handles and their host metadata.  Host buffers
+ * passed in or out belong to the caller.  A handle is not thread-safe: use it
+ * from one host thread at a time.
+ *
+ * Errors: every function returns DF_OK (0) or a negative DF_E* code;
+ * df_strerror() names a code and df_last_error() returns the text of the last
+ * error raised on the calling thread (with the HIP message for DF_EDEVICE).
+ */
+#ifndef DF_H
+#define DF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DF_OK 0
+#define DF_EINVAL (-1)   /* bad size, level, field or parameter               */
+#define DF_ESTATE (-2)   /* call out of order (step before bind/perturber ...) */
+#define DF_ENOMEM (-3)   /* arena smaller than df_required_bytes()            */
+#define DF_EDEVICE (-4)  /* HIP runtime error                                 */
+#define DF_ENUMERIC (-5) /* density or energy non-positive or not finite      */
+#define DF_EBUSY (-6)    /* engine: no free slot or HBM budget exhausted      */
+
+enum { DF_FP64 = 0, DF_FP32 = 1 };
+enum { DF_RHO = 0, DF_E = 1, DF_VX = 2, DF_VY = 3, DF_VZ = 4 };
+
+typedef struct df_run df_run;
+
+/* Mesh description (Sect. 3.4).
+ *  nx, ny, nz : active cells per level, each even (the perturber is a vertex),
+ *               each a multiple of 4 and >= 16 when nlevels > 1;
+ *  nlevels    : 1..12;
+ *  dx0        : cell size of level 0 (> 0);
+ *  gamma      : adiabatic index (> 1); cfl: Courant factor in (0, 1];
+ *  precision  : DF_FP64 (FP64 storage and arithmetic) or DF_FP32 (FP32
+ *               storage of the departure from the uniform background, FP32
+ *               stencils, FP64 force and totals);
+ *  ghost_fine : ghost width of levels >= 1 (0 selects 10, the least width that
+ *               carries two sub-cycles without a refill, Sect. 3.2.1);
+ *  seed, noise_amp : every active density is multiplied by 1 + noise_amp (2U-1),
+ *               U uniform in [0,1) from a counter-based SplitMix64 stream. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t nlevels;
+  double dx0;
+  double gamma;
+  double cfl;
+  int32_t precision;
+  int32_t ghost_fine;
+  uint64_t seed;
+  double noise_amp;
+} df_mesh_desc;
+
+/* Validate a mesh description and create a run handle (host memory only; no
+ * HIP call).  *out receives the handle.  DF_EINVAL on a bad description. */
+int df_init_mesh(const df_mesh_desc *desc, df_run **out);
+
+/* Device bytes the run needs for its arena (256-byte aligned). */
+int df_required_bytes(const df_run *run, size_t *bytes);
+
+/* Attach a caller-owned device arena of `bytes` bytes at `dev_ptr` (device
+ * pointer, 256-byte aligned) and the HIP stream `stream` (hipStream_t, may be
+ * NULL for the null stream).  The arena is cleared.  DF_ENOMEM if too small. */
+int df_bind(df_run *run, void *dev_ptr, size_t bytes, void *stream);
+
+/* Set the perturber and the gas (Sect. 2, eq. 16): GM >= 0, Plummer softening
+ * eps >= 0 (also the standard deviation of the Gaussian heat-release weights;
+ * eps = 0 splits the heat equally over the 8 cells around the perturber),
+ * luminosity L >= 0, mach = V / c_s >= 0, thermal diffusivity chi >= 0.
+ * Resets t = 0 and writes the initial state (uniform wind plus density noise,
+ * levels made consistent by restriction then prolongation).  Synchronises the
+ * stream.  Requires df_bind(). */
+int df_set_perturber(df_run *run, double GM, double eps, double L, double mach, double chi);
+
+/* Advance n >= 0 coarse steps (each: time step from the Courant and diffusion
+ * limits, then the recursive sub-cycled update of every level).  Enqueues
+ * kernels on the bound stream and returns without synchronising. */
+int df_step(df_run *run, int32_t n);
+
+/* Force on the perturber (eq. 18, FP64): out[0..2] = Fx, Fy, Fz, out[3] = t.
+ * Synchronises the stream; DF_ENUMERIC if the health check of the last steps
+ * found a non-positive or non-finite density or energy. */
+int df_force(df_run *run, double out[4]);
+
+/* Composite totals over uncovered active cells (FP64): out[0] mass,
+ * out[1] internal energy, out[2] kinetic energy.  Synchronises. */
+int df_totals(df_run *run, double out[3]);
+
+/* Copy a field of one level to / from host memory (FP64 values, x fastest).
+ * Centred fields: nx*ny*nz entries.  Face fields: one more entry along their
+ * own axis (DF_VX: (nx+1)*ny*nz, x fastest).  Synchronises.  After
+ * df_set_field, call df_sync_levels() before stepping a nested run. */
+int df_get_field(df_run *run, int32_t level, int32_t field, double *host);
+int df_set_field(df_run *run, int32_t level, int32_t field, const double *host);
+
+/* Restrict every level onto its parent (finest first), then refill the ghost
+ * entries of every finer level from its parent (CommMean then CommUp). */
+int df_sync_levels(df_run *run);
+
+/* The coarse time step the next df_step would take (synchronises). */
+int df_get_dt(df_run *run, double *dt);
+
+/* Run one stage of the level update on a single-level run, with step dt:
+ *  1 velocity kick over dt, 2 compressional heating, 3 thermal diffusion,
+ *  4 heat release, 5 transport, 6 stages 2-4, 7 a whole level step.
+ * Used by the parity tests.  DF_EINVAL for other stages or nested runs. */
+int df_debug_stage(df_run *run, int32_t stage, double dt);
+
+/* Release the handle (not the caller's arena or stream). */
+int df_destroy(df_run *run);
+
+const char *df_strerror(int code);
+const char *df_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DF_H */

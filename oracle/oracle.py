@@ -1,0 +1,189 @@
+"""Python handle on the plain FP64 CPU oracle (``oracle/dfo.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The product package never imports
+it.  This module only marshals arguments; every step of the method is in the C
+file, which follows Sect. 3 of Velasco Romero & Masset (2018).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dfo.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+FIELDS = {"rho": 0, "e": 1, "vx": 2, "vy": 3, "vz": 4}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with FMA contraction off (plain FP64 arithmetic)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+             "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("nlevels", ctypes.c_int), ("g0", ctypes.c_int), ("gf", ctypes.c_int),
+        ("dx0", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("cs", ctypes.c_double),
+        ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("GM", ctypes.c_double), ("eps", ctypes.c_double), ("L", ctypes.c_double),
+        ("mach", ctypes.c_double), ("chi", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        lib.dfo_create.restype = vp
+        lib.dfo_create.argtypes = [ctypes.POINTER(_Params)]
+        lib.dfo_destroy.argtypes = [vp]
+        lib.dfo_step.argtypes = [vp, ip]
+        lib.dfo_time.restype = ctypes.c_double
+        lib.dfo_time.argtypes = [vp]
+        lib.dfo_dt.restype = ctypes.c_double
+        lib.dfo_dt.argtypes = [vp]
+        lib.dfo_force.argtypes = [vp, dp]
+        lib.dfo_totals.argtypes = [vp, dp]
+        lib.dfo_get_field.argtypes = [vp, ip, ip, dp, ip]
+        lib.dfo_set_field.argtypes = [vp, ip, ip, dp, ip]
+        lib.dfo_get_lastface.argtypes = [vp, ip, ip, dp]
+        lib.dfo_sync.argtypes = [vp]
+        lib.dfo_commup.argtypes = [vp, ip]
+        lib.dfo_commmean.argtypes = [vp, ip]
+        lib.dfo_prolong_all.argtypes = [vp, ip]
+        lib.dfo_stage.argtypes = [vp, ip, ctypes.c_double]
+        lib.dfo_heat_weights.argtypes = [vp, ip, dp]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Oracle:
+    """One oracle run.  Parameters as in the C ``dfo_params``; field arrays are
+    returned with shape (nz, ny, nx) (x fastest), active entries only unless
+    ``ghosts=True``."""
+
+    STAGES = {"kick": 1, "compress": 2, "diffuse": 3, "heat": 4, "transport": 5,
+              "sources": 6, "level_step": 7}
+
+    def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0=None, gamma=5.0 / 3.0,
+                 cfl=0.4, rho0=1.0, cs=1.0, seed=1, noise_amp=1e-6, GM=0.01, eps=0.0,
+                 L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None):
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        if dx0 is None:
+            raise ValueError("dx0 is required")
+        if threads is not None:
+            os.environ["OMP_NUM_THREADS"] = str(threads)
+        self._lib = _load()
+        self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
+                         noise_amp, GM, eps, L, mach, chi)
+        self.n = (nx, ny, nz)
+        self.nlevels = nlevels
+        self.g = [g0] + [gf] * (nlevels - 1)
+        self._h = self._lib.dfo_create(ctypes.byref(self.p))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.dfo_destroy(h)
+            self._h = None
+
+    # --- stepping -------------------------------------------------------
+    def step(self, n: int = 1) -> None:
+        self._lib.dfo_step(self._h, int(n))
+
+    def stage(self, name: str, dt: float) -> None:
+        if self._lib.dfo_stage(self._h, self.STAGES[name], float(dt)) != 0:
+            raise ValueError(f"stage {name} not available for this run")
+
+    def dt(self) -> float:
+        return self._lib.dfo_dt(self._h)
+
+    @property
+    def time(self) -> float:
+        return self._lib.dfo_time(self._h)
+
+    # --- results ---------------------------------------------------------
+    def force(self) -> np.ndarray:
+        out = np.zeros(3)
+        self._lib.dfo_force(self._h, _dp(out))
+        return out
+
+    def totals(self) -> np.ndarray:
+        """mass, internal energy, kinetic energy, net boundary mass inflow"""
+        out = np.zeros(4)
+        self._lib.dfo_totals(self._h, _dp(out))
+        return out
+
+    def _shape(self, level, ghosts):
+        g = self.g[level] if ghosts else 0
+        nx, ny, nz = self.n
+        return (nz + 2 * g, ny + 2 * g, nx + 2 * g)
+
+    def field(self, level: int, name: str, ghosts: bool = False) -> np.ndarray:
+        out = np.zeros(self._shape(level, ghosts))
+        if self._lib.dfo_get_field(self._h, level, FIELDS[name], _dp(out), int(ghosts)) != 0:
+            raise ValueError("bad level/field")
+        return out
+
+    def set_field(self, level: int, name: str, arr, ghosts: bool = False) -> None:
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        if a.shape != self._shape(level, ghosts):
+            raise ValueError(f"shape {a.shape} != {self._shape(level, ghosts)}")
+        if self._lib.dfo_set_field(self._h, level, FIELDS[name], _dp(a), int(ghosts)) != 0:
+            raise ValueError("bad level/field")
+
+    def last_face(self, level: int, name: str) -> np.ndarray:
+        """the face-velocity entries with index n along their own axis"""
+        nx, ny, nz = self.n
+        dn = FIELDS[name] - 2
+        shp = {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[dn]
+        out = np.zeros(shp)
+        self._lib.dfo_get_lastface(self._h, level, FIELDS[name], _dp(out))
+        return out
+
+    def sync(self) -> None:
+        self._lib.dfo_sync(self._h)
+
+    def commup(self, coarse_level: int) -> None:
+        self._lib.dfo_commup(self._h, coarse_level)
+
+    def prolong_all(self, coarse_level: int) -> None:
+        self._lib.dfo_prolong_all(self._h, coarse_level)
+
+    def commmean(self, coarse_level: int) -> None:
+        self._lib.dfo_commmean(self._h, coarse_level)
+
+    def heat_weights(self, level: int) -> np.ndarray:
+        nx, ny, nz = self.n
+        out = np.zeros((nz, ny, nx))
+        self._lib.dfo_heat_weights(self._h, level, _dp(out))
+        return out
+
+    def state(self, level: int = 0, ghosts: bool = False) -> dict:
+        return {k: self.field(level, k, ghosts) for k in FIELDS}

@@ -1,0 +1,410 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix:
+exact invariants, closed forms, conservation, symmetry and the second-order
+convergence of smooth solutions.  Each test names the property it pins and
+the part of the paper it comes from.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle
+
+GAMMA = 5.0 / 3.0
+E0 = 1.0 / (GAMMA * (GAMMA - 1.0))  # rho0 c_s^2 / (gamma (gamma-1)), Sect. 3.4
+
+
+def _full_faces(o, level, name):
+    """face field with all n+1 active faces along its own axis"""
+    a = o.field(level, name)
+    last = o.last_face(level, name)
+    ax = {"vx": 2, "vy": 1, "vz": 0}[name]
+    return np.concatenate([a, np.expand_dims(last, ax)], axis=ax)
+
+
+# ----------------------------------------------------------- exact invariants
+
+def test_uniform_flow_stays_uniform_single_level():
+    # GM = 0, L = 0, no noise: every stage is exact on uniform data (bitwise).
+    o = Oracle(16, 16, 16, dx0=0.05, GM=0.0, L=0.0, noise_amp=0.0, mach=0.7, chi=0.1)
+    s0 = o.state()
+    o.step(40)
+    s1 = o.state()
+    for k in s0:
+        assert np.array_equal(s0[k], s1[k]), k
+    assert np.array_equal(s1["rho"], np.ones_like(s1["rho"]))
+    assert np.all(s1["vx"] == -0.7)
+    assert np.all(s1["e"] == E0)
+
+
+def test_uniform_flow_stays_uniform_nested():
+    o = Oracle(16, 16, 16, nlevels=3, dx0=0.2, GM=0.0, L=0.0, noise_amp=0.0, mach=1.3, chi=0.1)
+    o.step(6)
+    for lev in range(3):
+        s = o.state(lev, ghosts=True)
+        assert np.all(s["rho"] == 1.0), lev
+        assert np.all(s["e"] == E0), lev
+        assert np.all(s["vx"] == -1.3), lev
+        assert np.all(s["vy"] == 0.0) and np.all(s["vz"] == 0.0), lev
+    assert np.all(o.force() == 0.0)
+
+
+def test_force_zero_on_uniform_state():
+    # eq. 18 over a grid symmetric about the perturber: uniform gas pulls nowhere
+    o = Oracle(16, 16, 16, nlevels=2, dx0=0.1, GM=0.01, eps=0.02, noise_amp=0.0)
+    assert np.all(o.force() == 0.0)
+
+
+# ------------------------------------------------------------------ symmetry
+
+@pytest.mark.parametrize("nlevels", [1, 2])
+def test_mirror_symmetry_y_z(nlevels):
+    # The setup is symmetric under y -> -y and z -> -z (perturber on the
+    # central vertex, flow along x).  The discrete scheme preserves this
+    # bitwise; the mirror-odd force components vanish to round-off.
+    o = Oracle(16, 16, 16, nlevels=nlevels, dx0=0.08, GM=0.01, eps=0.02, L=2e-3,
+               noise_amp=0.0, mach=0.8, chi=0.1)
+    o.step(8)
+    for lev in range(nlevels):
+        for name in ("rho", "e", "vx"):
+            a = o.field(lev, name)
+            assert np.array_equal(a, a[:, ::-1, :]), (lev, name, "y")
+            assert np.array_equal(a, a[::-1, :, :]), (lev, name, "z")
+        vy = _full_faces(o, lev, "vy")
+        assert np.array_equal(vy, -vy[:, ::-1, :]), lev
+        assert np.array_equal(vy, vy[::-1, :, :]), lev
+        vz = _full_faces(o, lev, "vz")
+        assert np.array_equal(vz, -vz[::-1, :, :]), lev
+        assert np.array_equal(vz, vz[:, ::-1, :]), lev
+    F = o.force()
+    assert F[0] != 0.0
+    assert abs(F[1]) <= 1e-12 * abs(F[0]) and abs(F[2]) <= 1e-12 * abs(F[0])
+
+
+# ------------------------------------------------------- diffusion (eqs. 19-22)
+
+@pytest.mark.parametrize("modes", [(0, 1, 0), (1, 2, 3), (2, 0, 1)])
+def test_diffusion_cosine_mode_decays_exactly(modes):
+    # Discrete cosine modes are eigenvectors of the flux-form Laplacian with
+    # the level-0 boundaries (zero gradient everywhere, fixed inflow value at
+    # x_max): e' ~ cos(kx(i+1/2)dx) cos(ky(j+1/2)dx) cos(kz(k+1/2)dx) with
+    # kx = pi (m+1/2)/((n+1/2) dx), ky,kz = pi m / (n dx).  One explicit step
+    # multiplies the mode by 1 - chi dt sum_d 4 sin^2(k_d dx/2)/dx^2; a
+    # diffusing (not anti-diffusing) update requires the factor to be < 1.
+    n, dx, chi, A = 12, 0.1, 0.1, 1e-3
+    o = Oracle(n, n, n, dx0=dx, GM=0.0, noise_amp=0.0, chi=chi, mach=0.3)
+    mx, my, mz = modes
+    kx = math.pi * (mx + 0.5) / ((n + 0.5) * dx)
+    ky = math.pi * my / (n * dx)
+    kz = math.pi * mz / (n * dx)
+    c = (np.arange(n) + 0.5) * dx
+    mode = (np.cos(kz * c)[:, None, None] * np.cos(ky * c)[None, :, None] * np.cos(kx * c)[None, None, :])
+    o.set_field(0, "e", E0 + A * mode)
+    dt = 0.4 * dx * dx / (6 * chi)
+    o.stage("diffuse", dt)
+    lam = sum(4.0 * math.sin(k * dx / 2) ** 2 / dx ** 2 for k in (kx, ky, kz))
+    factor = 1.0 - chi * dt * lam
+    assert factor < 1.0
+    got = o.field(0, "e") - E0
+    assert np.max(np.abs(got - factor * A * mode)) < 1e-14
+
+
+def _gaussian_error(n, sigma_cells):
+    dx = 1.0 / n
+    chi = 0.05
+    o = Oracle(n, n, n, dx0=dx, GM=0.0, noise_amp=0.0, chi=chi, mach=0.3)
+    c = (np.arange(n) - n / 2 + 0.5) * dx
+    r2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
+    s0 = sigma_cells * (1.0 / 32)
+    A = 1e-2
+    o.set_field(0, "e", E0 * (1.0 + A * np.exp(-r2 / (2 * s0 * s0))))
+    t_end = s0 * s0 / (2 * chi)  # sigma^2 doubles
+    dt0 = 0.4 * dx * dx / (6 * chi)
+    nsteps = int(math.ceil(t_end / dt0))
+    dt = t_end / nsteps
+    for _ in range(nsteps):
+        o.stage("diffuse", dt)
+    s2 = s0 * s0 + 2 * chi * t_end
+    exact = E0 * A * (s0 * s0 / s2) ** 1.5 * np.exp(-r2 / (2 * s2))
+    return np.max(np.abs(o.field(0, "e") - E0 - exact)) / (E0 * A)
+
+
+def test_gaussian_diffusion_closed_form_second_order():
+    # heat kernel: sigma^2 = sigma0^2 + 2 chi t, peak (sigma0/sigma)^3; error O(dx^2)
+    e1 = _gaussian_error(32, 2.0)
+    e2 = _gaussian_error(64, 2.0)
+    assert e2 < 5e-3
+    assert 3.0 < e1 / e2 < 5.0, (e1, e2)
+
+
+# ----------------------------------------------------- acoustics (Sect. 4.2.1)
+
+def _pulse_speeds(n, axis, mach, t_end):
+    # an acoustic pulse at rest splits into two halves that travel at
+    # -V +- c_s along the flow (x) or +- c_s across it (y); GM = chi = L = 0.
+    # The centroids of the two halves give the two signal speeds.  The pulse
+    # never reaches the boundary.  c_s = sqrt(gamma p0/rho0) = 1 (Sect. 3.4).
+    dx, A, w = 1.0 / n, 1e-5, 0.04
+    shape = [4, 4, 4]
+    shape[2 - axis] = n
+    nx, ny, nz = shape[2], shape[1], shape[0]
+    o = Oracle(nx, ny, nz, dx0=dx, GM=0.0, L=0.0, chi=0.0, noise_amp=0.0, mach=mach)
+    y = (np.arange(n) - n / 2 + 0.5) * dx
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    prof = np.broadcast_to(np.exp(-y * y / (2 * w * w)).reshape(bshape), tuple(shape))
+    o.set_field(0, "rho", 1.0 + A * prof)
+    o.set_field(0, "e", E0 * (1.0 + GAMMA * A * prof))
+    while o.time < t_end - 1e-12:
+        o.step(1)
+    t = o.time
+    rho = o.field(0, "rho") - 1.0
+    line = rho.mean(axis=tuple(d for d in range(3) if d != 2 - axis))
+    mid = -mach * t  # the two halves sit symmetrically about the advected centre
+    right, left = y > mid, y < mid
+    cr = np.sum(y[right] * line[right]) / np.sum(line[right])
+    cl = np.sum(y[left] * line[left]) / np.sum(line[left])
+    return cr / t, cl / t
+
+
+def test_linear_sound_speed_adiabatic():
+    # across the flow: +-c_s; an isothermal update (no compressional heating,
+    # SubStep3) would give sqrt(1/gamma) = 0.775, a dropped pressure term 0.
+    errs = []
+    for n in (128, 256):
+        cr, cl = _pulse_speeds(n, 1, 0.0, 0.25)
+        errs.append(max(abs(cr - 1.0), abs(cl + 1.0)))
+    assert errs[1] < 5e-3, errs
+    assert errs[1] < errs[0], errs
+
+
+def test_sound_speed_doppler_along_flow():
+    # along the flow (gas moving at -V): signal speeds -V + c_s and -V - c_s
+    mach = 0.5
+    cr, cl = _pulse_speeds(256, 0, mach, 0.2)
+    assert abs(cr - (1.0 - mach)) < 1e-2, cr
+    assert abs(cl - (-1.0 - mach)) < 1e-2, cl
+
+
+# ------------------------------------------------------ heat release (Sect. 3.4)
+
+def test_heat_split_over_eight_cells():
+    o = Oracle(8, 8, 8, dx0=0.1, GM=0.0, eps=0.0, L=1e-3, noise_amp=0.0)
+    w = o.heat_weights(0)
+    nz = np.argwhere(w != 0.0)
+    assert len(nz) == 8
+    assert set(map(tuple, nz)) == {(k, j, i) for k in (3, 4) for j in (3, 4) for i in (3, 4)}
+    assert np.all(w[w != 0.0] == 0.125)
+
+
+@pytest.mark.parametrize("eps", [0.0, 0.2])
+def test_heat_release_total(eps):
+    # energy released over one step is L dt, to the round-off of adding small
+    # increments to e ~ 0.9 in up to n^3 cells
+    n, dx, L, dt = 16, 0.1, 3e-3, 0.01
+    o = Oracle(n, n, n, dx0=dx, GM=0.0, eps=eps, L=L, noise_amp=0.0)
+    e0 = o.field(0, "e")
+    o.stage("heat", dt)
+    dE = np.sum(o.field(0, "e") - e0) * dx ** 3
+    assert abs(dE - L * dt) < 1e-10 * L * dt
+    w = o.heat_weights(0)
+    assert abs(np.sum(w) - 1.0) < 1e-14
+
+
+# --------------------------------------------------------------- conservation
+
+def test_mass_accounting_single_level():
+    # transport is conservative: the mass change equals the net inflow through
+    # the boundary faces (inflow injection at x_max, outflow elsewhere)
+    o = Oracle(16, 16, 16, dx0=0.06, GM=0.02, eps=0.12, L=2e-3, mach=0.9, chi=0.1,
+               noise_amp=1e-3, seed=7)
+    m0 = o.totals()[0]
+    o.step(12)
+    m1, _, _, inflow = o.totals()
+    assert abs((m1 - m0) - inflow) < 2e-15 * m0 * 16
+    assert abs(inflow) > 1e-10
+
+
+@pytest.mark.parametrize("nlevels", [2, 3])
+def test_composite_mass_conservation(nlevels):
+    # with flux matching (CommFlux) and mean restriction (CommMean) the mass
+    # of uncovered coarse cells plus fine cells changes only through the
+    # level-0 boundary (Sect. 3.2.3)
+    o = Oracle(16, 16, 16, nlevels=nlevels, dx0=0.16, GM=0.02, eps=0.04, L=2e-3, mach=0.9,
+               chi=0.1, noise_amp=1e-3, seed=11)
+    m0 = o.totals()[0]
+    o.step(4)
+    m1, _, _, inflow = o.totals()
+    assert abs((m1 - m0) - inflow) < 1e-14 * m0 * 16, (m1 - m0, inflow)
+
+
+def test_covered_cells_hold_restricted_fine_data():
+    # after a coarse step the covered coarse cells are the 8-cell means of the
+    # fine level (CommMean), so the composite mass counts each region once
+    o = Oracle(16, 16, 16, nlevels=2, dx0=0.16, GM=0.02, eps=0.04, L=2e-3, mach=0.9,
+               chi=0.1, noise_amp=1e-3, seed=11)
+    o.step(1)
+    rho_c = o.field(0, "rho")
+    fine = o.field(1, "rho")
+    restricted = fine.reshape(8, 2, 8, 2, 8, 2).mean(axis=(1, 3, 5))
+    cov = rho_c[4:12, 4:12, 4:12]
+    assert np.max(np.abs(cov - restricted)) < 1e-15
+
+
+# --------------------------------------------------------- nested-mesh transfer
+
+def test_restriction_of_prolongation_is_identity():
+    # CommUp then CommMean returns the coarse data (Sect. 3.2.1-3.2.2): the
+    # eight children of a coarse cell sit symmetrically about its centre, the
+    # four coincident fine faces about the coarse face.
+    o = Oracle(16, 16, 16, nlevels=2, dx0=0.1, GM=0.0, noise_amp=0.0)
+    rng = np.random.default_rng(3)
+    sh = (16 + 6, 16 + 6, 16 + 6)
+    coarse = {}
+    for name in ("rho", "e", "vx", "vy", "vz"):
+        a = 1.0 + 0.1 * rng.standard_normal(sh)
+        coarse[name] = a
+        o.set_field(0, name, a, ghosts=True)
+    o.prolong_all(0)
+    o.commmean(0)
+    for name in ("rho", "e", "vx", "vy", "vz"):
+        got = o.field(0, name, ghosts=True)
+        sl = slice(3 + 4, 3 + 12)
+        d = np.max(np.abs(got[sl, sl, sl] - coarse[name][sl, sl, sl]))
+        assert d < 1e-15 * 4, (name, d)
+
+
+def test_prolongation_reproduces_linear_data():
+    # van Leer-limited interpolation is exact on linear data (no limiting on a
+    # monotone linear profile): fine values equal the linear field at the fine
+    # positions, for cell centres and for faces (staggered alignment)
+    n, dx = 16, 0.1
+    o = Oracle(n, n, n, nlevels=2, dx0=dx, GM=0.0, noise_amp=0.0)
+    g = 3
+    idx = np.arange(-g, n + g)
+    xc = (idx - n / 2 + 0.5) * dx
+    xf = (idx - n / 2) * dx
+    a, b, c = 0.3, -0.2, 0.7
+
+    def lin(x, y, z):
+        return 1.0 + a * x[None, None, :] + b * y[None, :, None] + c * z[:, None, None]
+
+    o.set_field(0, "rho", lin(xc, xc, xc), ghosts=True)
+    o.set_field(0, "vx", lin(xf, xc, xc), ghosts=True)
+    o.set_field(0, "vz", lin(xc, xc, xf), ghosts=True)
+    o.prolong_all(0)
+    gf = 10
+    fidx = np.arange(-gf, n + gf)
+    fdx = dx / 2
+    fxc = (fidx - n / 2 + 0.5) * fdx
+    fxf = (fidx - n / 2) * fdx
+    for name, want in (("rho", lin(fxc, fxc, fxc)), ("vx", lin(fxf, fxc, fxc)), ("vz", lin(fxc, fxc, fxf))):
+        got = o.field(1, name, ghosts=True)
+        assert np.max(np.abs(got - want)) < 1e-14, name
+
+
+def test_ghost_width_independence():
+    # The fine ghost shell must outlast two sub-cycles without a refill
+    # (Sect. 3.2.1).  With a width of 10 (twice the one-cycle dependency
+    # radius of 5) the active cells are bitwise those of a wider shell;
+    # a too-thin shell changes them (negative control).
+    kw = dict(nlevels=2, dx0=0.16, GM=0.02, eps=0.04, L=2e-3, mach=0.9, chi=0.1,
+              noise_amp=1e-3, seed=5)
+    runs = {gf: Oracle(16, 16, 16, gf=gf, **kw) for gf in (10, 12, 6)}
+    for r in runs.values():
+        r.step(3)
+    for lev in (0, 1):
+        for name in ("rho", "e", "vx", "vy", "vz"):
+            assert np.array_equal(runs[10].field(lev, name), runs[12].field(lev, name)), (lev, name)
+    assert not np.array_equal(runs[10].field(1, "rho"), runs[6].field(1, "rho"))
+
+
+# ------------------------------------------------------------- gravity and force
+
+def test_kick_gravity_matches_analytic_gradient():
+    # uniform gas, GM > 0: the face velocities change by -h dPhi/dx of the
+    # Plummer potential (eq. 16), second order in dx at fixed position
+    errs = []
+    for n in (16, 32):
+        dx = 0.8 / n
+        GM, eps, h = 0.01, 0.1, 1e-3
+        o = Oracle(n, n, n, dx0=dx, GM=GM, eps=eps, noise_amp=0.0, mach=0.0, chi=0.0)
+        o.stage("kick", h)
+        u = o.field(0, "vx")
+        xf = (np.arange(n) - n / 2) * dx
+        yc = (np.arange(n) - n / 2 + 0.5) * dx
+        X, Y, Z = xf[None, None, :], yc[None, :, None], yc[:, None, None]
+        gx = -GM * X / (X * X + Y * Y + Z * Z + eps * eps) ** 1.5
+        # interior faces only (face 0 borders a copied ghost)
+        errs.append(np.max(np.abs(u[:, :, 1:] - h * gx[:, :, 1:])))
+    assert errs[1] < errs[0] / 3.0, errs
+
+
+def test_cold_drag_negative_and_quadratic_in_mass():
+    # the wake of a cold perturber pulls it backwards (drag, Sect. 2.2 sign
+    # convention) and, at small GM, scales as GM^2 (linear response times
+    # the GM in eq. 18)
+    F = []
+    for GM in (2e-3, 4e-3):
+        o = Oracle(16, 16, 16, dx0=0.05, GM=GM, eps=0.1, L=0.0, noise_amp=0.0, mach=0.5, chi=0.1)
+        o.step(20)
+        F.append(o.force()[0])
+    assert F[0] < 0.0 and F[1] < 0.0
+    assert abs(F[1] / F[0] - 4.0) < 0.05, F
+
+
+def test_heating_force_positive_and_linear_in_luminosity():
+    # the heating force F(M,L) - F(M,0) (eq. 5) is a thrust
+    # and is proportional to L at small L (linear regime, Sect. 2.2)
+    kw = dict(dx0=0.05, GM=2e-3, eps=0.1, noise_amp=0.0, mach=0.5, chi=0.1)
+    Fs = {}
+    for L in (0.0, 1e-4, 2e-4):
+        o = Oracle(16, 16, 16, L=L, **kw)
+        o.step(20)
+        Fs[L] = o.force()[0]
+    h1, h2 = Fs[1e-4] - Fs[0.0], Fs[2e-4] - Fs[0.0]
+    assert h1 > 0.0 and h2 > 0.0
+    assert abs(h2 / h1 - 2.0) < 0.01, (h1, h2)
+
+
+# --------------------------------------------------------------- time step
+
+def test_time_step_rule_diffusion_limited_config1():
+    # 32^3, dx = 0.024, chi = 0.1: the diffusion limit 0.4 dx^2/(6 chi) binds
+    o = Oracle(32, dx0=0.024, GM=0.01, eps=0.048, mach=0.5, chi=0.1)
+    assert math.isclose(o.dt(), 0.4 * 0.024 ** 2 / 0.6, rel_tol=1e-14)
+
+
+def test_time_step_rule_courant_when_adiabatic():
+    o = Oracle(8, dx0=0.1, GM=0.0, noise_amp=0.0, mach=1.5, chi=0.0)
+    assert math.isclose(o.dt(), 0.4 * 0.1 / 2.5, rel_tol=1e-14)
+    o2 = Oracle(8, nlevels=3, dx0=0.4, GM=0.0, noise_amp=0.0, mach=1.5, chi=0.0)
+    # every level gives the same 2^l dt_l for a uniform state
+    assert math.isclose(o2.dt(), 0.4 * 0.4 / 2.5, rel_tol=1e-14)
+
+
+# ------------------------------------------------------------------ transport
+
+def _advection_error(n):
+    # a density bump at uniform pressure and velocity is carried unchanged at
+    # the flow speed (a contact); chi = 0, GM = 0.  Compare with the shifted
+    # profile after the bump moved 4 of its widths... less than the box.
+    dx = 1.0 / n
+    o = Oracle(n, 8, 8, dx0=dx, GM=0.0, L=0.0, chi=0.0, noise_amp=0.0, mach=0.5)
+    x = (np.arange(n) - n / 2 + 0.5) * dx
+    w = 0.08
+    prof = lambda xx: 1.0 + 1e-3 * np.exp(-((xx - 0.15) ** 2) / (2 * w * w))
+    o.set_field(0, "rho", np.broadcast_to(prof(x)[None, None, :], (8, 8, n)))
+    # keep pressure uniform: e = e0 everywhere (already)
+    while o.time < 0.5 - 1e-12:
+        o.step(1)
+    t = o.time
+    want = prof(x + 0.5 * t)
+    got = o.field(0, "rho")[4, 4, :]
+    inner = np.abs(x) < 0.4
+    return np.max(np.abs(got - want)[inner]) / 1e-3
+
+
+def test_contact_advection_converges():
+    e1, e2 = _advection_error(64), _advection_error(128)
+    assert e2 < 0.03
+    assert e1 / e2 > 2.5, (e1, e2)
