@@ -986,6 +986,22 @@ int dfo_get_lastface(void *h, int l, int f, double *out) {
   return 0;
 }
 
+int dfo_set_lastface(void *h, int l, int f, const double *in) {
+  run_t *R = (run_t *)h;
+  if (!field_ok(R, l, f) || f < S_VX) return -1;
+  lev_t *L = &R->lev[l];
+  int dn = f - S_VX, t1, t2;
+  tdims(dn, &t1, &t2);
+  size_t a = 0;
+  for (int b2 = 0; b2 < L->n[t2]; ++b2)
+    for (int b1 = 0; b1 < L->n[t1]; ++b1) {
+      int id[3];
+      id[dn] = L->n[dn]; id[t1] = b1; id[t2] = b2;
+      L->st[f][IX(L, id[0], id[1], id[2])] = in[a++];
+    }
+  return 0;
+}
+
 /* make the hierarchy consistent after fields were set: restrict every level
  * onto its parent (finest first), refill level-0 ghosts, prolong ghosts */
 void dfo_sync(void *h) { restrict_prolong_all((run_t *)h); }

@@ -66,6 +66,7 @@ def _load():
         lib.dfo_get_field.argtypes = [vp, ip, ip, dp, ip]
         lib.dfo_set_field.argtypes = [vp, ip, ip, dp, ip]
         lib.dfo_get_lastface.argtypes = [vp, ip, ip, dp]
+        lib.dfo_set_lastface.argtypes = [vp, ip, ip, dp]
         lib.dfo_sync.argtypes = [vp]
         lib.dfo_commup.argtypes = [vp, ip]
         lib.dfo_commmean.argtypes = [vp, ip]
@@ -166,6 +167,28 @@ class Oracle:
         out = np.zeros(shp)
         self._lib.dfo_get_lastface(self._h, level, FIELDS[name], _dp(out))
         return out
+
+    def set_last_face(self, level: int, name: str, arr) -> None:
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        self._lib.dfo_set_lastface(self._h, level, FIELDS[name], _dp(a))
+
+    def full_field(self, level: int, name: str) -> np.ndarray:
+        """active entries; face fields include entry n along their own axis"""
+        a = self.field(level, name)
+        if name in ("vx", "vy", "vz"):
+            ax = {"vx": 2, "vy": 1, "vz": 0}[name]
+            a = np.concatenate([a, np.expand_dims(self.last_face(level, name), ax)], axis=ax)
+        return a
+
+    def set_full_field(self, level: int, name: str, arr) -> None:
+        a = np.asarray(arr, dtype=np.float64)
+        if name in ("vx", "vy", "vz"):
+            ax = {"vx": 2, "vy": 1, "vz": 0}[name]
+            n = a.shape[ax] - 1
+            self.set_field(level, name, np.take(a, np.arange(n), axis=ax))
+            self.set_last_face(level, name, np.take(a, n, axis=ax))
+        else:
+            self.set_field(level, name, a)
 
     def sync(self) -> None:
         self._lib.dfo_sync(self._h)

@@ -1,0 +1,228 @@
+"""ctypes marshalling for libdfmesh.so.  One Python function per C entry point
+(same names without the ``df_`` prefix) plus :class:`Run`, which owns a
+device arena allocated by PyTorch and binds the current HIP stream."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libdfmesh.so")
+
+DF_FP64, DF_FP32 = 0, 1
+FIELDS = {"rho": 0, "e": 1, "vx": 2, "vy": 3, "vz": 4}
+STAGES = {"kick": 1, "compress": 2, "diffuse": 3, "heat": 4, "transport": 5, "sources": 6,
+          "level_step": 7}
+
+
+class DFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libdfmesh error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("nlevels", ctypes.c_int32),
+        ("dx0", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("ghost_fine", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run paper_1812_03191_amd/build.py (there is no CPU fallback)")
+    # the HIP runtime that PyTorch loaded must be the one the library uses
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "df_init_mesh": [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)],
+        "df_required_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+        "df_bind": [vp, vp, ctypes.c_size_t, vp],
+        "df_set_perturber": [vp] + [ctypes.c_double] * 5,
+        "df_step": [vp, i32],
+        "df_force": [vp, dp],
+        "df_totals": [vp, dp],
+        "df_get_field": [vp, i32, i32, dp],
+        "df_set_field": [vp, i32, i32, dp],
+        "df_sync_levels": [vp],
+        "df_get_dt": [vp, dp],
+        "df_debug_stage": [vp, i32, ctypes.c_double],
+        "df_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.df_strerror.restype = ctypes.c_char_p
+    lib.df_strerror.argtypes = [ctypes.c_int]
+    lib.df_last_error.restype = ctypes.c_char_p
+    lib.df_last_error.argtypes = []
+    _lib = lib
+    return lib
+
+
+def _ck(rc: int) -> None:
+    if rc != 0:
+        raise DFError(rc, _lib.df_last_error().decode() or _lib.df_strerror(rc).decode())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# ---------------------------------------------------------------- entry points
+
+def init_mesh(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
+              ghost_fine=0, seed=1, noise_amp=1e-6) -> int:
+    lib = _load()
+    d = MeshDesc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp)
+    h = ctypes.c_void_p()
+    _ck(lib.df_init_mesh(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def required_bytes(h) -> int:
+    n = ctypes.c_size_t()
+    _ck(_load().df_required_bytes(h, ctypes.byref(n)))
+    return n.value
+
+
+def bind(h, dev_ptr: int, nbytes: int, stream: int) -> None:
+    _ck(_load().df_bind(h, dev_ptr, nbytes, stream))
+
+
+def set_perturber(h, GM, eps, L, mach, chi) -> None:
+    _ck(_load().df_set_perturber(h, GM, eps, L, mach, chi))
+
+
+def step(h, n: int) -> None:
+    _ck(_load().df_step(h, int(n)))
+
+
+def force(h) -> np.ndarray:
+    out = np.zeros(4)
+    _ck(_load().df_force(h, _dp(out)))
+    return out
+
+
+def totals(h) -> np.ndarray:
+    out = np.zeros(3)
+    _ck(_load().df_totals(h, _dp(out)))
+    return out
+
+
+def get_field(h, level: int, field: int, out: np.ndarray) -> None:
+    _ck(_load().df_get_field(h, level, field, _dp(out)))
+
+
+def set_field(h, level: int, field: int, arr: np.ndarray) -> None:
+    _ck(_load().df_set_field(h, level, field, _dp(arr)))
+
+
+def sync_levels(h) -> None:
+    _ck(_load().df_sync_levels(h))
+
+
+def get_dt(h) -> float:
+    out = ctypes.c_double()
+    _ck(_load().df_get_dt(h, ctypes.byref(out)))
+    return out.value
+
+
+def debug_stage(h, stage: int, dt: float) -> None:
+    _ck(_load().df_debug_stage(h, int(stage), float(dt)))
+
+
+def destroy(h) -> None:
+    _ck(_load().df_destroy(h))
+
+
+# ------------------------------------------------------------------ Run
+
+class Run:
+    """One solver run on a GPU: the arena is a uint8 torch tensor on
+    ``device``; kernels go to the stream current at construction."""
+
+    def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0, gamma=5.0 / 3.0, cfl=0.4,
+                 precision=DF_FP64, ghost_fine=0, seed=1, noise_amp=1e-6, device="cuda"):
+        import torch
+
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        self.n = (nx, ny, nz)
+        self.nlevels = nlevels
+        self._h = init_mesh(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed,
+                            noise_amp)
+        self.nbytes = required_bytes(self._h)
+        self.device = torch.device(device)
+        self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        bind(self._h, self.arena.data_ptr(), self.nbytes, self.stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                destroy(h)
+            finally:
+                self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_perturber(self, GM, eps, L, mach, chi):
+        set_perturber(self._h, GM, eps, L, mach, chi)
+
+    def step(self, n=1):
+        step(self._h, n)
+
+    def force(self):
+        return force(self._h)
+
+    def totals(self):
+        return totals(self._h)
+
+    def dt(self):
+        return get_dt(self._h)
+
+    def sync_levels(self):
+        sync_levels(self._h)
+
+    def stage(self, name, dt):
+        debug_stage(self._h, STAGES[name], dt)
+
+    def shape(self, name):
+        nx, ny, nz = self.n
+        e = [nx, ny, nz]
+        if name in ("vx", "vy", "vz"):
+            e["xyz".index(name[1])] += 1
+        return (e[2], e[1], e[0])
+
+    def field(self, level, name):
+        out = np.zeros(self.shape(name))
+        get_field(self._h, level, FIELDS[name], out)
+        return out
+
+    def set_field(self, level, name, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        if a.shape != self.shape(name):
+            raise ValueError(f"shape {a.shape} != {self.shape(name)}")
+        set_field(self._h, level, FIELDS[name], a)

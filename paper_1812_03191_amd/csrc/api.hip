@@ -1,0 +1,501 @@
+// api.hip -- C ABI of libdfmesh (include/df.h): run handles, arena layout,
+// the recursive sub-cycling scheduler and the host side of the reductions.
+//
+// Scheduling (Velasco Romero & Masset 2018, Sects. 3.1 and 3.3): one coarse
+// step computes the time step on the device (Courant and diffusion limits of
+// every level, eq. 55 with two sub-cycles per level), then runs Cycle(0):
+//   Cycle(l): [Cycle(l+1) twice, finer level first] ; level step on l ;
+//             CommUp l -> l+1 ; CommMean l+1 -> l
+// Every launch goes to the caller's stream; nothing in df_step waits on the
+// device, so a sequence of steps can be captured into a HIP graph.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "df.h"
+#include "dfk.h"
+
+using dfk::Geo;
+using dfk::LevBufs;
+using dfk::MAXLEV;
+using dfk::NQ;
+using dfk::Phys;
+using dfk::Scal;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char *where) {
+  if (e == hipSuccess) return DF_OK;
+  return fail(DF_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int launch_check(const char *where) { return hip_check(hipGetLastError(), where); }
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+}  // namespace
+
+struct df_run {
+  df_mesh_desc desc{};
+  int nl = 0;
+  Geo geo[MAXLEV]{};
+  Phys phys{};
+  LevBufs buf[MAXLEV]{};
+  int cur[MAXLEV]{};
+  size_t vol[MAXLEV]{};
+  size_t acc_n[MAXLEV]{};
+  size_t npart[MAXLEV]{};
+  size_t need = 0;
+  char *base = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  Scal *scal = nullptr;
+  bool bound = false;
+  bool ready = false;
+  double eps = 0.0;
+};
+
+namespace {
+
+// ----------------------------------------------------------- arena layout
+struct Carver {
+  char *base;
+  size_t off = 0;
+  template <class T>
+  T *take(size_t count) {
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+void carve(df_run *R, char *base) {
+  Carver c{base};
+  R->scal = c.take<Scal>(1);
+  for (int l = 0; l < R->nl; ++l) {
+    LevBufs &B = R->buf[l];
+    size_t v = R->vol[l];
+    for (int s = 0; s < 2; ++s)
+      for (int m = 0; m < NQ; ++m) B.q[s][m] = c.take<double>(v);
+    for (int d = 0; d < 3; ++d) B.v[d] = c.take<double>(v);
+    B.etmp = c.take<double>(v);
+    B.acc = R->acc_n[l] ? c.take<double>(R->acc_n[l]) : nullptr;
+    const Geo &G = R->geo[l];
+    B.hw = c.take<double>((size_t)G.n[0] * G.n[1] * G.n[2]);
+    B.part = c.take<double>(3 * R->npart[l]);
+  }
+  R->need = c.off;
+}
+
+// ------------------------------------------------------- heat-release weights
+// Normalised Gaussian weights of standard deviation sigma = eps over the
+// active cells of a level, truncated at r_min + 8 sigma, r_min the distance of
+// the eight cells around the perturber's vertex; sigma = 0 gives those eight
+// cells 1/8 each (the split of Sect. 3.4).  Stored on the smallest centred box
+// of active cells that holds every non-zero weight.
+void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3]) {
+  double dx = G.dx;
+  auto cen = [&](int d, int i) { return ((double)i - 0.5 * (double)G.n[d] + 0.5) * dx; };
+  double r2min = 3.0 * (0.5 * dx) * (0.5 * dx);
+  double rcut = std::sqrt(r2min) + 8.0 * sigma;
+  int half = (sigma == 0.0) ? 1 : (int)std::ceil(rcut / dx) + 1;
+  for (int d = 0; d < 3; ++d) edge[d] = 2 * half < G.n[d] ? 2 * half : G.n[d];
+  w.assign((size_t)edge[0] * edge[1] * edge[2], 0.0);
+  double sum = 0.0;
+  for (int c = 0; c < edge[2]; ++c)
+    for (int b = 0; b < edge[1]; ++b)
+      for (int a = 0; a < edge[0]; ++a) {
+        int i = G.n[0] / 2 - edge[0] / 2 + a, j = G.n[1] / 2 - edge[1] / 2 + b, k = G.n[2] / 2 - edge[2] / 2 + c;
+        double x = cen(0, i), y = cen(1, j), z = cen(2, k);
+        double r2 = x * x + y * y + z * z;
+        double g = 0.0;
+        if (sigma == 0.0) g = (r2 <= r2min * (1.0 + 1e-12)) ? 1.0 : 0.0;
+        else if (std::sqrt(r2) <= rcut) g = std::exp(-(r2 - r2min) / (2.0 * sigma * sigma));
+        w[((size_t)c * edge[1] + b) * edge[0] + a] = g;
+        sum += g;
+      }
+  for (double &x : w) x /= sum;
+}
+
+// ------------------------------------------------------------- scheduler
+void level_step(df_run *R, int l, const double *dtp, double scale) {
+  hipStream_t st = R->stream;
+  const Geo &G = R->geo[l];
+  LevBufs &B = R->buf[l];
+  const Phys &P = R->phys;
+  int c = R->cur[l];
+  const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
+  const double *facc = Gf ? R->buf[l + 1].acc : nullptr;
+  dfk::kick(st, G, P, B, c, dtp, 0.5 * scale);
+  dfk::compress(st, G, P, B, c, dtp, scale);
+  dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true);
+  std::swap(B.etmp, B.q[c][1]);
+  dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc);
+  dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc);
+  dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc);
+  dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true);
+  R->cur[l] = 1 - c;
+}
+
+void cycle(df_run *R, int l) {
+  if (l + 1 < R->nl) {
+    dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1]);
+    cycle(R, l + 1);
+    cycle(R, l + 1);
+  }
+  level_step(R, l, &R->scal->dt[l], 1.0);
+  if (l + 1 < R->nl) {
+    dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
+                R->cur[l + 1]);
+    dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
+                  R->cur[l]);
+  }
+}
+
+void compute_dt(df_run *R, int advance) {
+  for (int l = 0; l < R->nl; ++l) dfk::signal_speed(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->scal);
+  dfk::dt_final(R->stream, R->geo, R->nl, R->phys, R->scal, advance);
+}
+
+void sync_levels(df_run *R) {
+  for (int l = R->nl - 2; l >= 0; --l)
+    dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l], R->cur[l]);
+  for (int l = 0; l + 1 < R->nl; ++l)
+    dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
+                R->cur[l + 1]);
+}
+
+double *field_ptr(df_run *R, int l, int f) {
+  LevBufs &B = R->buf[l];
+  if (f == DF_RHO) return B.q[R->cur[l]][0];
+  if (f == DF_E) return B.q[R->cur[l]][1];
+  return B.v[f - DF_VX];
+}
+
+int check_run(const df_run *R, bool need_ready) {
+  if (!R) return fail(DF_EINVAL, "null run handle");
+  if (!R->bound) return fail(DF_ESTATE, "run not bound to an arena (df_bind)");
+  if (need_ready && !R->ready) return fail(DF_ESTATE, "perturber not set (df_set_perturber)");
+  return DF_OK;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+}  // namespace
+
+// ================================================================== ABI
+
+extern "C" {
+
+const char *df_strerror(int code) {
+  switch (code) {
+    case DF_OK: return "ok";
+    case DF_EINVAL: return "invalid argument";
+    case DF_ESTATE: return "call out of order";
+    case DF_ENOMEM: return "arena too small";
+    case DF_EDEVICE: return "HIP runtime error";
+    case DF_ENUMERIC: return "non-positive or non-finite density or energy";
+    case DF_EBUSY: return "no free slot or HBM budget";
+    default: return "unknown error";
+  }
+}
+
+const char *df_last_error(void) { return g_last_error.c_str(); }
+
+int df_init_mesh(const df_mesh_desc *d, df_run **out) {
+  if (!d || !out) return fail(DF_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->nlevels < 1 || d->nlevels > MAXLEV) return fail(DF_EINVAL, "nlevels must be 1..12");
+  const int n[3] = {d->nx, d->ny, d->nz};
+  for (int k = 0; k < 3; ++k) {
+    if (n[k] < 2 || (n[k] % 2) != 0 || n[k] > 4096) return fail(DF_EINVAL, "cell counts must be even, 2..4096");
+    if (d->nlevels > 1 && (n[k] % 4 != 0 || n[k] < 16))
+      return fail(DF_EINVAL, "nested runs need cell counts that are multiples of 4 and >= 16");
+  }
+  if (!(d->dx0 > 0.0) || !std::isfinite(d->dx0)) return fail(DF_EINVAL, "dx0 must be positive");
+  if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return fail(DF_EINVAL, "gamma must exceed 1");
+  if (!(d->cfl > 0.0) || d->cfl > 1.0) return fail(DF_EINVAL, "cfl must be in (0, 1]");
+  if (d->precision != DF_FP64 && d->precision != DF_FP32) return fail(DF_EINVAL, "unknown precision");
+  if (d->precision == DF_FP32) return fail(DF_EINVAL, "FP32 storage is not available in this build");
+  int gf = d->ghost_fine == 0 ? 10 : d->ghost_fine;
+  if (d->nlevels > 1 && (gf < 10 || gf > 16)) return fail(DF_EINVAL, "ghost_fine must be 10..16");
+  if (!std::isfinite(d->noise_amp) || std::fabs(d->noise_amp) >= 0.5) return fail(DF_EINVAL, "noise_amp out of range");
+
+  df_run *R = new df_run();
+  R->desc = *d;
+  R->nl = d->nlevels;
+  for (int l = 0; l < R->nl; ++l) {
+    Geo &G = R->geo[l];
+    for (int k = 0; k < 3; ++k) G.n[k] = n[k];
+    G.g = (l == 0) ? 3 : gf;
+    for (int k = 0; k < 3; ++k) G.s[k] = G.n[k] + 2 * G.g;
+    G.sy = G.s[0];
+    G.sz = (long)G.s[0] * G.s[1];
+    G.off = G.g + G.g * G.sy + G.g * G.sz;
+    G.dx = std::ldexp(d->dx0, -l);
+    G.level = l;
+    G.bc = (l == 0);
+    G.has_fine = (l + 1 < R->nl);
+    R->vol[l] = (size_t)G.s[0] * G.s[1] * G.s[2];
+    size_t face_max = (size_t)G.n[0] * G.n[1];
+    if ((size_t)G.n[0] * G.n[2] > face_max) face_max = (size_t)G.n[0] * G.n[2];
+    if ((size_t)G.n[1] * G.n[2] > face_max) face_max = (size_t)G.n[1] * G.n[2];
+    // frontier accumulators of a fine level: [dir][side][quantity][face]
+    R->acc_n[l] = (l > 0) ? (size_t)3 * 2 * NQ * face_max : 0;
+    R->npart[l] = dfk::part_count(G);
+  }
+  carve(R, nullptr);
+  *out = R;
+  return DF_OK;
+}
+
+int df_required_bytes(const df_run *R, size_t *bytes) {
+  if (!R || !bytes) return fail(DF_EINVAL, "null argument");
+  *bytes = R->need;
+  return DF_OK;
+}
+
+int df_bind(df_run *R, void *dev_ptr, size_t bytes, void *stream) {
+  if (!R || !dev_ptr) return fail(DF_EINVAL, "null argument");
+  if (((uintptr_t)dev_ptr) % ALIGN) return fail(DF_EINVAL, "arena must be 256-byte aligned");
+  if (bytes < R->need) return fail(DF_ENOMEM, "arena smaller than df_required_bytes()");
+  R->base = (char *)dev_ptr;
+  R->bytes = bytes;
+  R->stream = (hipStream_t)stream;
+  carve(R, R->base);
+  int rc = hip_check(hipMemsetAsync(R->base, 0, R->need, R->stream), "df_bind clear");
+  if (rc) return rc;
+  R->bound = true;
+  R->ready = false;
+  return DF_OK;
+}
+
+int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, double chi) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (!finite_nonneg(GM) || !finite_nonneg(eps) || !finite_nonneg(L) || !finite_nonneg(mach) ||
+      !finite_nonneg(chi))
+    return fail(DF_EINVAL, "GM, eps, L, mach and chi must be finite and >= 0");
+  const df_mesh_desc &d = R->desc;
+  Phys &P = R->phys;
+  P.gamma = d.gamma;
+  P.gm1 = d.gamma - 1.0;
+  P.GM = GM;
+  P.eps2 = eps * eps;
+  P.L = L;
+  P.rho0 = 1.0;
+  double cs = 1.0;
+  P.V = mach * cs;
+  P.chi = chi;
+  P.e0 = P.rho0 * cs * cs / (d.gamma * (d.gamma - 1.0));
+  P.cfl = d.cfl;
+  R->eps = eps;
+  hipStream_t st = R->stream;
+  // heat tables
+  for (int l = 0; l < R->nl; ++l) {
+    std::vector<double> w;
+    int edge[3] = {0, 0, 0};
+    heat_table(R->geo[l], eps, w, edge);
+    for (int d = 0; d < 3; ++d) R->buf[l].hw_n[d] = edge[d];
+    rc = hip_check(hipMemcpyAsync(R->buf[l].hw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, st),
+                   "heat table upload");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(st), "heat table upload");
+    if (rc) return rc;
+  }
+  // initial state: both transported sets and the diffusion buffer hold the
+  // uniform background so that no entry of any array is ever uninitialised
+  for (int l = 0; l < R->nl; ++l) {
+    LevBufs &B = R->buf[l];
+    R->cur[l] = 1;
+    dfk::init_state(st, R->geo[l], P, B, 1, d.seed, 0.0);
+    std::swap(B.etmp, B.q[1][1]);
+    dfk::init_state(st, R->geo[l], P, B, 1, d.seed, 0.0);
+    std::swap(B.etmp, B.q[1][1]);
+    R->cur[l] = 0;
+    dfk::init_state(st, R->geo[l], P, B, 0, d.seed, d.noise_amp);
+    if (B.acc) dfk::zero(st, B.acc, R->acc_n[l]);
+  }
+  Scal zero{};
+  rc = hip_check(hipMemcpyAsync(R->scal, &zero, sizeof(Scal), hipMemcpyHostToDevice, st), "scalars");
+  if (rc) return rc;
+  sync_levels(R);
+  rc = launch_check("df_set_perturber");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(st), "df_set_perturber");
+  if (rc) return rc;
+  R->ready = true;
+  return DF_OK;
+}
+
+int df_step(df_run *R, int32_t n) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (n < 0) return fail(DF_EINVAL, "negative step count");
+  for (int s = 0; s < n; ++s) {
+    compute_dt(R, 1);
+    cycle(R, 0);
+  }
+  return launch_check("df_step");
+}
+
+static int reduce3(df_run *R, int slot, double out[3]) {
+  double *parts[MAXLEV];
+  int np[MAXLEV];
+  for (int l = 0; l < R->nl; ++l) {
+    np[l] = slot == 0 ? dfk::force_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l])
+                      : dfk::totals_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l]);
+    parts[l] = R->buf[l].part;
+  }
+  dfk::force_final(R->stream, parts, np, R->nl, R->scal, slot);
+  int rc = launch_check("reduction");
+  if (rc) return rc;
+  Scal h;
+  rc = hip_check(hipMemcpyAsync(&h, R->scal, sizeof(Scal), hipMemcpyDeviceToHost, R->stream), "reduction copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(R->stream), "reduction sync");
+  if (rc) return rc;
+  const double *src = slot == 0 ? h.force : h.totals;
+  for (int q = 0; q < 3; ++q) out[q] = src[q];
+  if (slot == 0) out[3] = h.t;
+  if (h.health) return fail(DF_ENUMERIC, "non-positive or non-finite density or energy");
+  return DF_OK;
+}
+
+int df_force(df_run *R, double out[4]) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (!out) return fail(DF_EINVAL, "null output");
+  return reduce3(R, 0, out);
+}
+
+int df_totals(df_run *R, double out[3]) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (!out) return fail(DF_EINVAL, "null output");
+  double tmp[4];
+  rc = reduce3(R, 1, tmp);
+  for (int q = 0; q < 3; ++q) out[q] = tmp[q];
+  return rc;
+}
+
+static int field_io(df_run *R, int l, int f, double *hout, const double *hin) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (l < 0 || l >= R->nl || f < DF_RHO || f > DF_VZ) return fail(DF_EINVAL, "bad level or field");
+  const Geo &G = R->geo[l];
+  std::vector<double> full(R->vol[l]);
+  double *dev = field_ptr(R, l, f);
+  rc = hip_check(hipMemcpyAsync(full.data(), dev, full.size() * sizeof(double), hipMemcpyDeviceToHost, R->stream),
+                 "field copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(R->stream), "field copy");
+  if (rc) return rc;
+  int e[3] = {G.n[0], G.n[1], G.n[2]};
+  if (f >= DF_VX) e[f - DF_VX] += 1;
+  size_t a = 0;
+  for (int k = 0; k < e[2]; ++k)
+    for (int j = 0; j < e[1]; ++j)
+      for (int i = 0; i < e[0]; ++i) {
+        size_t c = (size_t)(G.off + i + (long)j * G.sy + (long)k * G.sz);
+        if (hout) hout[a++] = full[c];
+        else full[c] = hin[a++];
+      }
+  if (hin) {
+    rc = hip_check(hipMemcpyAsync(dev, full.data(), full.size() * sizeof(double), hipMemcpyHostToDevice, R->stream),
+                   "field copy");
+    if (rc) return rc;
+    rc = hip_check(hipStreamSynchronize(R->stream), "field copy");
+  }
+  return rc;
+}
+
+int df_get_field(df_run *R, int32_t level, int32_t field, double *host) {
+  if (!host) return fail(DF_EINVAL, "null output");
+  return field_io(R, level, field, host, nullptr);
+}
+
+int df_set_field(df_run *R, int32_t level, int32_t field, const double *host) {
+  if (!host) return fail(DF_EINVAL, "null input");
+  return field_io(R, level, field, nullptr, host);
+}
+
+int df_sync_levels(df_run *R) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  sync_levels(R);
+  rc = launch_check("df_sync_levels");
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(R->stream), "df_sync_levels");
+}
+
+int df_get_dt(df_run *R, double *dt) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (!dt) return fail(DF_EINVAL, "null output");
+  compute_dt(R, 0);
+  rc = launch_check("df_get_dt");
+  if (rc) return rc;
+  Scal h;
+  rc = hip_check(hipMemcpyAsync(&h, R->scal, sizeof(Scal), hipMemcpyDeviceToHost, R->stream), "dt copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(R->stream), "dt copy");
+  *dt = h.dt[0];
+  return rc;
+}
+
+int df_debug_stage(df_run *R, int32_t stage, double dt) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (R->nl != 1) return fail(DF_EINVAL, "stage harness needs a single-level run");
+  if (!std::isfinite(dt)) return fail(DF_EINVAL, "dt must be finite");
+  hipStream_t st = R->stream;
+  rc = hip_check(hipMemcpyAsync(&R->scal->dbg_dt, &dt, sizeof(double), hipMemcpyHostToDevice, st), "dt upload");
+  if (rc) return rc;
+  const double *dtp = &R->scal->dbg_dt;
+  const Geo &G = R->geo[0];
+  LevBufs &B = R->buf[0];
+  const Phys &P = R->phys;
+  int c = R->cur[0];
+  switch (stage) {
+    case 1: dfk::kick(st, G, P, B, c, dtp, 1.0); break;
+    case 2: dfk::compress(st, G, P, B, c, dtp, 1.0); break;
+    case 3: dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, true, false); std::swap(B.etmp, B.q[c][1]); break;
+    case 4: dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, false, true); std::swap(B.etmp, B.q[c][1]); break;
+    case 5:
+      dfk::transport_pass(st, 0, G, P, B, c, dtp, 1.0, nullptr, nullptr);
+      dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, 1.0, nullptr, nullptr);
+      dfk::transport_pass(st, 2, G, P, B, c, dtp, 1.0, nullptr, nullptr);
+      dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.0, false);
+      R->cur[0] = 1 - c;
+      break;
+    case 6:
+      dfk::compress(st, G, P, B, c, dtp, 1.0);
+      dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, true, true);
+      std::swap(B.etmp, B.q[c][1]);
+      break;
+    case 7: level_step(R, 0, dtp, 1.0); break;
+    default: return fail(DF_EINVAL, "unknown stage");
+  }
+  rc = launch_check("df_debug_stage");
+  if (rc) return rc;
+  return hip_check(hipStreamSynchronize(st), "df_debug_stage");
+}
+
+int df_destroy(df_run *R) {
+  if (!R) return fail(DF_EINVAL, "null run handle");
+  delete R;
+  return DF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// dfk.h -- internal interface between the C-ABI runtime (api.hip) and the
+// gfx950 kernels (dfk.hip) of libdfmesh.  Not installed; not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfk {
+
+constexpr int NQ = 8;       // transported set: rho, e, P-x, P+x, P-y, P+y, P-z, P+z
+constexpr int NSTATE = 5;   // rho, e, vx, vy, vz
+constexpr int MAXLEV = 12;
+
+// Array geometry of one level.  Every field of a level is one 3-D array of
+// s[0] x s[1] x s[2] entries, x fastest; entry (i,j,k), i in [-g, n+g), is at
+// off + i + j*sy + k*sz.  A face field stores at (i,j,k) the face on the low
+// side of cell (i,j,k) along its own axis.
+struct Geo {
+  int n[3];
+  int g;
+  int s[3];
+  long sy, sz;
+  long off;
+  double dx;
+  int level;
+  int bc;        // 1: level 0, outer boundary conditions applied on read
+  int has_fine;  // a finer level covers the central half
+};
+
+// Gas and perturber parameters (code units).
+struct Phys {
+  double gamma, gm1;   // adiabatic index, gamma - 1
+  double GM, eps2;     // perturber mass and squared Plummer length
+  double L;            // luminosity
+  double V;            // wind speed (gas enters through x_max at -V)
+  double chi, rho0, e0;
+  double cfl;
+};
+
+// Device-resident scalars of a run (one small array in the arena).
+struct Scal {
+  double dt[MAXLEV];         // step length of each level for the current coarse step
+  unsigned long long smax[MAXLEV];  // max signal speed per level (bits of a positive double)
+  double t;                  // time
+  double dbg_dt;             // step length used by the stage harness
+  double force[3];
+  double totals[3];
+  int health;                // bit 0: a non-positive or non-finite rho or e seen
+  int pad;
+};
+
+// Pointers of one level (FP64 storage).
+struct LevBufs {
+  double *q[2][NQ];   // ping-pong transported sets; q[cur][0], q[cur][1] are rho, e
+  double *v[3];       // face velocities
+  double *etmp;       // diffusion output
+  double *acc;        // frontier transfers of this (fine) level: [dir][side][q][t2][t1]
+  double *hw;         // heat weights on a box of hw_n[0] x hw_n[1] x hw_n[2] cells
+                      // centred on the perturber vertex (x fastest)
+  int hw_n[3];        // box extent (0: no heat table)
+  double *part;       // reduction partials
+};
+
+// ---- launchers (all asynchronous on `st`) ---------------------------------
+void init_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, uint64_t seed,
+                double amp);
+void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+          double fac);
+// face velocities from the transported momenta of q[src], then an optional kick
+void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src,
+                  const double *dtp, double fac, bool do_kick);
+void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+              double fac);
+// writes etmp; the caller swaps etmp and q[cur][1]
+void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur,
+                  const double *dtp, double fac, bool do_diff, bool do_heat);
+// one transport pass q[src] -> q[1-src]; dir 0 builds the momenta from the
+// face velocities; a fine level adds its frontier transfers into B.acc; a
+// level with a finer one (Gf, fine_acc) takes that level's sums on the frontier
+void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src,
+                    const double *dtp, double fac, const Geo *Gf, const double *fine_acc);
+void zero(hipStream_t st, double *p, size_t n);
+void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf,
+            LevBufs &Bf, int curf);
+void commmean(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, const Geo &Gc, LevBufs &Bc,
+              int curc);
+// max signal speed of one level into S->smax[level]; health flag
+void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
+// dt of every level from smax; clears smax; t += dt0 if advance
+void dt_final(hipStream_t st, const Geo *G, int nl, const Phys &P, Scal *S, int advance);
+// force (3 FP64 sums) of one level into B.part, then the fixed-order final sum
+int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
+void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S,
+                 int slot);
+int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
+size_t part_count(const Geo &G);
+
+}  // namespace dfk

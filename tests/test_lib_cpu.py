@@ -1,0 +1,69 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every entry point that include/df.h declares, and validates descriptions."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "df.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(df_\w+)\s*\(", src, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("df_init_mesh", "df_set_perturber", "df_step", "df_force"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1812_03191_amd as dfm
+
+    lib = ctypes.CDLL(dfm.lib_path())
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=33), dict(nlevels=0), dict(nlevels=13), dict(dx0=0.0), dict(gamma=1.0),
+    dict(cfl=0.0), dict(cfl=1.5), dict(precision=7), dict(nlevels=2, nx=18),
+    dict(nlevels=2, nx=12, ny=12, nz=12), dict(nlevels=2, ghost_fine=6), dict(noise_amp=0.7),
+])
+def test_init_mesh_rejects_bad_descriptions(bad):
+    import paper_1812_03191_amd as dfm
+
+    kw = dict(nx=16, ny=16, nz=16, nlevels=1, dx0=0.1)
+    kw.update(bad)
+    with pytest.raises(dfm.DFError) as ei:
+        dfm.init_mesh(**kw)
+    assert ei.value.code == -1
+
+
+def test_required_bytes_scales_with_mesh():
+    import paper_1812_03191_amd as dfm
+
+    a = dfm.init_mesh(32, 32, 32, 1, 0.1)
+    b = dfm.init_mesh(64, 64, 64, 1, 0.1)
+    c = dfm.init_mesh(64, 64, 64, 3, 0.1)
+    na, nb, nc = (dfm.required_bytes(h) for h in (a, b, c))
+    assert 8 * 20 * 38 ** 3 <= na < 2 * 8 * 20 * 38 ** 3
+    assert nb > 6 * na
+    assert nc > 3 * nb
+    for h in (a, b, c):
+        dfm.destroy(h)
+
+
+def test_calls_out_of_order_fail_cleanly():
+    import paper_1812_03191_amd as dfm
+
+    h = dfm.init_mesh(16, 16, 16, 1, 0.1)
+    with pytest.raises(dfm.DFError) as ei:
+        dfm.step(h, 1)
+    assert ei.value.code == -2
+    with pytest.raises(dfm.DFError):
+        dfm.set_perturber(h, 0.01, 0.0, 0.0, 0.5, 0.1)
+    dfm.destroy(h)
