@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the nested-mesh dynamical-friction update on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): one level of
+128^3 cells in FP64, gamma 5/3, Mach 1.5, GM 0.01, chi 0.1, a luminous
+perturber (L 1e-3) whose heat is released with Gaussian weights of width two
+cells, seeded 1e-6 density noise.  A step is one coarse step of the whole
+update: time step, kick, compression + diffusion + heat release, three
+transport passes, rebuild + kick, force reduction into the force log.
+
+Prints one JSON line: cell-updates/s (active cells x steps / wall time of the
+timed steps, inputs resident in HBM), the roofline of the dominant kernel
+(algorithmic bytes per launch / its average duration measured with HIP events
+on the run's stream) and the FP64 CPU oracle timed on a bounded sample of the
+same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("cell-updates/s + % HBM roofline (FP64 plain vs FP32 batched); "
+          "p50/p99 job latency")
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per active cell of one launch of each kernel kind (FP64):
+# the fields the kernel must read and write once each.
+ALG_BYTES = {
+    "kick": 8 * (5 + 3),          # read rho, e, vx, vy, vz; write vx, vy, vz
+    "compress": 8 * (4 + 1),      # read e, vx, vy, vz; write e
+    "diffuse_heat": 8 * (2 + 1),  # read rho, e; write e
+    "pass_x": 8 * (5 + 8),        # read rho, e, vx, vy, vz; write the 8 transported
+    "pass_y": 8 * (9 + 8),        # read 8 transported + vy; write 8
+    "pass_z": 8 * (9 + 8),        # read 8 transported + vz; write 8
+    "rebuild_kick": 8 * (8 + 3),  # read 8 transported; write vx, vy, vz
+    "dt": 8 * 5,                  # read rho, e, vx, vy, vz
+    "force": 8 * 1,               # read rho
+}
+
+
+def workload():
+    from tests import inputs
+
+    cfg, steps = inputs.config2()
+    return cfg, steps
+
+
+def dfk_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dfk.hip", "dfk.h"):
+        with open(os.path.join(ROOT, "paper_1812_03191_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_config2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != dfk_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    os.environ["OMP_NUM_THREADS"] = str(nthreads)
+    from oracle.oracle import Oracle
+
+    o = Oracle(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
+               gamma=cfg["gamma"], cfl=cfg["cfl"], seed=cfg["seed"], noise_amp=cfg["noise_amp"],
+               GM=cfg["GM"], eps=cfg["eps"], L=cfg["L"], mach=cfg["mach"], chi=cfg["chi"])
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    n = max(2, min(60, int(budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    o.step(n)
+    el = time.perf_counter() - t0
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    return {"value": cells * n / el, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"128^3 single level FP64, {n} coarse steps after one untimed step "
+                      f"({el:.1f} s, OpenMP threads={nthreads})"}
+
+
+def copy_probe(nbytes=1 << 30):
+    """a plain device copy of known size, for scaling the byte counters"""
+    import torch
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": nbytes, "launches": 3}), file=sys.stderr)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(each run is independent; see DESIGN.md for how the update would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1812_03191_amd as dfm
+
+    cfg, default_steps = workload()
+    K = args.steps if args.steps is not None else default_steps
+    W = args.warmup
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+
+    run = dfm.Run(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
+                  gamma=cfg["gamma"], cfl=cfg["cfl"], seed=cfg["seed"], noise_amp=cfg["noise_amp"])
+    run.set_perturber(cfg["GM"], cfg["eps"], cfg["L"], cfg["mach"], cfg["chi"])
+    stream = run.stream
+    print(f"[bench] 128^3 FP64: warmup {W}, timed {K}", file=sys.stderr, flush=True)
+    run.step(W)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    run.step(K)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    value = cells * K / (ms / 1e3)
+    F = run.force()
+    print(f"[bench] {ms / K:.4f} ms/step, {value:.4e} cell-updates/s", file=sys.stderr, flush=True)
+
+    roof = None
+    kern = {}
+    if not args.no_kernel_timing:
+        # the same K steps again, with HIP events around every launch on the run's stream
+        launches = 16 * K
+        dfm.timing_enable(run.handle, launches)
+        run.step(K)
+        kern = dfm.timing_read(run.handle)
+        dfm.timing_enable(run.handle, 0)
+        busy = {k: v for k, v in kern.items() if v[1] > 0 and k in ALG_BYTES}
+        dom = max(busy, key=lambda k: busy[k][0])
+        avg_ms = busy[dom][0] / busy[dom][1]
+        per_launch = ALG_BYTES[dom] * cells
+        achieved = per_launch / (avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profiles(dom), "avg_launch_us": round(avg_ms * 1e3, 2),
+                "alg_bytes_per_launch": per_launch}
+        kern = {k: {"ms_total": round(v[0], 3), "launches": v[1],
+                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None} for k, v in kern.items()
+                if v[1]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": ms / K, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "128^3 single level FP64, Mach 1.5, GM 0.01, chi 0.1, L 1e-3, "
+                               "Gaussian heat width 2 cells, seed 2 (500-step run)",
+                   "cells": cells, "precision": "fp64"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "force": {"Fx": F[0], "Fy": F[1], "Fz": F[2], "t": F[3]},
+        "kernels": kern,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -112,6 +112,12 @@ int df_step(df_run *run, int32_t n);
  * found a non-positive or non-finite density or energy. */
 int df_force(df_run *run, double out[4]);
 
+/* The force log: df_step appends (Fx, Fy, Fz, t) after every coarse step to a
+ * device ring of 4096 entries (the force time series monitored in Sect. 3.4).
+ * Copies the last min(steps, 4096, cap) entries, oldest first, to out (4
+ * doubles each) and their number to *count.  Synchronises. */
+int df_force_log(df_run *run, double *out, int32_t cap, int32_t *count);
+
 /* Composite totals over uncovered active cells (FP64): out[0] mass,
  * out[1] internal energy, out[2] kinetic energy.  Synchronises. */
 int df_totals(df_run *run, double out[3]);
@@ -135,6 +141,19 @@ int df_get_dt(df_run *run, double *dt);
  *  4 heat release, 5 transport, 6 stages 2-4, 7 a whole level step.
  * Used by the parity tests.  DF_EINVAL for other stages or nested runs. */
 int df_debug_stage(df_run *run, int32_t stage, double dt);
+
+/* Kernel timing for measurement (off by default).  df_timing_enable(run, n)
+ * creates 2n HIP events and from then on records an event pair on the bound
+ * stream around each of the next n kernel launches of df_step (0 disables and
+ * frees them).  df_timing_read(run, ms, count, nkinds) synchronises, adds the
+ * elapsed times by kernel kind into ms[kind] and the launch numbers into
+ * count[kind] (kinds DF_K_*), and restarts the recording. */
+enum {
+  DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
+  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_NKINDS
+};
+int df_timing_enable(df_run *run, int32_t max_launches);
+int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);
 
 /* Release the handle (not the caller's arena or stream). */
 int df_destroy(df_run *run);

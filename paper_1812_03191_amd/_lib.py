@@ -65,6 +65,9 @@ def _load():
         "df_get_dt": [vp, dp],
         "df_debug_stage": [vp, i32, ctypes.c_double],
         "df_destroy": [vp],
+        "df_force_log": [vp, dp, i32, ctypes.POINTER(i32)],
+        "df_timing_enable": [vp, i32],
+        "df_timing_read": [vp, dp, ctypes.POINTER(i32), i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -154,6 +157,29 @@ def destroy(h) -> None:
     _ck(_load().df_destroy(h))
 
 
+def force_log(h, cap: int = 4096) -> np.ndarray:
+    out = np.zeros((cap, 4))
+    n = ctypes.c_int32()
+    _ck(_load().df_force_log(h, _dp(out), cap, ctypes.byref(n)))
+    return out[: n.value].copy()
+
+
+KERNEL_KINDS = ("kick", "compress", "diffuse_heat", "pass_x", "pass_y", "pass_z", "rebuild_kick",
+                "commup", "commmean", "dt", "force", "zero")
+
+
+def timing_enable(h, max_launches: int) -> None:
+    _ck(_load().df_timing_enable(h, int(max_launches)))
+
+
+def timing_read(h) -> dict:
+    nk = len(KERNEL_KINDS)
+    ms = np.zeros(nk)
+    cnt = (ctypes.c_int32 * nk)()
+    _ck(_load().df_timing_read(h, _dp(ms), cnt, nk))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
 # ------------------------------------------------------------------ Run
 
 class Run:
@@ -202,6 +228,9 @@ class Run:
 
     def dt(self):
         return get_dt(self._h)
+
+    def force_log(self, cap=4096):
+        return force_log(self._h, cap)
 
     def sync_levels(self):
         sync_levels(self._h)

@@ -60,9 +60,15 @@ struct df_run {
   size_t bytes = 0;
   hipStream_t stream = nullptr;
   Scal *scal = nullptr;
+  double *flog = nullptr;
   bool bound = false;
   bool ready = false;
   double eps = 0.0;
+  // optional per-kernel-kind timing: event pairs around launches
+  bool timing = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> ev_kind;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -82,6 +88,7 @@ struct Carver {
 void carve(df_run *R, char *base) {
   Carver c{base};
   R->scal = c.take<Scal>(1);
+  R->flog = c.take<double>(4 * (size_t)dfk::FLOG);
   for (int l = 0; l < R->nl; ++l) {
     LevBufs &B = R->buf[l];
     size_t v = R->vol[l];
@@ -127,6 +134,28 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
   for (double &x : w) x /= sum;
 }
 
+// ---------------------------------------------------------------- timing
+// Kernel kinds timed by df_timing_read (the order of the DF_K_* list in df.h).
+enum { K_KICK = 0, K_COMPRESS, K_DIFFUSE, K_PASSX, K_PASSY, K_PASSZ, K_REBUILD, K_COMMUP, K_COMMMEAN,
+       K_DT, K_FORCE, K_ZERO, K_NKINDS };
+
+struct TScope {
+  df_run *R;
+  bool on;
+  TScope(df_run *r, int kind) : R(r), on(r->timing && r->ev_used + 1 < r->ev.size()) {
+    if (on) {
+      R->ev_kind[R->ev_used / 2] = kind;
+      hipEventRecord(R->ev[R->ev_used], R->stream);
+    }
+  }
+  ~TScope() {
+    if (on) {
+      hipEventRecord(R->ev[R->ev_used + 1], R->stream);
+      R->ev_used += 2;
+    }
+  }
+};
+
 // ------------------------------------------------------------- scheduler
 void level_step(df_run *R, int l, const double *dtp, double scale) {
   hipStream_t st = R->stream;
@@ -136,35 +165,51 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   int c = R->cur[l];
   const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
   const double *facc = Gf ? R->buf[l + 1].acc : nullptr;
-  dfk::kick(st, G, P, B, c, dtp, 0.5 * scale);
-  dfk::compress(st, G, P, B, c, dtp, scale);
-  dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true);
+  { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale); }
+  { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale); }
+  { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
   std::swap(B.etmp, B.q[c][1]);
-  dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc);
-  dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc);
-  dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc);
-  dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true);
+  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc); }
+  { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc); }
+  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc); }
+  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true); }
   R->cur[l] = 1 - c;
 }
 
 void cycle(df_run *R, int l) {
   if (l + 1 < R->nl) {
-    dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1]);
+    { TScope t(R, K_ZERO); dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1]); }
     cycle(R, l + 1);
     cycle(R, l + 1);
   }
   level_step(R, l, &R->scal->dt[l], 1.0);
   if (l + 1 < R->nl) {
-    dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
-                R->cur[l + 1]);
-    dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
-                  R->cur[l]);
+    { TScope t(R, K_COMMUP);
+      dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
+                  R->cur[l + 1]); }
+    { TScope t(R, K_COMMMEAN);
+      dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
+                    R->cur[l]); }
   }
 }
 
 void compute_dt(df_run *R, int advance) {
+  TScope t(R, K_DT);
   for (int l = 0; l < R->nl; ++l) dfk::signal_speed(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->scal);
-  dfk::dt_final(R->stream, R->geo, R->nl, R->phys, R->scal, advance);
+  dfk::dt_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, advance);
+}
+
+// force of the current state (eq. 18); slot 2 also appends it to the log
+void force_reduce(df_run *R, int slot) {
+  TScope t(R, K_FORCE);
+  double *parts[MAXLEV];
+  int np[MAXLEV];
+  for (int l = 0; l < R->nl; ++l) {
+    np[l] = slot == 1 ? dfk::totals_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l])
+                      : dfk::force_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l]);
+    parts[l] = R->buf[l].part;
+  }
+  dfk::force_final(R->stream, parts, np, R->nl, R->scal, slot, R->flog);
 }
 
 void sync_levels(df_run *R) {
@@ -345,19 +390,13 @@ int df_step(df_run *R, int32_t n) {
   for (int s = 0; s < n; ++s) {
     compute_dt(R, 1);
     cycle(R, 0);
+    force_reduce(R, 2);
   }
   return launch_check("df_step");
 }
 
-static int reduce3(df_run *R, int slot, double out[3]) {
-  double *parts[MAXLEV];
-  int np[MAXLEV];
-  for (int l = 0; l < R->nl; ++l) {
-    np[l] = slot == 0 ? dfk::force_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l])
-                      : dfk::totals_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l]);
-    parts[l] = R->buf[l].part;
-  }
-  dfk::force_final(R->stream, parts, np, R->nl, R->scal, slot);
+static int reduce3(df_run *R, int slot, double out[4]) {
+  force_reduce(R, slot);
   int rc = launch_check("reduction");
   if (rc) return rc;
   Scal h;
@@ -492,8 +531,78 @@ int df_debug_stage(df_run *R, int32_t stage, double dt) {
   return hip_check(hipStreamSynchronize(st), "df_debug_stage");
 }
 
+int df_force_log(df_run *R, double *out, int32_t cap, int32_t *count) {
+  int rc = check_run(R, true);
+  if (rc) return rc;
+  if (!out || !count || cap < 0) return fail(DF_EINVAL, "bad output");
+  Scal h;
+  rc = hip_check(hipMemcpyAsync(&h, R->scal, sizeof(Scal), hipMemcpyDeviceToHost, R->stream), "log copy");
+  if (rc) return rc;
+  std::vector<double> ring(4 * (size_t)dfk::FLOG);
+  rc = hip_check(hipMemcpyAsync(ring.data(), R->flog, ring.size() * sizeof(double), hipMemcpyDeviceToHost, R->stream),
+                 "log copy");
+  if (rc) return rc;
+  rc = hip_check(hipStreamSynchronize(R->stream), "log copy");
+  if (rc) return rc;
+  unsigned int n = h.nlog;
+  unsigned int avail = n < (unsigned)dfk::FLOG ? n : (unsigned)dfk::FLOG;
+  unsigned int take = avail < (unsigned)cap ? avail : (unsigned)cap;
+  for (unsigned int e = 0; e < take; ++e) {
+    unsigned int idx = (n - take + e) % dfk::FLOG;
+    for (int q = 0; q < 4; ++q) out[4 * e + q] = ring[4 * (size_t)idx + q];
+  }
+  *count = (int32_t)take;
+  return DF_OK;
+}
+
+int df_timing_enable(df_run *R, int32_t max_launches) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (max_launches < 0 || max_launches > (1 << 20)) return fail(DF_EINVAL, "max_launches out of range");
+  rc = hip_check(hipStreamSynchronize(R->stream), "timing");
+  if (rc) return rc;
+  for (hipEvent_t e : R->ev) hipEventDestroy(e);
+  R->ev.clear();
+  R->ev_kind.clear();
+  R->ev_used = 0;
+  R->timing = max_launches > 0;
+  if (!R->timing) return DF_OK;
+  R->ev.resize(2 * (size_t)max_launches);
+  R->ev_kind.resize((size_t)max_launches);
+  for (auto &e : R->ev) {
+    rc = hip_check(hipEventCreate(&e), "event create");
+    if (rc) return rc;
+  }
+  return DF_OK;
+}
+
+int df_timing_read(df_run *R, double *ms, int32_t *count, int32_t nkinds) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (!ms || !count || nkinds < 1) return fail(DF_EINVAL, "bad output");
+  for (int k = 0; k < nkinds; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  rc = hip_check(hipStreamSynchronize(R->stream), "timing");
+  if (rc) return rc;
+  for (size_t p = 0; p + 1 < R->ev_used; p += 2) {
+    float t = 0.0f;
+    rc = hip_check(hipEventElapsedTime(&t, R->ev[p], R->ev[p + 1]), "event time");
+    if (rc) return rc;
+    int kind = R->ev_kind[p / 2];
+    if (kind < nkinds) {
+      ms[kind] += t;
+      count[kind] += 1;
+    }
+  }
+  R->ev_used = 0;
+  return DF_OK;
+}
+
 int df_destroy(df_run *R) {
   if (!R) return fail(DF_EINVAL, "null run handle");
+  for (hipEvent_t e : R->ev) hipEventDestroy(e);
   delete R;
   return DF_OK;
 }

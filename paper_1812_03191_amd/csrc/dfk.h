@@ -39,14 +39,15 @@ struct Phys {
 // Device-resident scalars of a run (one small array in the arena).
 struct Scal {
   double dt[MAXLEV];         // step length of each level for the current coarse step
-  unsigned long long smax[MAXLEV];  // max signal speed per level (bits of a positive double)
   double t;                  // time
   double dbg_dt;             // step length used by the stage harness
   double force[3];
   double totals[3];
   int health;                // bit 0: a non-positive or non-finite rho or e seen
-  int pad;
+  unsigned int nlog;         // force-log entries written so far
 };
+
+constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
 
 // Pointers of one level (FP64 storage).
 struct LevBufs {
@@ -83,14 +84,16 @@ void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc,
             LevBufs &Bf, int curf);
 void commmean(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, const Geo &Gc, LevBufs &Bc,
               int curc);
-// max signal speed of one level into S->smax[level]; health flag
+// per-block maxima of the signal speed of one level into B.part; health flag
 void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
-// dt of every level from smax; clears smax; t += dt0 if advance
-void dt_final(hipStream_t st, const Geo *G, int nl, const Phys &P, Scal *S, int advance);
+// dt of every level from the per-block maxima; t += dt0 if advance
+void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S,
+              int advance);
 // force (3 FP64 sums) of one level into B.part, then the fixed-order final sum
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
+// slot 0: S->force; slot 1: S->totals; slot 2: S->force and the force log
 void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S,
-                 int slot);
+                 int slot, double *flog);
 int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
 size_t part_count(const Geo &G);
 

@@ -301,42 +301,37 @@ struct PassArgs {
   int fn[3];              // finer level's active cells (for accumulator strides)
 };
 
-// quantity m of the cell at offset o along DIR from (i,j,k)
-template <int DIR, bool BC, bool FIRST>
-__device__ __forceinline__ void load_cell(const Geo &G, const Phys &P, const PassArgs &A, int i, int j,
-                                          int k, int o, double q[NQ]) {
+// Offsets of the cell at o along DIR from (i,j,k) for level 0, with the
+// boundary conditions: returns false for an inflow ghost (beyond x_max).
+template <int DIR, bool BC>
+__device__ __forceinline__ bool cell_at(const Geo &G, int i, int j, int k, int o, long &c) {
   int ii = i + (DIR == 0 ? o : 0), jj = j + (DIR == 1 ? o : 0), kk = k + (DIR == 2 ? o : 0);
   if (BC) {
-    if (ii >= G.n[0]) {
-#pragma unroll
-      for (int m = 0; m < NQ; ++m) q[m] = q_inflow(P, m);
-      return;
-    }
+    if (ii >= G.n[0]) return false;
     ii = ii < 0 ? 0 : ii;
     jj = clampi(jj, 0, G.n[1] - 1);
     kk = clampi(kk, 0, G.n[2] - 1);
   }
-  long c = lin(G, ii, jj, kk);
-  if (FIRST) {
-    double r = A.qi[0][c];
-    q[0] = r;
-    q[1] = A.qi[1][c];
-    q[2] = r * A.v[0][c];
-    q[3] = r * A.v[0][c + 1];
-    q[4] = r * A.v[1][c];
-    q[5] = r * A.v[1][c + G.sy];
-    q[6] = r * A.v[2][c];
-    q[7] = r * A.v[2][c + G.sz];
-  } else {
-#pragma unroll
-    for (int m = 0; m < NQ; ++m) q[m] = A.qi[m][c];
-  }
+  c = lin(G, ii, jj, kk);
+  return true;
+}
+
+// upwind van Leer face value from the specific values s[0..3] of the cells
+// -2..+1 around the face (offsets relative to the face's high-side cell)
+__device__ __forceinline__ double face_value(double sm2, double sm1, double s0, double sp1, double a,
+                                             double nu) {
+  if (a > 0.0) return sm1 + 0.5 * vleer(s0 - sm1, sm1 - sm2) * (1.0 - nu);
+  return s0 - 0.5 * vleer(sp1 - s0, s0 - sm1) * (1.0 + nu);
 }
 
 // One dimensional pass of the van Leer upwind transport along DIR for the cell
 // (i,j,k): transfers through its two faces, M = face(rho) a dt dx^2 and
 // face(q/rho) M, then q -= (right - left) / dx^3.  The face values use the
 // limited differences of the upwind cell and the Courant number a dt / dx.
+// The quantities are processed one at a time so that only the densities, their
+// reciprocals and the two mass transfers stay live across the loop.  In the
+// first (x) pass the momenta are built from the face velocities, whose values
+// are the momenta's specific values.
 template <int DIR, bool BC, bool FIRST>
 __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs A) {
   int i, j, k;
@@ -345,103 +340,94 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs A) {
   const double dx = G.dx;
   const double mfac = dt * dx * dx;
   const double ivol = 1.0 / (dx * dx * dx);
-  double s[5][NQ];   // rho and specific values q/rho at offsets -2..2
-  double q0[NQ];     // the cell's own values
+  long cc[5];
+  bool in[5];
 #pragma unroll
-  for (int o = -2; o <= 2; ++o) {
-    double q[NQ];
-    load_cell<DIR, BC, FIRST>(G, P, A, i, j, k, o, q);
-    double ir = 1.0 / q[0];
-    s[o + 2][0] = q[0];
+  for (int o = 0; o < 5; ++o) in[o] = cell_at<DIR, BC>(G, i, j, k, o - 2, cc[o]);
+  double r[5], ir[5];
 #pragma unroll
-    for (int m = 1; m < NQ; ++m) s[o + 2][m] = q[m] * ir;
-    if (o == 0) {
-#pragma unroll
-      for (int m = 0; m < NQ; ++m) q0[m] = q[m];
-    }
+  for (int o = 0; o < 5; ++o) {
+    r[o] = in[o] ? A.qi[0][cc[o]] : P.rho0;
+    ir[o] = 1.0 / r[o];
   }
-  // limited differences of cells -1, 0, +1
-  double ds[3][NQ];
-#pragma unroll
-  for (int o = 1; o <= 3; ++o)
-#pragma unroll
-    for (int m = 0; m < NQ; ++m) ds[o - 1][m] = vleer(s[o + 1][m] - s[o][m], s[o][m] - s[o - 1][m]);
-  long c = lin(G, i, j, k);
-  long st = dstride(G, DIR);
+  const long c = lin(G, i, j, k);
+  const long st = dstride(G, DIR);
   const double aL = A.v[DIR][c], aR = A.v[DIR][c + st];
-  double FL[NQ], FR[NQ];
-  {
-    // left face: between offsets -1 (index 1) and 0 (index 2)
-    double nu = aL * dt / dx;
-    double face[NQ];
-#pragma unroll
-    for (int m = 0; m < NQ; ++m)
-      face[m] = (aL > 0.0) ? s[1][m] + 0.5 * ds[0][m] * (1.0 - nu) : s[2][m] - 0.5 * ds[1][m] * (1.0 + nu);
-    double M = face[0] * aL * mfac;
-    FL[0] = M;
-#pragma unroll
-    for (int m = 1; m < NQ; ++m) FL[m] = face[m] * M;
-  }
-  {
-    double nu = aR * dt / dx;
-    double face[NQ];
-#pragma unroll
-    for (int m = 0; m < NQ; ++m)
-      face[m] = (aR > 0.0) ? s[2][m] + 0.5 * ds[1][m] * (1.0 - nu) : s[3][m] - 0.5 * ds[2][m] * (1.0 + nu);
-    double M = face[0] * aR * mfac;
-    FR[0] = M;
-#pragma unroll
-    for (int m = 1; m < NQ; ++m) FR[m] = face[m] * M;
-  }
+  const double nuL = aL * dt / dx, nuR = aR * dt / dx;
+  const double ML = face_value(r[0], r[1], r[2], r[3], aL, nuL) * aL * mfac;
+  const double MR = face_value(r[1], r[2], r[3], r[4], aR, nuR) * aR * mfac;
+
   const int id[3] = {i, j, k};
   constexpr int T1 = (DIR == 0) ? 1 : 0;
   constexpr int T2 = (DIR == 2) ? 1 : 2;
   const int cd = id[DIR];
   // flux matching on the frontier of the finer level: the sum of its 4 faces
   // over its 2 sub-cycles replaces this level's transfers there
+  int side_L = -1, side_R = -1;
+  long fbase = 0;
+  long fnt = 0;
   if (A.facc) {
     int o1 = G.n[T1] / 4, o2 = G.n[T2] / 4;
     int t1 = id[T1] - o1, t2 = id[T2] - o2;
     if (t1 >= 0 && t2 >= 0 && t1 < G.n[T1] / 2 && t2 < G.n[T2] / 2) {
       int lo = G.n[DIR] / 4, hi = (3 * G.n[DIR]) / 4;
-      long nt = (long)A.fn[T1] * A.fn[T2];
-      long f1 = 2 * t1, f2 = 2 * t2;
-      auto fine_sum = [&](int side, int m) {
-        const double *a = A.facc + ((long)(DIR * 2 + side) * NQ + m) * nt;
-        double s00 = a[f2 * A.fn[T1] + f1], s10 = a[f2 * A.fn[T1] + f1 + 1];
-        double s01 = a[(f2 + 1) * A.fn[T1] + f1], s11 = a[(f2 + 1) * A.fn[T1] + f1 + 1];
-        return (s00 + s10) + (s01 + s11);
-      };
-      if (cd == lo || cd == hi) {
-        int side = (cd == hi);
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) FL[m] = fine_sum(side, m);
-      }
-      if (cd + 1 == lo || cd + 1 == hi) {
-        int side = (cd + 1 == hi);
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) FR[m] = fine_sum(side, m);
-      }
+      if (cd == lo || cd == hi) side_L = (cd == hi);
+      if (cd + 1 == lo || cd + 1 == hi) side_R = (cd + 1 == hi);
+      fnt = (long)A.fn[T1] * A.fn[T2];
+      fbase = (long)(2 * t2) * A.fn[T1] + 2 * t1;
     }
   }
-  // accumulate this (fine) level's transfers through its own frontier
+  auto fine_sum = [&](int side, int m) {
+    const double *a = A.facc + ((long)(DIR * 2 + side) * NQ + m) * fnt + fbase;
+    return (a[0] + a[1]) + (a[A.fn[T1]] + a[A.fn[T1] + 1]);
+  };
+  // this (fine) level's own frontier: accumulate its transfers there
+  long acc_i = -1;
+  int acc_side = -1;
+  long acc_nt = 0;
   if (A.acc) {
     int t1 = id[T1], t2 = id[T2];
-    if (t1 >= 0 && t2 >= 0 && t1 < G.n[T1] && t2 < G.n[T2]) {
-      long nt = (long)G.n[T1] * G.n[T2];
-      long ti = (long)t2 * G.n[T1] + t1;
-      if (cd == 0) {
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) A.acc[((long)(DIR * 2 + 0) * NQ + m) * nt + ti] += FL[m];
-      }
-      if (cd == G.n[DIR] - 1) {
-#pragma unroll
-        for (int m = 0; m < NQ; ++m) A.acc[((long)(DIR * 2 + 1) * NQ + m) * nt + ti] += FR[m];
-      }
+    if (t1 >= 0 && t2 >= 0 && t1 < G.n[T1] && t2 < G.n[T2] && (cd == 0 || cd == G.n[DIR] - 1)) {
+      acc_nt = (long)G.n[T1] * G.n[T2];
+      acc_i = (long)t2 * G.n[T1] + t1;
+      acc_side = (cd == 0) ? 0 : 1;
     }
   }
+  auto finish = [&](int m, double own, double FL, double FR) {
+    if (side_L >= 0) FL = fine_sum(side_L, m);
+    if (side_R >= 0) FR = fine_sum(side_R, m);
+    if (acc_side == 0) A.acc[((long)(DIR * 2 + 0) * NQ + m) * acc_nt + acc_i] += FL;
+    if (acc_side == 1) A.acc[((long)(DIR * 2 + 1) * NQ + m) * acc_nt + acc_i] += FR;
+    A.qo[m][c] = own - (FR - FL) * ivol;
+  };
+  finish(0, r[2], ML, MR);
+
+#pragma unroll 1
+  for (int m = 1; m < NQ; ++m) {
+    double sv[5];
+    double own;
+    if (FIRST && m >= 2) {
+      // momentum P = rho v of a face velocity: its specific value is v itself
+      const int d = (m - 2) >> 1;
+      const bool hi = (m & 1);
+      const double *vd = A.v[d];
+      const long off = hi ? dstride(G, d) : 0;
 #pragma unroll
-  for (int m = 0; m < NQ; ++m) A.qo[m][c] = q0[m] - (FR[m] - FL[m]) * ivol;
+      for (int o = 0; o < 5; ++o) sv[o] = in[o] ? vd[cc[o] + off] : (d == 0 ? -P.V : 0.0);
+      own = r[2] * sv[2];
+    } else {
+      const double *q = A.qi[m];
+      double qv[5];
+#pragma unroll
+      for (int o = 0; o < 5; ++o) qv[o] = in[o] ? q[cc[o]] : q_inflow(P, m);
+#pragma unroll
+      for (int o = 0; o < 5; ++o) sv[o] = qv[o] * ir[o];
+      own = qv[2];
+    }
+    double FL = face_value(sv[0], sv[1], sv[2], sv[3], aL, nuL) * ML;
+    double FR = face_value(sv[1], sv[2], sv[3], sv[4], aR, nuR) * MR;
+    finish(m, own, FL, FR);
+  }
 }
 
 // ------------------------------------------------------------ CommUp
@@ -632,7 +618,9 @@ struct FinalArgs {
   const double *part[MAXLEV];
   int npart[MAXLEV];
   int nl;
-  double *out;  // 3 doubles
+  double *out;   // 3 doubles
+  Scal *S;       // with flog: append (out, t) to the ring
+  double *flog;
 };
 
 __global__ void __launch_bounds__(256) k_final3(FinalArgs A) {
@@ -650,8 +638,16 @@ __global__ void __launch_bounds__(256) k_final3(FinalArgs A) {
   if (threadIdx.x % 64 == 0)
     for (int q = 0; q < 3; ++q) sh[q][w] = s[q];
   __syncthreads();
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     for (int q = 0; q < 3; ++q) A.out[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    if (A.flog) {
+      unsigned int n = A.S->nlog;
+      double *e = A.flog + 4 * (size_t)(n % FLOG);
+      for (int q = 0; q < 3; ++q) e[q] = A.out[q];
+      e[3] = A.S->t;
+      A.S->nlog = n + 1;
+    }
+  }
 }
 
 // Largest signal speed c_s + |v| over the active cells and their faces, and
@@ -677,30 +673,49 @@ __global__ void __launch_bounds__(BX * BY) k_signal(Geo G, Phys P, RedArgs A) {
   }
   sig = wave_max(bad ? 0.0 : sig);
   bool anybad = __any(bad);
+  __shared__ double sh[BX * BY / 64];
   int t = threadIdx.y * BX + threadIdx.x;
   if ((t % 64) == 0) {
-    atomicMax(&A.S->smax[G.level], (unsigned long long)__double_as_longlong(sig));
+    sh[t / 64] = sig;
     if (anybad) atomicOr(&A.S->health, 1);
+  }
+  __syncthreads();
+  if (t == 0) {
+    double m = sh[0];
+    for (int q = 1; q < BX * BY / 64; ++q) m = fmax(m, sh[q]);
+    long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    A.part[blk] = m;  // per-block maximum; reduced by k_dt_final
   }
 }
 
 struct DtArgs {
   double dx[MAXLEV];
+  const double *part[MAXLEV];  // per-block maximum signal speeds of each level
+  int npart[MAXLEV];
   int nl;
   int advance;
 };
 
 // coarse step cfl * min_l 2^l min(dx_l / smax_l, dx_l^2 / (6 chi)) (eq. 55, xi = 2)
-__global__ void k_dt_final(Phys P, DtArgs A, Scal *S) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(256) k_dt_final(Phys P, DtArgs A, Scal *S) {
+  __shared__ double sh[4];
+  __shared__ double smax[MAXLEV];
+  for (int l = 0; l < A.nl; ++l) {
+    double m = 0.0;
+    for (int b = threadIdx.x; b < A.npart[l]; b += 256) m = fmax(m, A.part[l][b]);
+    m = wave_max(m);
+    if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) smax[l] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   double best = INFINITY;
   for (int l = 0; l < A.nl; ++l) {
-    double smax = __longlong_as_double((long long)S->smax[l]);
-    double dtl = A.dx[l] / smax;
+    double dtl = A.dx[l] / smax[l];
     if (P.chi > 0.0) dtl = fmin(dtl, A.dx[l] * A.dx[l] / (6.0 * P.chi));
     dtl = ldexp(dtl, l);
     best = fmin(best, dtl);
-    S->smax[l] = 0ULL;
   }
   double dt0 = P.cfl * best;
   for (int l = 0; l < A.nl; ++l) S->dt[l] = ldexp(dt0, -l);
@@ -957,12 +972,16 @@ void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
   DFK_LAUNCH(k_signal, grid_of(A.b), dim3(BX, BY), st, G, P, A);
 }
 
-void dt_final(hipStream_t st, const Geo *G, int nl, const Phys &P, Scal *S, int advance) {
+void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S, int advance) {
   DtArgs A;
-  for (int l = 0; l < MAXLEV; ++l) A.dx[l] = l < nl ? G[l].dx : 0.0;
+  for (int l = 0; l < MAXLEV; ++l) {
+    A.dx[l] = l < nl ? G[l].dx : 0.0;
+    A.part[l] = l < nl ? B[l].part : nullptr;
+    A.npart[l] = l < nl ? (int)part_count(G[l]) : 0;
+  }
   A.nl = nl;
   A.advance = advance;
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(64), 0, st, P, A, S);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, P, A, S);
 }
 
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {
@@ -977,14 +996,17 @@ int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int
   return (int)part_count(G);
 }
 
-void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S, int slot) {
+void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S, int slot,
+                 double *flog) {
   FinalArgs A;
   for (int l = 0; l < MAXLEV; ++l) {
     A.part[l] = l < nl ? parts[l] : nullptr;
     A.npart[l] = l < nl ? nparts[l] : 0;
   }
   A.nl = nl;
-  A.out = slot == 0 ? S->force : S->totals;
+  A.out = slot == 1 ? S->totals : S->force;
+  A.S = S;
+  A.flog = slot == 2 ? flog : nullptr;
   hipLaunchKernelGGL(k_final3, dim3(1), dim3(256), 0, st, A);
 }
 
