@@ -282,16 +282,18 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
     for (int k = 0; k < 3; ++k) G.n[k] = n[k];
-    G.g = (l == 0) ? 3 : gf;
-    for (int k = 0; k < 3; ++k) G.s[k] = G.n[k] + 2 * G.g;
-    G.sy = G.s[0];
-    G.sz = (long)G.s[0] * G.s[1];
-    G.off = G.g + G.g * G.sy + G.g * G.sz;
+    G.g = (l == 0) ? 0 : gf;
+    for (int k = 0; k < 3; ++k) G.s[k] = (l == 0) ? G.n[k] + 1 : G.n[k] + 2 * G.g;
+    // x = 0 of each row on a 128-byte boundary (16 doubles)
+    const int px = (G.g + 15) / 16 * 16;
+    G.sy = (px + G.s[0] - G.g + 15) / 16 * 16;
+    G.sz = G.sy * G.s[1];
+    G.off = px + G.g * G.sy + G.g * G.sz;
     G.dx = std::ldexp(d->dx0, -l);
     G.level = l;
     G.bc = (l == 0);
     G.has_fine = (l + 1 < R->nl);
-    R->vol[l] = (size_t)G.s[0] * G.s[1] * G.s[2];
+    R->vol[l] = (size_t)G.sz * G.s[2];
     size_t face_max = (size_t)G.n[0] * G.n[1];
     if ((size_t)G.n[0] * G.n[2] > face_max) face_max = (size_t)G.n[0] * G.n[2];
     if ((size_t)G.n[1] * G.n[2] > face_max) face_max = (size_t)G.n[1] * G.n[2];

@@ -10,14 +10,17 @@ constexpr int NQ = 8;       // transported set: rho, e, P-x, P+x, P-y, P+y, P-z,
 constexpr int NSTATE = 5;   // rho, e, vx, vy, vz
 constexpr int MAXLEV = 12;
 
-// Array geometry of one level.  Every field of a level is one 3-D array of
-// s[0] x s[1] x s[2] entries, x fastest; entry (i,j,k), i in [-g, n+g), is at
-// off + i + j*sy + k*sz.  A face field stores at (i,j,k) the face on the low
-// side of cell (i,j,k) along its own axis.
+// Array geometry of one level.  Every field of a level is one 3-D array,
+// x fastest; entry (i,j,k), i in [-g, s[0]-g), is at off + i + j*sy + k*sz.
+// A face field stores at (i,j,k) the face on the low side of cell (i,j,k)
+// along its own axis.  Rows are padded so that x = 0 of every row sits on a
+// 128-byte boundary.  Level 0 stores no ghosts (g = 0, s = n + 1: its
+// boundary conditions are applied on read); finer levels store a ghost shell
+// of width g (s = n + 2g).
 struct Geo {
   int n[3];
   int g;
-  int s[3];
+  int s[3];      // stored extent along each dimension
   long sy, sz;
   long off;
   double dx;

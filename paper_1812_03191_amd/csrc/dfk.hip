@@ -21,18 +21,50 @@ struct Box {
   int lo[3], hi[3];
 };
 
-inline bool empty_grid(const dim3 &g) { return g.x == 0 || g.y == 0 || g.z == 0; }
+inline bool empty_grid(const dim3 &g) { return g.x == 0; }
 
+// Kernels over a box launch a 1-D grid of tiles of 64 x 4 entries (x fastest)
+// times one plane.  The hardware hands workgroups to the 8 XCDs round-robin
+// (workgroup h runs on XCD h % 8); thread_cell gives each XCD one contiguous
+// range of tiles: a band of rows through all planes, walked plane by plane
+// (x-tile fastest, then y-tile within the band, then plane), so the neighbour
+// planes a stencil reads are in its own L2 (a few planes of one band fit
+// there) and neighbour rows are too except at band edges.
 inline dim3 grid_of(const Box &b) {
   int ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
-  if (ex <= 0 || ey <= 0 || ez <= 0) return dim3(0, 0, 0);
-  return dim3((ex + BX - 1) / BX, (ey + BY - 1) / BY, ez);
+  if (ex <= 0 || ey <= 0 || ez <= 0) return dim3(0, 1, 1);
+  long n = (long)((ex + BX - 1) / BX) * ((ey + BY - 1) / BY) * ez;
+  return dim3((unsigned)n, 1, 1);
 }
 
 __device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k) {
-  i = b.lo[0] + (int)(blockIdx.x * BX + threadIdx.x);
-  j = b.lo[1] + (int)(blockIdx.y * BY + threadIdx.y);
-  k = b.lo[2] + (int)blockIdx.z;
+  const unsigned nbx = (unsigned)(b.hi[0] - b.lo[0] + BX - 1) / BX;
+  const unsigned nby = (unsigned)(b.hi[1] - b.lo[1] + BY - 1) / BY;
+  const unsigned N = gridDim.x, h = blockIdx.x;
+  const unsigned nbz = N / (nbx * nby);
+  // contiguous tile range of this workgroup's XCD
+  const unsigned q = N / 8, r = N % 8, x = h % 8, s = h / 8;
+  unsigned L = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+  // 8 bands of y-tiles (sizes differ by at most one); a band's tiles are
+  // ordered x-tile fastest, then y-tile, then plane
+  const unsigned hq = nby / 8, hr = nby % 8;
+  unsigned band = 0, y0 = 0, hb = hq + (hr > 0);
+  for (unsigned bb = 0; bb < 8; ++bb) {
+    hb = hq + (bb < hr ? 1u : 0u);
+    unsigned nt = nbx * hb * nbz;
+    if (L < nt || bb == 7) {
+      band = bb;
+      break;
+    }
+    L -= nt;
+    y0 += hb;
+  }
+  (void)band;
+  const unsigned bx = L % nbx, t = L / nbx;
+  const unsigned by = y0 + t % hb, bz = t / hb;
+  i = b.lo[0] + (int)(bx * BX + threadIdx.x);
+  j = b.lo[1] + (int)(by * BY + threadIdx.y);
+  k = b.lo[2] + (int)bz;
   return i < b.hi[0] && j < b.hi[1];
 }
 
@@ -430,6 +462,187 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs A) {
   }
 }
 
+// Streaming form of the y and z passes.  A thread owns one column segment
+// [c0, c1) along DIR (lanes along x, so every load is coalesced) and walks it
+// once: each cell is loaded once, each limited difference and each face
+// transfer is computed once, and the cell is written as soon as its right face
+// is known.  The eight quantities are split over two waves of the block: one
+// moves rho, e, P-x, P+x, the other P-y, P+y, P-z, P+z (both compute the mass
+// transfers they scale).
+struct MarchArgs {
+  int lo[3], hi[3];    // cells to update; DIR is the walked dimension
+  int chunk;           // cells per segment
+  const double *qi[NQ];
+  double *qo[NQ];
+  const double *v;     // face velocity normal to DIR (after the first kick)
+  const double *dtp;
+  double fac;
+  double *acc;         // this level's frontier accumulators (fine levels) or null
+  const double *facc;  // the finer level's accumulators or null
+  int fn[3];
+};
+
+template <int DIR, bool BC>
+__global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs A) {
+  constexpr int TD = (DIR == 1) ? 2 : 1;   // transverse dimension walked by blocks
+  constexpr int T1 = (DIR == 0) ? 1 : 0;   // transverse dimensions of a face, in order
+  constexpr int T2 = (DIR == 2) ? 1 : 2;
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int grp = ty & 1;
+  const int nbx = (A.hi[0] - A.lo[0] + 63) / 64;
+  const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
+  const unsigned h = blockIdx.x;
+  const int bx = (int)(h % (unsigned)nbx);
+  const unsigned r1 = h / (unsigned)nbx;
+  const int tb = (int)(r1 % (unsigned)ntb);
+  const int ch = (int)(r1 / (unsigned)ntb);
+  const int i = A.lo[0] + bx * 64 + lane;
+  const int t = A.lo[TD] + tb * 2 + (ty >> 1);
+  if (i >= A.hi[0] || t >= A.hi[TD]) return;
+  const int c0 = A.lo[DIR] + ch * A.chunk;
+  const int c1 = min(c0 + A.chunk, A.hi[DIR]);
+  if (c0 >= c1) return;
+
+  const double dt = A.fac * A.dtp[0];
+  const double dx = G.dx;
+  const double mfac = dt * dx * dx, ivol = 1.0 / (dx * dx * dx), cour = dt / dx;
+  const long st = dstride(G, DIR);
+  // linear index of the cell at position c along DIR in this column
+  int id3[3];
+  id3[0] = i;
+  id3[TD] = t;
+  id3[DIR] = 0;
+  const long base = lin(G, id3[0], id3[1], id3[2]);
+  auto cidx = [&](int c) -> long {
+    if (BC) c = clampi(c, 0, G.n[DIR] - 1);
+    return base + (long)c * st;
+  };
+  // quantities of this wave: q[0] is always rho
+  const int mq[4] = {grp ? 4 : 1, grp ? 5 : 2, grp ? 6 : 3, grp ? 7 : -1};
+  const int nq = grp ? 4 : 3;
+
+  // frontier bookkeeping (transverse position of this column's faces)
+  const int tv1 = id3[T1], tv2 = id3[T2];
+  bool ov = false;
+  long fbase = 0, fnt = 0;
+  int flo = 0, fhi = 0;
+  if (A.facc) {
+    int a1 = tv1 - G.n[T1] / 4, a2 = tv2 - G.n[T2] / 4;
+    if (a1 >= 0 && a2 >= 0 && a1 < G.n[T1] / 2 && a2 < G.n[T2] / 2) {
+      ov = true;
+      fnt = (long)A.fn[T1] * A.fn[T2];
+      fbase = (long)(2 * a2) * A.fn[T1] + 2 * a1;
+      flo = G.n[DIR] / 4;
+      fhi = (3 * G.n[DIR]) / 4;
+    }
+  }
+  const bool acc_col = A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
+  const long acc_nt = (long)G.n[T1] * G.n[T2];
+  const long acc_i = (long)tv2 * G.n[T1] + tv1;
+  // final transfer of quantity m through face f, given the solver's value
+  auto fix = [&](int f, int m, double F) -> double {
+    if (ov && (f == flo || f == fhi)) {
+      const double *a = A.facc + ((long)(DIR * 2 + (f == fhi)) * NQ + m) * fnt + fbase;
+      F = (a[0] + a[1]) + (a[A.fn[T1]] + a[A.fn[T1] + 1]);
+    }
+    if (acc_col && f >= c0 && f < c1 && (f == 0 || f == G.n[DIR]))
+      A.acc[((long)(DIR * 2 + (f != 0)) * NQ + m) * acc_nt + acc_i] += F;
+    return F;
+  };
+  auto upwind = [&](double sl, double dl, double sr, double dr, double a, double nu) {
+    return (a > 0.0) ? sl + 0.5 * dl * (1.0 - nu) : sr - 0.5 * dr * (1.0 + nu);
+  };
+
+  // window: specific values at c, c+1 (s0, s1), limited difference at c (d0),
+  // transfer through face c (F0); index 0 is rho
+  double s0[5], s1[5], d0[5], F0[5];
+  {
+    double sm2[5], sm1[5];
+    const long im2 = cidx(c0 - 2), im1 = cidx(c0 - 1), i0 = cidx(c0), ip1 = cidx(c0 + 1);
+    const double r_m2 = A.qi[0][im2], r_m1 = A.qi[0][im1], r_0 = A.qi[0][i0], r_p1 = A.qi[0][ip1];
+    const double ir_m2 = 1.0 / r_m2, ir_m1 = 1.0 / r_m1, ir_0 = 1.0 / r_0, ir_p1 = 1.0 / r_p1;
+    sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = r_0; s1[0] = r_p1;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u >= nq) break;
+      const double *q = A.qi[mq[u]];
+      sm2[u + 1] = q[im2] * ir_m2;
+      sm1[u + 1] = q[im1] * ir_m1;
+      s0[u + 1] = q[i0] * ir_0;
+      s1[u + 1] = q[ip1] * ir_p1;
+    }
+    const double a = A.v[i0], nu = a * cour;
+    double M = 0.0;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      if (u > nq) break;
+      const double dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
+      d0[u] = vleer(s1[u] - s0[u], s0[u] - sm1[u]);
+      const double fv = upwind(sm1[u], dm1, s0[u], d0[u], a, nu);
+      if (u == 0) {
+        M = fv * a * mfac;
+        F0[0] = grp ? M : fix(c0, 0, M);  // rho belongs to the first wave
+      } else {
+        F0[u] = fix(c0, mq[u - 1], fv * M);
+      }
+    }
+  }
+  // raw values of cell c+2, loaded one iteration ahead of their use
+  double nx[5];
+  {
+    const long ip2 = cidx(c0 + 2);
+    nx[0] = A.qi[0][ip2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < nq) nx[u + 1] = A.qi[mq[u]][ip2];
+  }
+  for (int c = c0; c < c1; ++c) {
+    const long ic = cidx(c), ip3 = cidx(c + 3);
+    // issue this iteration's independent loads first: the cell's own values,
+    // its right face velocity and the cell two steps ahead
+    double own[5], nn[5];
+    const double a = A.v[base + (long)(c + 1) * st];
+    own[0] = A.qi[0][ic];
+    nn[0] = A.qi[0][ip3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < nq) {
+        own[u + 1] = A.qi[mq[u]][ic];
+        nn[u + 1] = A.qi[mq[u]][ip3];
+      }
+    }
+    const double ir2 = 1.0 / nx[0];
+    double s2[5];
+    s2[0] = nx[0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < nq) s2[u + 1] = nx[u + 1] * ir2;
+    const double nu = a * cour;
+    double M = 0.0;
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      if (u > nq) break;
+      const double d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
+      const double fv = upwind(s0[u], d0[u], s1[u], d1, a, nu);
+      double F1;
+      if (u == 0) {
+        M = fv * a * mfac;
+        F1 = grp ? M : fix(c + 1, 0, M);
+      } else {
+        F1 = fix(c + 1, mq[u - 1], fv * M);
+      }
+      const int m = (u == 0) ? 0 : mq[u - 1];
+      if (u > 0 || grp == 0) A.qo[m][ic] = own[u] - (F1 - F0[u]) * ivol;
+      F0[u] = F1;
+      d0[u] = d1;
+      s0[u] = s1[u];
+      s1[u] = s2[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) nx[u] = nn[u];
+  }
+}
+
 // ------------------------------------------------------------ CommUp
 
 struct UpArgs {
@@ -559,7 +772,7 @@ __device__ void block_sum3(double a, double b, double c, double *part) {
   }
   __syncthreads();
   if (t == 0) {
-    long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    long blk = blockIdx.x;
     double s0 = 0, s1 = 0, s2 = 0;
     for (int q = 0; q < BX * BY / 64; ++q) {
       s0 += sh[0][q];
@@ -683,7 +896,7 @@ __global__ void __launch_bounds__(BX * BY) k_signal(Geo G, Phys P, RedArgs A) {
   if (t == 0) {
     double m = sh[0];
     for (int q = 1; q < BX * BY / 64; ++q) m = fmax(m, sh[q]);
-    long blk = ((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    long blk = blockIdx.x;
     A.part[blk] = m;  // per-block maximum; reduced by k_dt_final
   }
 }
@@ -728,11 +941,12 @@ __global__ void k_zero(double *p, size_t n) {
   for (; t < n; t += stride) p[t] = 0.0;
 }
 
+// every stored entry (level 0 stores cells 0..n-1 and faces 0..n)
 Box full_box(const Geo &G) {
   Box b;
   for (int d = 0; d < 3; ++d) {
     b.lo[d] = -G.g;
-    b.hi[d] = G.n[d] + G.g;
+    b.hi[d] = G.s[d] - G.g;
   }
   return b;
 }
@@ -891,18 +1105,42 @@ void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBuf
   A.acc = G.level > 0 ? B.acc : nullptr;
   A.facc = (G.has_fine && fine_acc) ? fine_acc : nullptr;
   for (int d = 0; d < 3; ++d) A.fn[d] = Gf ? Gf->n[d] : 0;
-  dim3 gr = grid_of(A.b), bl(BX, BY);
-#define DFK_PASS(D, BCV, F) DFK_LAUNCH((k_pass<D, BCV, F>), gr, bl, st, G, P, A)
-  if (G.bc) {
-    if (dir == 0) DFK_PASS(0, true, true);
-    else if (dir == 1) DFK_PASS(1, true, false);
-    else DFK_PASS(2, true, false);
-  } else {
-    if (dir == 0) DFK_PASS(0, false, true);
-    else if (dir == 1) DFK_PASS(1, false, false);
-    else DFK_PASS(2, false, false);
+  if (dir == 0) {
+    dim3 gr = grid_of(A.b), bl(BX, BY);
+    if (G.bc) DFK_LAUNCH((k_pass<0, true, true>), gr, bl, st, G, P, A);
+    else DFK_LAUNCH((k_pass<0, false, true>), gr, bl, st, G, P, A);
+    return;
   }
-#undef DFK_PASS
+  MarchArgs M;
+  for (int d = 0; d < 3; ++d) {
+    M.lo[d] = A.b.lo[d];
+    M.hi[d] = A.b.hi[d];
+    M.fn[d] = A.fn[d];
+  }
+  const int ext = M.hi[dir] - M.lo[dir];
+  M.chunk = ext <= 16 ? ext : 16;
+  for (int m = 0; m < NQ; ++m) {
+    M.qi[m] = A.qi[m];
+    M.qo[m] = A.qo[m];
+  }
+  M.v = A.v[dir];
+  M.dtp = A.dtp;
+  M.fac = A.fac;
+  M.acc = A.acc;
+  M.facc = A.facc;
+  const int td = (dir == 1) ? 2 : 1;
+  const long nbx = (M.hi[0] - M.lo[0] + 63) / 64;
+  const long ntb = (M.hi[td] - M.lo[td] + 1) / 2;
+  const long nch = (ext + M.chunk - 1) / M.chunk;
+  dim3 gr((unsigned)(nbx * ntb * nch)), bl(64, 4);
+  if (ext <= 0) return;
+  if (G.bc) {
+    if (dir == 1) DFK_LAUNCH((k_march<1, true>), gr, bl, st, G, P, M);
+    else DFK_LAUNCH((k_march<2, true>), gr, bl, st, G, P, M);
+  } else {
+    if (dir == 1) DFK_LAUNCH((k_march<1, false>), gr, bl, st, G, P, M);
+    else DFK_LAUNCH((k_march<2, false>), gr, bl, st, G, P, M);
+  }
 }
 
 void zero(hipStream_t st, double *p, size_t n) {

@@ -50,7 +50,8 @@ def test_required_bytes_scales_with_mesh():
     b = dfm.init_mesh(64, 64, 64, 1, 0.1)
     c = dfm.init_mesh(64, 64, 64, 3, 0.1)
     na, nb, nc = (dfm.required_bytes(h) for h in (a, b, c))
-    assert 8 * 20 * 38 ** 3 <= na < 2 * 8 * 20 * 38 ** 3
+    # level 0 stores cells and faces 0..n (no ghosts), rows padded to 16 doubles
+    assert 8 * 20 * 33 ** 3 <= na < 2 * 8 * 20 * 33 ** 3
     assert nb > 6 * na
     assert nc > 3 * nb
     for h in (a, b, c):
