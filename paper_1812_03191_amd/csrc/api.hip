@@ -61,6 +61,8 @@ struct df_run {
   hipStream_t stream = nullptr;
   Scal *scal = nullptr;
   double *flog = nullptr;
+  size_t esz = 8;      // bytes per stored value (8 FP64, 4 FP32)
+  int chunk = 16;      // column segment of the streaming passes
   bool bound = false;
   bool ready = false;
   double eps = 0.0;
@@ -89,14 +91,15 @@ void carve(df_run *R, char *base) {
   Carver c{base};
   R->scal = c.take<Scal>(1);
   R->flog = c.take<double>(4 * (size_t)dfk::FLOG);
+  const size_t e = R->esz;
   for (int l = 0; l < R->nl; ++l) {
     LevBufs &B = R->buf[l];
-    size_t v = R->vol[l];
+    const size_t v = R->vol[l] * e;
     for (int s = 0; s < 2; ++s)
-      for (int m = 0; m < NQ; ++m) B.q[s][m] = c.take<double>(v);
-    for (int d = 0; d < 3; ++d) B.v[d] = c.take<double>(v);
-    B.etmp = c.take<double>(v);
-    B.acc = R->acc_n[l] ? c.take<double>(R->acc_n[l]) : nullptr;
+      for (int m = 0; m < NQ; ++m) B.q[s][m] = c.take<char>(v);
+    for (int d = 0; d < 3; ++d) B.v[d] = c.take<char>(v);
+    B.etmp = c.take<char>(v);
+    B.acc = R->acc_n[l] ? (void *)c.take<char>(R->acc_n[l] * e) : nullptr;
     const Geo &G = R->geo[l];
     B.hw = c.take<double>((size_t)G.n[0] * G.n[1] * G.n[2]);
     B.part = c.take<double>(3 * R->npart[l]);
@@ -164,21 +167,21 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   const Phys &P = R->phys;
   int c = R->cur[l];
   const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
-  const double *facc = Gf ? R->buf[l + 1].acc : nullptr;
+  const void *facc = Gf ? R->buf[l + 1].acc : nullptr;
   { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale); }
   { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale); }
   { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
   std::swap(B.etmp, B.q[c][1]);
-  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc); }
-  { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc); }
-  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc); }
+  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
+  { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
+  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true); }
   R->cur[l] = 1 - c;
 }
 
 void cycle(df_run *R, int l) {
   if (l + 1 < R->nl) {
-    { TScope t(R, K_ZERO); dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1]); }
+    { TScope t(R, K_ZERO); dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1] * R->esz); }
     cycle(R, l + 1);
     cycle(R, l + 1);
   }
@@ -188,7 +191,7 @@ void cycle(df_run *R, int l) {
       dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
                   R->cur[l + 1]); }
     { TScope t(R, K_COMMMEAN);
-      dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
+      dfk::commmean(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
                     R->cur[l]); }
   }
 }
@@ -214,13 +217,14 @@ void force_reduce(df_run *R, int slot) {
 
 void sync_levels(df_run *R) {
   for (int l = R->nl - 2; l >= 0; --l)
-    dfk::commmean(R->stream, R->geo[l + 1], R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l], R->cur[l]);
+    dfk::commmean(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
+                  R->cur[l]);
   for (int l = 0; l + 1 < R->nl; ++l)
     dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
                 R->cur[l + 1]);
 }
 
-double *field_ptr(df_run *R, int l, int f) {
+void *field_ptr(df_run *R, int l, int f) {
   LevBufs &B = R->buf[l];
   if (f == DF_RHO) return B.q[R->cur[l]][0];
   if (f == DF_E) return B.q[R->cur[l]][1];
@@ -271,7 +275,6 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return fail(DF_EINVAL, "gamma must exceed 1");
   if (!(d->cfl > 0.0) || d->cfl > 1.0) return fail(DF_EINVAL, "cfl must be in (0, 1]");
   if (d->precision != DF_FP64 && d->precision != DF_FP32) return fail(DF_EINVAL, "unknown precision");
-  if (d->precision == DF_FP32) return fail(DF_EINVAL, "FP32 storage is not available in this build");
   int gf = d->ghost_fine == 0 ? 10 : d->ghost_fine;
   if (d->nlevels > 1 && (gf < 10 || gf > 16)) return fail(DF_EINVAL, "ghost_fine must be 10..16");
   if (!std::isfinite(d->noise_amp) || std::fabs(d->noise_amp) >= 0.5) return fail(DF_EINVAL, "noise_amp out of range");
@@ -279,6 +282,8 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   df_run *R = new df_run();
   R->desc = *d;
   R->nl = d->nlevels;
+  R->esz = d->precision == DF_FP32 ? 4 : 8;
+  R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
     for (int k = 0; k < 3; ++k) G.n[k] = n[k];
@@ -346,6 +351,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
   P.chi = chi;
   P.e0 = P.rho0 * cs * cs / (d.gamma * (d.gamma - 1.0));
   P.cfl = d.cfl;
+  P.fp32 = d.precision == DF_FP32;
   R->eps = eps;
   hipStream_t st = R->stream;
   // heat tables
@@ -371,7 +377,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
     std::swap(B.etmp, B.q[1][1]);
     R->cur[l] = 0;
     dfk::init_state(st, R->geo[l], P, B, 0, d.seed, d.noise_amp);
-    if (B.acc) dfk::zero(st, B.acc, R->acc_n[l]);
+    if (B.acc) dfk::zero(st, B.acc, R->acc_n[l] * R->esz);
   }
   Scal zero{};
   rc = hip_check(hipMemcpyAsync(R->scal, &zero, sizeof(Scal), hipMemcpyHostToDevice, st), "scalars");
@@ -430,31 +436,47 @@ int df_totals(df_run *R, double out[3]) {
   return rc;
 }
 
+// background of a field (values are stored as departures from it)
+static double field_back(const df_run *R, int f) {
+  if (f == DF_RHO) return R->phys.rho0;
+  if (f == DF_E) return R->phys.e0;
+  if (f == DF_VX) return -R->phys.V;
+  return 0.0;
+}
+
 static int field_io(df_run *R, int l, int f, double *hout, const double *hin) {
   int rc = check_run(R, true);
   if (rc) return rc;
   if (l < 0 || l >= R->nl || f < DF_RHO || f > DF_VZ) return fail(DF_EINVAL, "bad level or field");
   const Geo &G = R->geo[l];
-  std::vector<double> full(R->vol[l]);
-  double *dev = field_ptr(R, l, f);
-  rc = hip_check(hipMemcpyAsync(full.data(), dev, full.size() * sizeof(double), hipMemcpyDeviceToHost, R->stream),
-                 "field copy");
+  const size_t nv = R->vol[l];
+  std::vector<char> raw(nv * R->esz);
+  void *dev = field_ptr(R, l, f);
+  rc = hip_check(hipMemcpyAsync(raw.data(), dev, raw.size(), hipMemcpyDeviceToHost, R->stream), "field copy");
   if (rc) return rc;
   rc = hip_check(hipStreamSynchronize(R->stream), "field copy");
   if (rc) return rc;
+  const bool f32 = R->esz == 4;
+  float *rf = reinterpret_cast<float *>(raw.data());
+  double *rd = reinterpret_cast<double *>(raw.data());
+  const double back = field_back(R, f);
   int e[3] = {G.n[0], G.n[1], G.n[2]};
   if (f >= DF_VX) e[f - DF_VX] += 1;
   size_t a = 0;
   for (int k = 0; k < e[2]; ++k)
     for (int j = 0; j < e[1]; ++j)
       for (int i = 0; i < e[0]; ++i) {
-        size_t c = (size_t)(G.off + i + (long)j * G.sy + (long)k * G.sz);
-        if (hout) hout[a++] = full[c];
-        else full[c] = hin[a++];
+        const size_t c = (size_t)(G.off + i + (long)j * G.sy + (long)k * G.sz);
+        if (hout) {
+          hout[a++] = back + (f32 ? (double)rf[c] : rd[c]);
+        } else {
+          const double dv = hin[a++] - back;
+          if (f32) rf[c] = (float)dv;
+          else rd[c] = dv;
+        }
       }
   if (hin) {
-    rc = hip_check(hipMemcpyAsync(dev, full.data(), full.size() * sizeof(double), hipMemcpyHostToDevice, R->stream),
-                   "field copy");
+    rc = hip_check(hipMemcpyAsync(dev, raw.data(), raw.size(), hipMemcpyHostToDevice, R->stream), "field copy");
     if (rc) return rc;
     rc = hip_check(hipStreamSynchronize(R->stream), "field copy");
   }
@@ -514,9 +536,9 @@ int df_debug_stage(df_run *R, int32_t stage, double dt) {
     case 3: dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, true, false); std::swap(B.etmp, B.q[c][1]); break;
     case 4: dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, false, true); std::swap(B.etmp, B.q[c][1]); break;
     case 5:
-      dfk::transport_pass(st, 0, G, P, B, c, dtp, 1.0, nullptr, nullptr);
-      dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, 1.0, nullptr, nullptr);
-      dfk::transport_pass(st, 2, G, P, B, c, dtp, 1.0, nullptr, nullptr);
+      dfk::transport_pass(st, 0, G, P, B, c, dtp, 1.0, nullptr, nullptr, R->chunk);
+      dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, 1.0, nullptr, nullptr, R->chunk);
+      dfk::transport_pass(st, 2, G, P, B, c, dtp, 1.0, nullptr, nullptr, R->chunk);
       dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.0, false);
       R->cur[0] = 1 - c;
       break;

@@ -29,7 +29,8 @@ struct Geo {
   int has_fine;  // a finer level covers the central half
 };
 
-// Gas and perturber parameters (code units).
+// Gas and perturber parameters (code units).  The fields are stored as
+// departures from the uniform background (rho0, e0, wind (-V, 0, 0)).
 struct Phys {
   double gamma, gm1;   // adiabatic index, gamma - 1
   double GM, eps2;     // perturber mass and squared Plummer length
@@ -37,6 +38,7 @@ struct Phys {
   double V;            // wind speed (gas enters through x_max at -V)
   double chi, rho0, e0;
   double cfl;
+  int fp32;            // storage type: float (1) or double (0)
 };
 
 // Device-resident scalars of a run (one small array in the arena).
@@ -52,12 +54,12 @@ struct Scal {
 
 constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
 
-// Pointers of one level (FP64 storage).
+// Buffers of one level, in the run's storage type (double or float).
 struct LevBufs {
-  double *q[2][NQ];   // ping-pong transported sets; q[cur][0], q[cur][1] are rho, e
-  double *v[3];       // face velocities
-  double *etmp;       // diffusion output
-  double *acc;        // frontier transfers of this (fine) level: [dir][side][q][t2][t1]
+  void *q[2][NQ];     // ping-pong transported sets; q[cur][0], q[cur][1] are rho, e
+  void *v[3];         // face velocities
+  void *etmp;         // diffusion output
+  void *acc;          // frontier transfers of this (fine) level: [dir][side][q][t2][t1]
   double *hw;         // heat weights on a box of hw_n[0] x hw_n[1] x hw_n[2] cells
                       // centred on the perturber vertex (x fastest)
   int hw_n[3];        // box extent (0: no heat table)
@@ -80,13 +82,14 @@ void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
 // one transport pass q[src] -> q[1-src]; dir 0 builds the momenta from the
 // face velocities; a fine level adds its frontier transfers into B.acc; a
 // level with a finer one (Gf, fine_acc) takes that level's sums on the frontier
+// chunk: cells per column segment of the streaming y and z passes
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src,
-                    const double *dtp, double fac, const Geo *Gf, const double *fine_acc);
-void zero(hipStream_t st, double *p, size_t n);
+                    const double *dtp, double fac, const Geo *Gf, const void *fine_acc, int chunk);
+void zero(hipStream_t st, void *p, size_t bytes);
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf,
             LevBufs &Bf, int curf);
-void commmean(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, const Geo &Gc, LevBufs &Bc,
-              int curc);
+void commmean(hipStream_t st, const Geo &Gf, const Phys &P, LevBufs &Bf, int curf, const Geo &Gc,
+              LevBufs &Bc, int curc);
 // per-block maxima of the signal speed of one level into B.part; health flag
 void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
 // dt of every level from the per-block maxima; t += dt0 if advance

@@ -234,3 +234,72 @@ def test_config2_full_run_properties(dfm):
     assert np.max(np.abs(rho - rho[:, ::-1, :])) < 1e-13
     assert np.max(np.abs(rho - rho[::-1, :, :])) < 1e-13
     assert abs(hot[1]) < 1e-9 * abs(hot[0]) and abs(hot[2]) < 1e-9 * abs(hot[0])
+
+
+# ---------------------------------------------------- FP32 departure storage
+
+def _pair32(dfm, cfg):
+    from oracle.oracle import Oracle
+
+    c = dict(cfg)
+    o = Oracle(c["nx"], c["ny"], c["nz"], nlevels=c["nlevels"], dx0=c["dx0"], gamma=c["gamma"],
+               cfl=c["cfl"], seed=c["seed"], noise_amp=c["noise_amp"], GM=c["GM"], eps=c["eps"],
+               L=c["L"], mach=c["mach"], chi=c["chi"])
+    g = dfm.Run(c["nx"], c["ny"], c["nz"], nlevels=c["nlevels"], dx0=c["dx0"], gamma=c["gamma"],
+                cfl=c["cfl"], seed=c["seed"], noise_amp=c["noise_amp"], precision=dfm.DF_FP32)
+    g.set_perturber(c["GM"], c["eps"], c["L"], c["mach"], c["chi"])
+    return o, g
+
+
+@pytest.mark.parametrize("stage,dt", STAGE_CASES)
+def test_stage_parity_fp32(dfm, stage, dt):
+    # departures of ~1e-3 stored in FP32: ~1e-10 absolute per stage
+    from oracle.oracle import Oracle
+
+    n = (20, 12, 18)
+    _say(f"[stage parity fp32] {stage}")
+    o, g64 = _random_pair(dfm, n, seed=23)
+    g = dfm.Run(*n, dx0=0.05, noise_amp=0.0, precision=dfm.DF_FP32)
+    g.set_perturber(0.01, 0.05, 2e-3, 0.5, 0.1)
+    for name in FIELD_NAMES:
+        g.set_field(0, name, g64.field(0, name))
+    o.stage(stage, dt)
+    g.stage(stage, dt)
+    errs = _field_errors(o, g, 1)
+    assert max(errs.values()) < 2e-8, errs
+
+
+def _fp32_report(o, g, nlevels):
+    fo, fg = o.force(), g.force()[:3]
+    to, tg = o.totals()[:3], g.totals()
+    rep = {"force_rel": float(abs(fg[0] - fo[0]) / abs(fo[0])),
+           "mass_rel": float(abs(tg[0] - to[0]) / to[0]),
+           "eint_rel": float(abs(tg[1] - to[1]) / to[1]),
+           "ekin_rel": float(abs(tg[2] - to[2]) / max(to[2], 1e-300))}
+    drho = max(float(np.max(np.abs(g.field(l, "rho") - o.field(l, "rho")))) for l in range(nlevels))
+    rep["rho_abs"] = drho
+    return rep
+
+
+def test_fp32_config1_force_error(dfm):
+    # FP32 departures vs the FP64 oracle after 100 steps: force within 1e-4
+    cfg, steps = inputs.config1()
+    _say("[fp32] config1 32^3 x 100")
+    o, g = _pair32(dfm, cfg)
+    o.step(steps)
+    g.step(steps)
+    rep = _fp32_report(o, g, 1)
+    _say(f"[fp32] config1 errors {rep}")
+    assert rep["force_rel"] < 1e-4, rep
+    assert rep["mass_rel"] < 1e-7, rep
+
+
+def test_fp32_nested_force_error(dfm):
+    cfg = inputs.job(32, 3, 0.3, 1e-3, 0.1, 1e-3, seed=3)
+    _say("[fp32] nested 3 x 32^3 x 20")
+    o, g = _pair32(dfm, cfg)
+    o.step(20)
+    g.step(20)
+    rep = _fp32_report(o, g, 3)
+    _say(f"[fp32] nested errors {rep}")
+    assert rep["force_rel"] < 1e-4, rep
