@@ -68,7 +68,10 @@ typedef struct df_run df_run;
  *  ghost_fine : ghost width of levels >= 1 (0 selects 10, the least width that
  *               carries two sub-cycles without a refill, Sect. 3.2.1);
  *  seed, noise_amp : every active density is multiplied by 1 + noise_amp (2U-1),
- *               U uniform in [0,1) from a counter-based SplitMix64 stream. */
+ *               U uniform in [0,1) from a counter-based SplitMix64 stream;
+ *  tile_chunk : cells per column segment of the streaming y and z transport
+ *               passes (0 selects 16; 2..256), a launch-shape parameter that
+ *               does not change results. */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t nlevels;
@@ -79,6 +82,7 @@ typedef struct {
   int32_t ghost_fine;
   uint64_t seed;
   double noise_amp;
+  int32_t tile_chunk;
 } df_mesh_desc;
 
 /* Validate a mesh description and create a run handle (host memory only; no
@@ -157,6 +161,55 @@ int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);
 
 /* Release the handle (not the caller's arena or stream). */
 int df_destroy(df_run *run);
+
+/* ---------------------------------------------------------------- engine
+ * Continuous batching of independent runs (for instance a Mach / luminosity
+ * sweep) on one GPU.  The caller owns one device arena, which is the HBM
+ * budget, and a stream.  Each admitted job is a run carved from a free range of
+ * the arena.  df_engine_step advances every active job by 2 coarse steps per
+ * call of its count: the launches of all active jobs are captured into one HIP
+ * graph, spread over nstreams worker streams so that jobs overlap on the
+ * device, and replayed on the caller's stream; the graph is captured again
+ * when the set of jobs changes.  A job's results are bitwise those of the same
+ * job run alone.  Jobs run a multiple of 2 coarse steps (nsteps rounded up). */
+typedef struct df_engine df_engine;
+
+/* dev_arena: device pointer (256-byte aligned) of `bytes` bytes owned by the
+ * caller; stream: hipStream_t of the caller; nstreams: 1..4 worker streams. */
+int df_engine_create(void *dev_arena, size_t bytes, void *stream, int32_t nstreams, df_engine **out);
+
+/* Arena bytes one job of this description takes. */
+int df_engine_job_bytes(const df_mesh_desc *desc, size_t *bytes);
+
+/* Admit a job: perturber = {GM, eps, L, mach, chi} (as df_set_perturber),
+ * nsteps >= 1 coarse steps.  Initialises it (synchronously, on the engine's own
+ * stream) and returns its slot.  DF_EBUSY if no arena range or slot is free. */
+int df_engine_admit(df_engine *eng, const df_mesh_desc *desc, const double perturber[5], int32_t nsteps,
+                    int32_t *slot);
+
+/* n engine steps (2 coarse steps of every active job each); asynchronous. */
+int df_engine_step(df_engine *eng, int32_t n);
+
+/* Slots of jobs that ran all their steps and whose work has completed on the
+ * device since the last poll (non-blocking): up to cap into done[], count into
+ * *ndone. */
+int df_engine_poll(df_engine *eng, int32_t *done, int32_t cap, int32_t *ndone);
+
+/* Number of active jobs and the largest free arena range in bytes. */
+int df_engine_active(df_engine *eng, int32_t *nactive, size_t *free_bytes);
+
+/* Results of a job (synchronise the engine's work so far): force as df_force,
+ * fields as df_get_field. */
+int df_engine_force(df_engine *eng, int32_t slot, double out[4]);
+int df_engine_get_field(df_engine *eng, int32_t slot, int32_t level, int32_t field, double *host);
+
+/* Free a job's slot and arena range (synchronises). */
+int df_engine_release(df_engine *eng, int32_t slot);
+
+/* out[0] graph replays, out[1] graph captures since creation. */
+int df_engine_stats(df_engine *eng, int64_t out[2]);
+
+int df_engine_destroy(df_engine *eng);
 
 const char *df_strerror(int code);
 const char *df_last_error(void);

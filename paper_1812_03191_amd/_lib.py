@@ -30,6 +30,7 @@ class MeshDesc(ctypes.Structure):
         ("dx0", ctypes.c_double), ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
         ("precision", ctypes.c_int32), ("ghost_fine", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
+        ("tile_chunk", ctypes.c_int32),
     ]
 
 
@@ -92,10 +93,17 @@ def _dp(a: np.ndarray):
 
 # ---------------------------------------------------------------- entry points
 
+def mesh_desc(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0) -> MeshDesc:
+    return MeshDesc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
+                    tile_chunk)
+
+
 def init_mesh(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
-              ghost_fine=0, seed=1, noise_amp=1e-6) -> int:
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0) -> int:
     lib = _load()
-    d = MeshDesc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp)
+    d = mesh_desc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
+                  tile_chunk)
     h = ctypes.c_void_p()
     _ck(lib.df_init_mesh(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -187,7 +195,8 @@ class Run:
     ``device``; kernels go to the stream current at construction."""
 
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0, gamma=5.0 / 3.0, cfl=0.4,
-                 precision=DF_FP64, ghost_fine=0, seed=1, noise_amp=1e-6, device="cuda"):
+                 precision=DF_FP64, ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0,
+                 device="cuda"):
         import torch
 
         ny = nx if ny is None else ny
@@ -195,7 +204,7 @@ class Run:
         self.n = (nx, ny, nz)
         self.nlevels = nlevels
         self._h = init_mesh(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed,
-                            noise_amp)
+                            noise_amp, tile_chunk)
         self.nbytes = required_bytes(self._h)
         self.device = torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
@@ -255,3 +264,116 @@ class Run:
         if a.shape != self.shape(name):
             raise ValueError(f"shape {a.shape} != {self.shape(name)}")
         set_field(self._h, level, FIELDS[name], a)
+
+
+# ------------------------------------------------------------------ engine
+
+def _engine_sigs(lib):
+    vp, i32, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "df_engine_create": [vp, ctypes.c_size_t, vp, i32, ctypes.POINTER(vp)],
+        "df_engine_job_bytes": [ctypes.POINTER(MeshDesc), ctypes.POINTER(ctypes.c_size_t)],
+        "df_engine_admit": [vp, ctypes.POINTER(MeshDesc), dp, i32, ctypes.POINTER(i32)],
+        "df_engine_step": [vp, i32],
+        "df_engine_poll": [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32)],
+        "df_engine_active": [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)],
+        "df_engine_force": [vp, i32, dp],
+        "df_engine_get_field": [vp, i32, i32, i32, dp],
+        "df_engine_release": [vp, i32],
+        "df_engine_stats": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "df_engine_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        if f.argtypes is None:
+            f.argtypes = args
+            f.restype = ctypes.c_int
+
+
+DF_EBUSY = -6
+
+
+def engine_job_bytes(cfg: dict, precision=DF_FP64, tile_chunk=0) -> int:
+    lib = _load()
+    _engine_sigs(lib)
+    d = _desc_of(cfg, precision, tile_chunk)
+    n = ctypes.c_size_t()
+    _ck(lib.df_engine_job_bytes(ctypes.byref(d), ctypes.byref(n)))
+    return n.value
+
+
+def _desc_of(cfg, precision, tile_chunk):
+    return mesh_desc(cfg["nx"], cfg["ny"], cfg["nz"], cfg["nlevels"], cfg["dx0"], cfg.get("gamma", 5.0 / 3.0),
+                     cfg.get("cfl", 0.4), precision, cfg.get("ghost_fine", 0), cfg.get("seed", 1),
+                     cfg.get("noise_amp", 1e-6), tile_chunk)
+
+
+class Engine:
+    """Continuous batching of independent runs (df_engine_*): one device arena
+    (the HBM budget) allocated by PyTorch, the current stream as the replay
+    stream."""
+
+    def __init__(self, budget_bytes: int, *, nstreams=4, device="cuda"):
+        import torch
+
+        lib = _load()
+        _engine_sigs(lib)
+        self.device = torch.device(device)
+        self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _ck(lib.df_engine_create(self.arena.data_ptr(), int(budget_bytes), self.stream.cuda_stream,
+                                 int(nstreams), ctypes.byref(h)))
+        self._h = h.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            try:
+                _ck(_load().df_engine_destroy(h))
+            finally:
+                self._h = None
+
+    def admit(self, cfg: dict, nsteps: int, *, precision=DF_FP64, tile_chunk=0):
+        """slot of the admitted job, or None when the budget or slots are exhausted"""
+        d = _desc_of(cfg, precision, tile_chunk)
+        pert = (ctypes.c_double * 5)(cfg["GM"], cfg["eps"], cfg["L"], cfg["mach"], cfg["chi"])
+        slot = ctypes.c_int32()
+        rc = _load().df_engine_admit(self._h, ctypes.byref(d), pert, int(nsteps), ctypes.byref(slot))
+        if rc == DF_EBUSY:
+            return None
+        _ck(rc)
+        return slot.value
+
+    def step(self, n=1):
+        _ck(_load().df_engine_step(self._h, int(n)))
+
+    def poll(self, cap=1024):
+        out = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32()
+        _ck(_load().df_engine_poll(self._h, out, cap, ctypes.byref(n)))
+        return [out[i] for i in range(n.value)]
+
+    def active(self):
+        n = ctypes.c_int32()
+        fb = ctypes.c_size_t()
+        _ck(_load().df_engine_active(self._h, ctypes.byref(n), ctypes.byref(fb)))
+        return n.value, fb.value
+
+    def force(self, slot):
+        out = np.zeros(4)
+        _ck(_load().df_engine_force(self._h, int(slot), _dp(out)))
+        return out
+
+    def field(self, slot, level, name, shape):
+        out = np.zeros(shape)
+        _ck(_load().df_engine_get_field(self._h, int(slot), int(level), FIELDS[name], _dp(out)))
+        return out
+
+    def release(self, slot):
+        _ck(_load().df_engine_release(self._h, int(slot)))
+
+    def stats(self):
+        out = (ctypes.c_int64 * 2)()
+        _ck(_load().df_engine_stats(self._h, out))
+        return {"replays": out[0], "captures": out[1]}

@@ -171,8 +171,11 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale); }
   { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale); }
   { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
-  std::swap(B.etmp, B.q[c][1]);
-  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
+  // the x pass reads the new energy from the diffusion output; every buffer
+  // keeps its role, so the launches of two consecutive steps repeat exactly
+  LevBufs Bx = B;
+  Bx.q[c][1] = B.etmp;
+  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true); }
@@ -240,6 +243,15 @@ int check_run(const df_run *R, bool need_ready) {
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
+// n coarse steps: device time step, recursive cycle, force into the log
+void enqueue_steps(df_run *R, int n) {
+  for (int s = 0; s < n; ++s) {
+    compute_dt(R, 1);
+    cycle(R, 0);
+    force_reduce(R, 2);
+  }
+}
+
 }  // namespace
 
 // ================================================================== ABI
@@ -278,11 +290,13 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   int gf = d->ghost_fine == 0 ? 10 : d->ghost_fine;
   if (d->nlevels > 1 && (gf < 10 || gf > 16)) return fail(DF_EINVAL, "ghost_fine must be 10..16");
   if (!std::isfinite(d->noise_amp) || std::fabs(d->noise_amp) >= 0.5) return fail(DF_EINVAL, "noise_amp out of range");
+  if (d->tile_chunk != 0 && (d->tile_chunk < 2 || d->tile_chunk > 256)) return fail(DF_EINVAL, "tile_chunk must be 2..256");
 
   df_run *R = new df_run();
   R->desc = *d;
   R->nl = d->nlevels;
   R->esz = d->precision == DF_FP32 ? 4 : 8;
+  R->chunk = d->tile_chunk ? d->tile_chunk : 16;
   R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
@@ -395,11 +409,7 @@ int df_step(df_run *R, int32_t n) {
   int rc = check_run(R, true);
   if (rc) return rc;
   if (n < 0) return fail(DF_EINVAL, "negative step count");
-  for (int s = 0; s < n; ++s) {
-    compute_dt(R, 1);
-    cycle(R, 0);
-    force_reduce(R, 2);
-  }
+  enqueue_steps(R, n);
   return launch_check("df_step");
 }
 
@@ -628,6 +638,389 @@ int df_destroy(df_run *R) {
   if (!R) return fail(DF_EINVAL, "null run handle");
   for (hipEvent_t e : R->ev) hipEventDestroy(e);
   delete R;
+  return DF_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== engine
+//
+// Continuous batching of independent runs on one GPU.  The engine owns nothing
+// but host metadata: the caller passes one device arena (its HBM budget) and a
+// stream.  Each admitted job is a run carved from a free range of the arena
+// (first fit, 256-byte aligned) and initialised on the engine's admission
+// stream.  One engine step advances every active job by two coarse steps: the
+// launches of all jobs are captured once into a HIP graph, spread over the
+// worker streams (forked from and joined back to the caller's stream inside
+// the capture, so the kernels of different jobs overlap on the device), and
+// the graph is replayed on the caller's stream.  Two steps bring every buffer
+// of every job back to its role, so the same graph replays until the set of
+// jobs changes (an admission, a completion or a release), when it is captured
+// again.  A job's arithmetic does not depend on the other jobs, on its stream
+// or on the graph, so its results are bitwise those of the same job run alone.
+
+namespace {
+
+constexpr int ENGINE_MAX_SLOTS = 1024;
+constexpr int ENGINE_STEPS_PER_REPLAY = 2;
+
+struct EngineJob {
+  bool used = false;
+  df_run *run = nullptr;
+  size_t off = 0, len = 0;
+  int32_t remaining = 0;  // coarse steps still to run
+  bool active = false;    // in the graph
+  bool done = false;      // all steps enqueued
+  bool reported = false;  // returned by poll
+  int worker = 0;
+};
+
+struct Pending {
+  hipEvent_t ev;
+  std::vector<int> slots;
+};
+
+}  // namespace
+
+struct df_engine {
+  char *base = nullptr;
+  size_t bytes = 0;
+  hipStream_t main = nullptr, admin = nullptr;
+  hipStream_t cap = nullptr;  // capture origin (the caller's stream may be the null stream)
+  std::vector<hipStream_t> workers;
+  std::vector<EngineJob> jobs;
+  std::vector<std::pair<size_t, size_t>> freel;  // (offset, length), sorted, coalesced
+  hipGraphExec_t exec = nullptr;
+  bool dirty = true;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  std::vector<Pending> pending;
+  std::vector<int> finished;  // completed and not yet polled
+  std::vector<hipEvent_t> ev_pool;
+  long replays = 0, captures = 0;
+};
+
+namespace {
+
+bool arena_take(df_engine *E, size_t need, size_t &off) {
+  need = align_up(need);
+  for (size_t i = 0; i < E->freel.size(); ++i) {
+    auto &fr = E->freel[i];
+    if (fr.second >= need) {
+      off = fr.first;
+      fr.first += need;
+      fr.second -= need;
+      if (fr.second == 0) E->freel.erase(E->freel.begin() + (long)i);
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_give(df_engine *E, size_t off, size_t len) {
+  len = align_up(len);
+  auto &F = E->freel;
+  size_t i = 0;
+  while (i < F.size() && F[i].first < off) ++i;
+  F.insert(F.begin() + (long)i, {off, len});
+  // coalesce neighbours
+  if (i + 1 < F.size() && F[i].first + F[i].second == F[i + 1].first) {
+    F[i].second += F[i + 1].second;
+    F.erase(F.begin() + (long)i + 1);
+  }
+  if (i > 0 && F[i - 1].first + F[i - 1].second == F[i].first) {
+    F[i - 1].second += F[i].second;
+    F.erase(F.begin() + (long)i);
+  }
+}
+
+hipEvent_t engine_event(df_engine *E) {
+  if (!E->ev_pool.empty()) {
+    hipEvent_t e = E->ev_pool.back();
+    E->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return e;
+}
+
+int engine_capture(df_engine *E) {
+  if (E->exec) {
+    hipGraphExecDestroy(E->exec);
+    E->exec = nullptr;
+  }
+  std::vector<int> act;
+  for (int s = 0; s < (int)E->jobs.size(); ++s)
+    if (E->jobs[s].used && E->jobs[s].active) act.push_back(s);
+  E->dirty = false;
+  if (act.empty()) return DF_OK;
+  int rc = hip_check(hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed), "graph capture");
+  if (rc) return rc;
+  hipEventRecord(E->fork, E->cap);
+  for (hipStream_t w : E->workers) hipStreamWaitEvent(w, E->fork, 0);
+  for (size_t q = 0; q < act.size(); ++q) {
+    EngineJob &J = E->jobs[act[q]];
+    J.worker = (int)(q % E->workers.size());
+    df_run *R = J.run;
+    R->stream = E->workers[J.worker];
+    const bool timing = R->timing;
+    R->timing = false;
+    enqueue_steps(R, ENGINE_STEPS_PER_REPLAY);
+    R->timing = timing;
+  }
+  for (size_t w = 0; w < E->workers.size(); ++w) {
+    hipEventRecord(E->join[w], E->workers[w]);
+    hipStreamWaitEvent(E->cap, E->join[w], 0);
+  }
+  hipGraph_t g = nullptr;
+  rc = hip_check(hipStreamEndCapture(E->cap, &g), "graph capture end");
+  if (rc) return rc;
+  rc = hip_check(hipGraphInstantiate(&E->exec, g, nullptr, nullptr, 0), "graph instantiate");
+  hipGraphDestroy(g);
+  E->captures++;
+  return rc;
+}
+
+int check_engine(const df_engine *E) { return E ? DF_OK : fail(DF_EINVAL, "null engine"); }
+
+// finished jobs whose last replay has completed on the device
+void engine_collect(df_engine *E, bool wait) {
+  size_t k = 0;
+  for (; k < E->pending.size(); ++k) {
+    Pending &p = E->pending[k];
+    hipError_t q = wait ? hipEventSynchronize(p.ev) : hipEventQuery(p.ev);
+    if (q != hipSuccess) break;
+    for (int s : p.slots) E->finished.push_back(s);
+    E->ev_pool.push_back(p.ev);
+  }
+  E->pending.erase(E->pending.begin(), E->pending.begin() + (long)k);
+}
+
+}  // namespace
+
+extern "C" {
+
+int df_engine_create(void *dev_arena, size_t bytes, void *stream, int32_t nstreams, df_engine **out) {
+  if (!dev_arena || !out) return fail(DF_EINVAL, "null argument");
+  if (((uintptr_t)dev_arena) % ALIGN) return fail(DF_EINVAL, "arena must be 256-byte aligned");
+  if (nstreams < 1 || nstreams > 4) return fail(DF_EINVAL, "nstreams must be 1..4");
+  df_engine *E = new df_engine();
+  E->base = (char *)dev_arena;
+  E->bytes = bytes / ALIGN * ALIGN;
+  E->main = (hipStream_t)stream;
+  E->jobs.resize(ENGINE_MAX_SLOTS);
+  E->freel.push_back({0, E->bytes});
+  int rc = hip_check(hipStreamCreate(&E->admin), "stream create");
+  if (!rc) rc = hip_check(hipStreamCreate(&E->cap), "stream create");
+  for (int w = 0; w < nstreams && !rc; ++w) {
+    hipStream_t s = nullptr;
+    rc = hip_check(hipStreamCreate(&s), "stream create");
+    E->workers.push_back(s);
+    hipEvent_t j = nullptr;
+    if (!rc) rc = hip_check(hipEventCreateWithFlags(&j, hipEventDisableTiming), "event create");
+    E->join.push_back(j);
+  }
+  if (!rc) rc = hip_check(hipEventCreateWithFlags(&E->fork, hipEventDisableTiming), "event create");
+  if (rc) {
+    df_engine_destroy(E);
+    return rc;
+  }
+  *out = E;
+  return DF_OK;
+}
+
+int df_engine_job_bytes(const df_mesh_desc *desc, size_t *bytes) {
+  if (!bytes) return fail(DF_EINVAL, "null output");
+  df_run *R = nullptr;
+  int rc = df_init_mesh(desc, &R);
+  if (rc) return rc;
+  *bytes = align_up(R->need);
+  delete R;
+  return DF_OK;
+}
+
+int df_engine_admit(df_engine *E, const df_mesh_desc *desc, const double perturber[5], int32_t nsteps,
+                    int32_t *slot) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  if (!desc || !perturber || !slot || nsteps < 1) return fail(DF_EINVAL, "bad admission arguments");
+  int s = -1;
+  for (int k = 0; k < (int)E->jobs.size(); ++k)
+    if (!E->jobs[k].used) {
+      s = k;
+      break;
+    }
+  if (s < 0) return fail(DF_EBUSY, "no free job slot");
+  df_run *R = nullptr;
+  rc = df_init_mesh(desc, &R);
+  if (rc) return rc;
+  size_t off = 0;
+  if (!arena_take(E, R->need, off)) {
+    delete R;
+    return fail(DF_EBUSY, "HBM budget exhausted");
+  }
+  rc = df_bind(R, E->base + off, align_up(R->need), E->admin);
+  if (!rc)
+    rc = df_set_perturber(R, perturber[0], perturber[1], perturber[2], perturber[3], perturber[4]);
+  if (rc) {
+    arena_give(E, off, R->need);
+    delete R;
+    return rc;
+  }
+  EngineJob &J = E->jobs[s];
+  J = EngineJob();
+  J.used = true;
+  J.run = R;
+  J.off = off;
+  J.len = R->need;
+  J.remaining = (nsteps + ENGINE_STEPS_PER_REPLAY - 1) / ENGINE_STEPS_PER_REPLAY * ENGINE_STEPS_PER_REPLAY;
+  J.active = true;
+  E->dirty = true;
+  *slot = s;
+  return DF_OK;
+}
+
+int df_engine_step(df_engine *E, int32_t n) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  if (n < 0) return fail(DF_EINVAL, "negative step count");
+  for (int r = 0; r < n; ++r) {
+    if (E->dirty) {
+      rc = engine_capture(E);
+      if (rc) return rc;
+    }
+    if (!E->exec) return DF_OK;  // nothing active
+    rc = hip_check(hipGraphLaunch(E->exec, E->main), "graph launch");
+    if (rc) return rc;
+    E->replays++;
+    Pending p;
+    for (int s = 0; s < (int)E->jobs.size(); ++s) {
+      EngineJob &J = E->jobs[s];
+      if (!J.used || !J.active) continue;
+      J.remaining -= ENGINE_STEPS_PER_REPLAY;
+      if (J.remaining <= 0) {
+        J.active = false;
+        J.done = true;
+        p.slots.push_back(s);
+        E->dirty = true;
+      }
+    }
+    if (!p.slots.empty()) {
+      p.ev = engine_event(E);
+      hipEventRecord(p.ev, E->main);
+      E->pending.push_back(p);
+    }
+  }
+  return DF_OK;
+}
+
+int df_engine_poll(df_engine *E, int32_t *done, int32_t cap, int32_t *ndone) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  if (!ndone || (cap > 0 && !done)) return fail(DF_EINVAL, "bad output");
+  engine_collect(E, false);
+  int32_t k = 0;
+  size_t used = 0;
+  for (; used < E->finished.size() && k < cap; ++used) {
+    int s = E->finished[used];
+    E->jobs[s].reported = true;
+    done[k++] = s;
+  }
+  E->finished.erase(E->finished.begin(), E->finished.begin() + (long)used);
+  *ndone = k;
+  return DF_OK;
+}
+
+int df_engine_active(df_engine *E, int32_t *nactive, size_t *free_bytes) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  int32_t a = 0;
+  for (auto &J : E->jobs) a += (J.used && J.active) ? 1 : 0;
+  size_t fb = 0;
+  for (auto &fr : E->freel) fb = fr.second > fb ? fr.second : fb;
+  if (nactive) *nactive = a;
+  if (free_bytes) *free_bytes = fb;
+  return DF_OK;
+}
+
+static int engine_job(df_engine *E, int32_t slot, EngineJob **J) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  if (slot < 0 || slot >= (int)E->jobs.size() || !E->jobs[slot].used) return fail(DF_EINVAL, "bad slot");
+  *J = &E->jobs[slot];
+  return DF_OK;
+}
+
+// results of a job: a job returned by poll has completed on the device; any
+// other job waits for the engine's work enqueued so far.  Reads then go to the
+// admission stream.
+static int engine_quiesce(df_engine *E, EngineJob *J) {
+  if (!(J->done && J->reported)) {
+    int rc = hip_check(hipStreamSynchronize(E->main), "engine sync");
+    if (rc) return rc;
+    engine_collect(E, true);
+  }
+  J->run->stream = E->admin;
+  if (J->active) E->dirty = true;  // its stream changed: capture again
+  return DF_OK;
+}
+
+int df_engine_force(df_engine *E, int32_t slot, double out[4]) {
+  EngineJob *J = nullptr;
+  int rc = engine_job(E, slot, &J);
+  if (rc) return rc;
+  rc = engine_quiesce(E, J);
+  if (rc) return rc;
+  return df_force(J->run, out);
+}
+
+int df_engine_get_field(df_engine *E, int32_t slot, int32_t level, int32_t field, double *host) {
+  EngineJob *J = nullptr;
+  int rc = engine_job(E, slot, &J);
+  if (rc) return rc;
+  rc = engine_quiesce(E, J);
+  if (rc) return rc;
+  return df_get_field(J->run, level, field, host);
+}
+
+int df_engine_release(df_engine *E, int32_t slot) {
+  EngineJob *J = nullptr;
+  int rc = engine_job(E, slot, &J);
+  if (rc) return rc;
+  rc = engine_quiesce(E, J);
+  if (rc) return rc;
+  arena_give(E, J->off, J->len);
+  delete J->run;
+  *J = EngineJob();
+  return DF_OK;
+}
+
+int df_engine_stats(df_engine *E, int64_t out[2]) {
+  int rc = check_engine(E);
+  if (rc) return rc;
+  if (!out) return fail(DF_EINVAL, "null output");
+  out[0] = E->replays;
+  out[1] = E->captures;
+  return DF_OK;
+}
+
+int df_engine_destroy(df_engine *E) {
+  if (!E) return fail(DF_EINVAL, "null engine");
+  if (E->main) hipStreamSynchronize(E->main);
+  if (E->exec) hipGraphExecDestroy(E->exec);
+  for (auto &J : E->jobs)
+    if (J.used) delete J.run;
+  for (auto &p : E->pending) hipEventDestroy(p.ev);
+  for (hipEvent_t e : E->ev_pool) hipEventDestroy(e);
+  for (hipEvent_t e : E->join)
+    if (e) hipEventDestroy(e);
+  if (E->fork) hipEventDestroy(E->fork);
+  for (hipStream_t w : E->workers)
+    if (w) hipStreamDestroy(w);
+  if (E->admin) hipStreamDestroy(E->admin);
+  if (E->cap) hipStreamDestroy(E->cap);
+  delete E;
   return DF_OK;
 }
 

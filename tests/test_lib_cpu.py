@@ -68,3 +68,19 @@ def test_calls_out_of_order_fail_cleanly():
     with pytest.raises(dfm.DFError):
         dfm.set_perturber(h, 0.01, 0.0, 0.0, 0.5, 0.1)
     dfm.destroy(h)
+
+
+def test_engine_job_bytes_on_host():
+    import paper_1812_03191_amd as dfm
+
+    cfg = dict(nx=48, ny=48, nz=48, nlevels=1, dx0=0.1)
+    b64 = dfm.engine_job_bytes(cfg, dfm.DF_FP64)
+    b32 = dfm.engine_job_bytes(cfg, dfm.DF_FP32)
+    assert b64 % 256 == 0 and b32 % 256 == 0
+    assert 0.45 < b32 / b64 < 0.6
+
+
+def test_serving_work_count():
+    from paper_1812_03191_amd.serve import job_cell_updates
+
+    assert job_cell_updates(dict(nx=32, ny=32, nz=32, nlevels=3), 10) == 10 * 32 ** 3 * 7
