@@ -95,6 +95,89 @@ def cpu_baseline(cfg, budget_s=15.0):
                       f"({el:.1f} s, OpenMP threads={nthreads})"}
 
 
+def fp32_single(cfg, K, W):
+    """the same 128^3 workload with FP32 departure storage (single run)"""
+    import torch
+
+    import paper_1812_03191_amd as dfm
+
+    run = dfm.Run(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=1, dx0=cfg["dx0"], seed=cfg["seed"],
+                  noise_amp=cfg["noise_amp"], precision=dfm.DF_FP32)
+    run.set_perturber(cfg["GM"], cfg["eps"], cfg["L"], cfg["mach"], cfg["chi"])
+    run.step(W)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(run.stream)
+    run.step(K)
+    e1.record(run.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
+    return {"cell_updates_per_s": cells * K / (ms / 1e3), "ms_per_step": ms / K, "force": run.force()[:3].tolist()}
+
+
+def batched_sweep(warm=2):
+    """64 independent single-level runs (edges 48-96, Mach 0.1-3, L 0 or 1e-3),
+    200 coarse steps each, FP32 departures, advanced together by the engine
+    (one HIP graph replay = 2 coarse steps of every job); the same sweep in
+    FP64 gives each job's force error of the FP32 storage."""
+    import numpy as np
+    import torch
+
+    import paper_1812_03191_amd as dfm
+    from paper_1812_03191_amd.autotune import best_chunk
+    from tests import inputs
+
+    jobs, steps = inputs.config4()
+    res = {}
+    forces = {}
+    for prec, name in ((dfm.DF_FP32, "fp32"), (dfm.DF_FP64, "fp64")):
+        chunks = {}
+        for c in jobs:
+            k = (c["nx"], c["ny"], c["nz"])
+            if k not in chunks:
+                chunks[k] = best_chunk(c, prec)
+        budget = sum(dfm.engine_job_bytes(c, prec) for c in jobs) + (64 << 20)
+        eng = dfm.Engine(budget, nstreams=4)
+        slots = [eng.admit(c, steps + 2 * warm, precision=prec, tile_chunk=chunks[(c["nx"], c["ny"], c["nz"])])
+                 for c in jobs]
+        assert None not in slots
+        eng.step(warm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(eng.stream)
+        eng.step(steps // 2)
+        e1.record(eng.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        cells = sum(c["nx"] * c["ny"] * c["nz"] for c in jobs)
+        forces[name] = np.array([eng.force(s)[0] for s in slots])
+        res[name] = {"cell_updates_per_s": cells * steps / (ms / 1e3), "ms_per_coarse_step": ms / steps,
+                     "cells_per_coarse_step": cells, "jobs": len(jobs), "steps_each": steps,
+                     "engine": eng.stats(), "tile_chunks": {f"{k[0]}": v for k, v in chunks.items()}}
+        del eng
+    rel = np.abs(forces["fp32"] - forces["fp64"]) / np.abs(forces["fp64"])
+    res["fp32"]["force_rel_err_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    return res
+
+
+def serving(njobs, budget_gb=8.0):
+    """Poisson arrivals at 20 jobs/s of runs with edges 32-128 and 1-3 levels,
+    300 coarse steps each, FP32 departures, continuous batching under an HBM
+    budget; p50/p99 latency from arrival to completion."""
+    import paper_1812_03191_amd as dfm
+    from paper_1812_03191_amd.serve import serve
+    from tests import inputs
+
+    t, jobs, steps = inputs.config5()
+    t, jobs = t[:njobs], jobs[:njobs]
+    r = serve(t - t[0], jobs, steps, budget_bytes=int(budget_gb * (1 << 30)), precision=dfm.DF_FP32)
+    r.pop("forces")
+    r["budget_gb"] = budget_gb
+    r["arrival_rate_per_s"] = 20.0
+    return r
+
+
 def copy_probe(nbytes=1 << 30):
     """a plain device copy of known size, for scaling the byte counters"""
     import torch
@@ -116,6 +199,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serve-jobs", type=int, default=100,
+                    help="jobs of the served workload to run (400 is the whole stream; 0 skips)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -175,6 +261,16 @@ def main():
                     "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None} for k, v in kern.items()
                 if v[1]}
 
+    extra = {}
+    if not args.no_batched:
+        print("[bench] FP32 single run", file=sys.stderr, flush=True)
+        extra["fp32_single"] = fp32_single(cfg, K, W)
+        print("[bench] batched sweep (64 jobs, FP32 and FP64)", file=sys.stderr, flush=True)
+        extra["batched"] = batched_sweep()
+    if args.serve_jobs > 0:
+        print(f"[bench] serving {args.serve_jobs} jobs", file=sys.stderr, flush=True)
+        extra["serving"] = serving(args.serve_jobs)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -192,6 +288,7 @@ def main():
         "force": {"Fx": F[0], "Fy": F[1], "Fz": F[2], "t": F[3]},
         "kernels": kern,
     }
+    out.update(extra)
     print(json.dumps(out))
 
 
