@@ -313,6 +313,10 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     G.bc = (l == 0);
     G.has_fine = (l + 1 < R->nl);
     R->vol[l] = (size_t)G.sz * G.s[2];
+    if (R->vol[l] >= ((size_t)1 << 31)) {
+      delete R;
+      return fail(DF_EINVAL, "a level holds 2^31 entries or more per field");
+    }
     size_t face_max = (size_t)G.n[0] * G.n[1];
     if ((size_t)G.n[0] * G.n[2] > face_max) face_max = (size_t)G.n[0] * G.n[2];
     if ((size_t)G.n[1] * G.n[2] > face_max) face_max = (size_t)G.n[1] * G.n[2];

@@ -68,12 +68,32 @@ __device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k
   return i < b.hi[0] && j < b.hi[1];
 }
 
-__device__ __forceinline__ long lin(const Geo &G, int i, int j, int k) {
-  return G.off + i + (long)j * G.sy + (long)k * G.sz;
+// Element indices are 32-bit (a field holds fewer than 2^31 entries, checked
+// when a mesh is created): with a uniform 64-bit base in scalar registers the
+// loads and stores then take a 32-bit per-lane offset, with no 64-bit address
+// arithmetic per lane.
+using idx_t = int;
+
+__device__ __forceinline__ idx_t lin(const Geo &G, int i, int j, int k) {
+  return (idx_t)G.off + i + j * (idx_t)G.sy + k * (idx_t)G.sz;
 }
 
-__device__ __forceinline__ long dstride(const Geo &G, int d) {
-  return d == 0 ? 1L : (d == 1 ? G.sy : G.sz);
+__device__ __forceinline__ idx_t dstride(const Geo &G, int d) {
+  return d == 0 ? 1 : (d == 1 ? (idx_t)G.sy : (idx_t)G.sz);
+}
+
+// Load and store at a non-negative element index whose byte offset fits 32
+// bits (every field is smaller than 4 GiB): the address is a uniform base plus
+// an unsigned 32-bit lane offset, which the hardware adds itself.
+template <typename T>
+__device__ __forceinline__ T gld(const T *p, idx_t i) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(p) +
+                                      (unsigned)i * (unsigned)sizeof(T));
+}
+
+template <typename T>
+__device__ __forceinline__ void gst(T *p, idx_t i, T v) {
+  *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + (unsigned)i * (unsigned)sizeof(T)) = v;
 }
 
 // cell-centre coordinate: the perturber is the central vertex of the level
@@ -82,10 +102,13 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
   return (T)(((double)i - 0.5 * (double)G.n[d] + 0.5) * G.dx);
 }
 
-// van Leer's harmonic limited difference
+// van Leer's harmonic limited difference; evaluated without a branch (the
+// quotient of the discarded side is selected away)
 template <typename T>
 __device__ __forceinline__ T vleer(T a, T b) {
-  return (a * b > T(0)) ? T(2) * a * b / (a + b) : T(0);
+  const T p = a * b;
+  const T r = (T(2) * p) / (a + b);
+  return p > T(0) ? r : T(0);
 }
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -151,7 +174,7 @@ template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_init(Geo G, Phys P, InitArgs<T> A) {
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
-  long c = lin(G, i, j, k);
+  idx_t c = lin(G, i, j, k);
   double dr = 0.0;
   bool active = i >= 0 && j >= 0 && k >= 0 && i < G.n[0] && j < G.n[1] && k < G.n[2];
   if (active && A.amp != 0.0) {
@@ -200,7 +223,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
   const T h = (T)(A.fac * A.dtp[0]);
   const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
   const T *rho = A.q[0], *e = A.q[1];
-  const long c = lin(G, i, j, k);
+  const idx_t c = lin(G, i, j, k);
   T drc, dec;
   if (BC) {
     drc = cread(rho, G, i, j, k);
@@ -218,7 +241,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
               k >= A.flo[d][2] && k < A.fhi[d][2];
     if (!in) continue;
     const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
-    const long m = c - dstride(G, d);
+    const idx_t m = c - dstride(G, d);
     T drm, dem;
     if (BC) {
       drm = cread(rho, G, im, jm, km);
@@ -275,7 +298,7 @@ __global__ void __launch_bounds__(BX * BY) k_compress(Geo G, Phys P, CellArgs<T>
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
   const T dt = (T)(A.fac * A.dtp[0]);
-  const long c = lin(G, i, j, k);
+  const idx_t c = lin(G, i, j, k);
   const T divv = ((A.v[0][c + 1] - A.v[0][c]) + (A.v[1][c + G.sy] - A.v[1][c]) +
                   (A.v[2][c + G.sz] - A.v[2][c])) / (T)G.dx;
   const T a = T(0.5) * (T)P.gm1 * dt * divv;
@@ -311,7 +334,7 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
   if (!thread_cell(A.b, i, j, k)) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const T rho0 = (T)P.rho0, e0 = (T)P.e0;
-  const long c = lin(G, i, j, k);
+  const idx_t c = lin(G, i, j, k);
   const T dec = A.e[c];
   T en = dec;
   if (A.do_diff) {
@@ -326,7 +349,7 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
         Tm = dtemp(cread(A.rho, G, im, jm, km), cread(A.e, G, im, jm, km), rho0, e0);
         Tp = dtemp(cread(A.rho, G, ip, jp, kp), cread(A.e, G, ip, jp, kp), rho0, e0);
       } else {
-        const long s = dstride(G, d);
+        const idx_t s = dstride(G, d);
         Tm = dtemp(A.rho[c - s], A.e[c - s], rho0, e0);
         Tp = dtemp(A.rho[c + s], A.e[c + s], rho0, e0);
       }
@@ -370,7 +393,7 @@ struct PassArgs {
 };
 
 template <int DIR, bool BC>
-__device__ __forceinline__ bool cell_at(const Geo &G, int i, int j, int k, int o, long &c) {
+__device__ __forceinline__ bool cell_at(const Geo &G, int i, int j, int k, int o, idx_t &c) {
   int ii = i + (DIR == 0 ? o : 0), jj = j + (DIR == 1 ? o : 0), kk = k + (DIR == 2 ? o : 0);
   if (BC) {
     if (ii >= G.n[0]) return false;
@@ -400,7 +423,7 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs<T> A) 
   const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx);
   const T rho0 = (T)P.rho0;
   const T vb = (T)vback(P, DIR);
-  long cc[5];
+  idx_t cc[5];
   bool in[5];
 #pragma unroll
   for (int o = 0; o < 5; ++o) in[o] = cell_at<DIR, BC>(G, i, j, k, o - 2, cc[o]);
@@ -410,8 +433,8 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs<T> A) 
     dr[o] = in[o] ? A.qi[0][cc[o]] : T(0);
     irr[o] = T(1) / (rho0 * (rho0 + dr[o]));
   }
-  const long c = lin(G, i, j, k);
-  const long st = dstride(G, DIR);
+  const idx_t c = lin(G, i, j, k);
+  const idx_t st = dstride(G, DIR);
   const T daL = A.v[DIR][c], daR = A.v[DIR][c + st];
   const T aL = vb + daL, aR = vb + daR;
   const T nuL = aL * dt / dx, nuR = aR * dt / dx;
@@ -468,7 +491,7 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs<T> A) 
     if (FIRST && m >= 2) {
       // momentum P = rho v of a face velocity: its specific value is v itself
       const int d = (m - 2) >> 1;
-      const long off = (m & 1) ? dstride(G, d) : 0;
+      const idx_t off = (m & 1) ? dstride(G, d) : 0;
       const T *vd = A.v[d];
 #pragma unroll
       for (int o = 0; o < 5; ++o) ds[o] = in[o] ? vd[cc[o] + off] : T(0);
@@ -511,50 +534,41 @@ struct MarchArgs {
   int fn[3];
 };
 
-template <typename T, int DIR, bool BC>
-__global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
+// One column segment [c0, c1) of the quantity group GRP (0: rho, e, P-x, P+x;
+// 1: P-y, P+y, P-z, P+z) at in-plane position (i, t).
+template <typename T, int DIR, bool BC, int GRP>
+__device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
+                                             int i, int t, int c0, int c1) {
   constexpr int TD = (DIR == 1) ? 2 : 1;
   constexpr int T1 = (DIR == 0) ? 1 : 0;
   constexpr int T2 = (DIR == 2) ? 1 : 2;
-  const int lane = threadIdx.x, ty = threadIdx.y;
-  const int grp = ty & 1;
-  const int nbx = (A.hi[0] - A.lo[0] + 63) / 64;
-  const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
-  const unsigned h = blockIdx.x;
-  const int bx = (int)(h % (unsigned)nbx);
-  const unsigned r1 = h / (unsigned)nbx;
-  const int tb = (int)(r1 % (unsigned)ntb);
-  const int ch = (int)(r1 / (unsigned)ntb);
-  const int i = A.lo[0] + bx * 64 + lane;
-  const int t = A.lo[TD] + tb * 2 + (ty >> 1);
-  if (i >= A.hi[0] || t >= A.hi[TD]) return;
-  const int c0 = A.lo[DIR] + ch * A.chunk;
-  const int c1 = min(c0 + A.chunk, A.hi[DIR]);
-  if (c0 >= c1) return;
-
   const T dt = (T)(A.fac * A.dtp[0]);
   const T dx = (T)G.dx;
   const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx), cour = dt / dx;
   const T rho0 = (T)P.rho0;
   const T vb = (T)vback(P, DIR);
   const T M0 = rho0 * vb * mfac;
-  const long st = dstride(G, DIR);
+  const idx_t st = dstride(G, DIR);
   int id3[3];
   id3[0] = i;
   id3[TD] = t;
   id3[DIR] = 0;
-  const long base = lin(G, id3[0], id3[1], id3[2]);
-  auto cidx = [&](int c) -> long {
+  const idx_t base = lin(G, id3[0], id3[1], id3[2]);
+  auto cidx = [&](int c) -> idx_t {
     if (BC) c = clampi(c, 0, G.n[DIR] - 1);
-    return base + (long)c * st;
+    return base + c * st;
   };
-  const int mq[4] = {grp ? 4 : 1, grp ? 5 : 2, grp ? 6 : 3, grp ? 7 : 1};
-  const int nq = grp ? 4 : 3;
+  constexpr int mq[4] = {GRP ? 4 : 1, GRP ? 5 : 2, GRP ? 6 : 3, GRP ? 7 : 1};
+  constexpr int nq = GRP ? 4 : 3;
   T q0[4], sb[4];
+  const T *qin[4];
+  T *qout[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     q0[u] = (T)qback(P, mq[u]);
     sb[u] = (T)sback(P, mq[u]);
+    qin[u] = A.qi[mq[u]];
+    qout[u] = A.qo[mq[u]];
   }
 
   const int tv1 = id3[T1], tv2 = id3[T2];
@@ -590,25 +604,32 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
 
   // window: departures of the specific values at c, c+1 (s0, s1; index 0 is
   // the density departure), limited difference at c (d0), transfer through
-  // face c (F0)
-  T s0[5], s1[5], d0[5], F0[5];
+  // face c (F0); raw departures of cells c, c+1, c+2 (w0, w1, w2) and the
+  // velocity departure on face c+1 (va), all loaded at least one iteration
+  // ahead of their use
+  T s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
+  T va;
   {
     T sm2[5], sm1[5];
-    const long im2 = cidx(c0 - 2), im1 = cidx(c0 - 1), i0 = cidx(c0), ip1 = cidx(c0 + 1);
-    const T r_m2 = A.qi[0][im2], r_m1 = A.qi[0][im1], r_0 = A.qi[0][i0], r_p1 = A.qi[0][ip1];
+    const idx_t im2 = cidx(c0 - 2), im1 = cidx(c0 - 1), i0 = cidx(c0), ip1 = cidx(c0 + 1);
+    const T r_m2 = gld(A.qi[0], im2), r_m1 = gld(A.qi[0], im1);
+    w0[0] = gld(A.qi[0], i0);
+    w1[0] = gld(A.qi[0], ip1);
     const T ir_m2 = T(1) / (rho0 * (rho0 + r_m2)), ir_m1 = T(1) / (rho0 * (rho0 + r_m1));
-    const T ir_0 = T(1) / (rho0 * (rho0 + r_0)), ir_p1 = T(1) / (rho0 * (rho0 + r_p1));
-    sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = r_0; s1[0] = r_p1;
+    const T ir_0 = T(1) / (rho0 * (rho0 + w0[0])), ir_p1 = T(1) / (rho0 * (rho0 + w1[0]));
+    sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = w0[0]; s1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (u >= nq) break;
-      const T *q = A.qi[mq[u]];
-      sm2[u + 1] = (rho0 * q[im2] - q0[u] * r_m2) * ir_m2;
-      sm1[u + 1] = (rho0 * q[im1] - q0[u] * r_m1) * ir_m1;
-      s0[u + 1] = (rho0 * q[i0] - q0[u] * r_0) * ir_0;
-      s1[u + 1] = (rho0 * q[ip1] - q0[u] * r_p1) * ir_p1;
+      const T *q = qin[u];
+      w0[u + 1] = gld(q, i0);
+      w1[u + 1] = gld(q, ip1);
+      sm2[u + 1] = (rho0 * gld(q, im2) - q0[u] * r_m2) * ir_m2;
+      sm1[u + 1] = (rho0 * gld(q, im1) - q0[u] * r_m1) * ir_m1;
+      s0[u + 1] = (rho0 * w0[u + 1] - q0[u] * w0[0]) * ir_0;
+      s1[u + 1] = (rho0 * w1[u + 1] - q0[u] * w1[0]) * ir_p1;
     }
-    const T da = A.v[base + (long)c0 * st];
+    const T da = gld(A.v, base + c0 * st);
     const T a = vb + da, nu = a * cour;
     T dM = T(0), M = T(0);
 #pragma unroll
@@ -620,40 +641,34 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
         M = M0 + dM;
-        F0[0] = grp ? dM : fix(c0, 0, dM);  // the density belongs to the first wave
+        F0[0] = GRP ? dM : fix(c0, 0, dM);  // the density belongs to the first wave
       } else {
         F0[u] = fix(c0, mq[u - 1], sb[u - 1] * dM + fv * M);
       }
     }
-  }
-  // raw departures of cell c+2, loaded one iteration ahead of their use
-  T nx[5];
-  {
-    const long ip2 = cidx(c0 + 2);
-    nx[0] = A.qi[0][ip2];
+    const idx_t ip2 = cidx(c0 + 2);
+    w2[0] = gld(A.qi[0], ip2);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) nx[u + 1] = A.qi[mq[u]][ip2];
+      if (u < nq) w2[u + 1] = gld(qin[u], ip2);
+    va = gld(A.v, base + (c0 + 1) * st);
   }
   for (int c = c0; c < c1; ++c) {
-    const long ic = cidx(c), ip3 = cidx(c + 3);
-    T own[5], nn[5];
-    const T da = A.v[base + (long)(c + 1) * st];
-    own[0] = A.qi[0][ic];
-    nn[0] = A.qi[0][ip3];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (u < nq) {
-        own[u + 1] = A.qi[mq[u]][ic];
-        nn[u + 1] = A.qi[mq[u]][ip3];
-      }
-    }
-    const T ir2 = T(1) / (rho0 * (rho0 + nx[0]));
-    T s2[5];
-    s2[0] = nx[0];
+    const idx_t ic = cidx(c), ip3 = cidx(c + 3);
+    // next iteration's loads: cell c+3 and face c+2
+    T nn[5];
+    nn[0] = gld(A.qi[0], ip3);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) s2[u + 1] = (rho0 * nx[u + 1] - q0[u] * nx[0]) * ir2;
+      if (u < nq) nn[u + 1] = gld(qin[u], ip3);
+    const T vn = gld(A.v, base + min(c + 2, c1) * st);
+    const T ir2 = T(1) / (rho0 * (rho0 + w2[0]));
+    T s2[5];
+    s2[0] = w2[0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < nq) s2[u + 1] = (rho0 * w2[u + 1] - q0[u] * w2[0]) * ir2;
+    const T da = va;
     const T a = vb + da, nu = a * cour;
     T dM = T(0), M = T(0);
 #pragma unroll
@@ -665,20 +680,54 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
         M = M0 + dM;
-        F1 = grp ? dM : fix(c + 1, 0, dM);
+        F1 = GRP ? dM : fix(c + 1, 0, dM);
       } else {
         F1 = fix(c + 1, mq[u - 1], sb[u - 1] * dM + fv * M);
       }
-      const int m = (u == 0) ? 0 : mq[u - 1];
-      if (u > 0 || grp == 0) A.qo[m][ic] = own[u] - (F1 - F0[u]) * ivol;
+      T *qo = (u == 0) ? A.qo[0] : qout[u - 1];
+      if (u > 0 || GRP == 0) gst(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
       F0[u] = F1;
       d0[u] = d1;
       s0[u] = s1[u];
       s1[u] = s2[u];
     }
 #pragma unroll
-    for (int u = 0; u < 5; ++u) nx[u] = nn[u];
+    for (int u = 0; u < 5; ++u) {
+      w0[u] = w1[u];
+      w1[u] = w2[u];
+      w2[u] = nn[u];
+    }
+    va = vn;
   }
+}
+
+template <typename T, int DIR, bool BC>
+__global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
+  constexpr int TD = (DIR == 1) ? 2 : 1;
+  constexpr int T1 = (DIR == 0) ? 1 : 0;
+  constexpr int T2 = (DIR == 2) ? 1 : 2;
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  // threadIdx.y is the same across a wave (blockDim.x is one wave): reading it
+  // from the first lane makes the quantity group, and so every field pointer,
+  // a scalar
+  const int grp = __builtin_amdgcn_readfirstlane(ty) & 1;
+  const int nbx = (A.hi[0] - A.lo[0] + 63) / 64;
+  const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
+  const unsigned h = blockIdx.x;
+  const int bx = (int)(h % (unsigned)nbx);
+  const unsigned r1 = h / (unsigned)nbx;
+  const int tb = (int)(r1 % (unsigned)ntb);
+  const int ch = (int)(r1 / (unsigned)ntb);
+  const int i = A.lo[0] + bx * 64 + lane;
+  const int t = A.lo[TD] + tb * 2 + (ty >> 1);
+  if (i >= A.hi[0] || t >= A.hi[TD]) return;
+  const int c0 = A.lo[DIR] + ch * A.chunk;
+  const int c1 = min(c0 + A.chunk, A.hi[DIR]);
+  if (c0 >= c1) return;
+  if (grp)
+    march_column<T, DIR, BC, 1>(G, P, A, i, t, c0, c1);
+  else
+    march_column<T, DIR, BC, 0>(G, P, A, i, t, c0, c1);
 }
 
 // ------------------------------------------------------------ CommUp
@@ -760,16 +809,16 @@ template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_commmean(Geo Gf, Geo Gc, MeanArgs<T> A) {
   int I, J, K;
   if (!thread_cell(A.b, I, J, K)) return;
-  const long f = lin(Gf, 2 * I, 2 * J, 2 * K);
+  const idx_t f = lin(Gf, 2 * I, 2 * J, 2 * K);
   const T *q = A.Q;
   T val;
   if (A.stag < 0) {
-    const long sx = 1, sy = Gf.sy, sz = Gf.sz;
+    const idx_t sx = 1, sy = (idx_t)Gf.sy, sz = (idx_t)Gf.sz;
     val = (((q[f] + q[f + sx]) + (q[f + sy] + q[f + sx + sy])) +
            ((q[f + sz] + q[f + sx + sz]) + (q[f + sy + sz] + q[f + sx + sy + sz]))) * T(0.125);
   } else {
-    const long e1 = (A.stag == 0) ? Gf.sy : 1;
-    const long e2 = (A.stag == 2) ? Gf.sy : Gf.sz;
+    const idx_t e1 = (A.stag == 0) ? (idx_t)Gf.sy : 1;
+    const idx_t e2 = (A.stag == 2) ? (idx_t)Gf.sy : (idx_t)Gf.sz;
     val = ((q[f] + q[f + e1]) + (q[f + e2] + q[f + e1 + e2])) * T(0.25);
   }
   A.out[lin(Gc, Gc.n[0] / 4 + I, Gc.n[1] / 4 + J, Gc.n[2] / 4 + K)] = val;
@@ -859,7 +908,7 @@ __global__ void __launch_bounds__(BX * BY) k_totals(Geo G, Phys P, RedArgs<T> A)
   const bool ok = thread_cell(A.b, i, j, k);
   double m = 0.0, ei = 0.0, ek = 0.0;
   if (ok && !is_covered(A, i, j, k)) {
-    const long c = lin(G, i, j, k);
+    const idx_t c = lin(G, i, j, k);
     const double vol = G.dx * G.dx * G.dx;
     const double r = P.rho0 + (double)A.rho[c];
     double v2 = 0.0;
@@ -922,7 +971,7 @@ __global__ void __launch_bounds__(BX * BY) k_signal(Geo G, Phys P, RedArgs<T> A)
   double sig = 0.0;
   int bad = 0;
   if (ok) {
-    const long c = lin(G, i, j, k);
+    const idx_t c = lin(G, i, j, k);
     const double r = P.rho0 + (double)A.rho[c], en = P.e0 + (double)A.e[c];
     if (!(r > 0.0) || !(en > 0.0) || !isfinite(r) || !isfinite(en)) bad = 1;
     const double cs = sqrt(P.gamma * P.gm1 * en / r);

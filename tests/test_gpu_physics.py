@@ -1,0 +1,89 @@
+"""Linear-theory pins of the low-Mach forces (Sects. 2.3, 4.1.1, 4.2), run on the
+HIP path (which matches the FP64 oracle to 1e-11, tests/test_gpu_parity.py).
+
+Setup as in the paper: perturber on the central vertex, epsilon = 0, heat split
+over the 8 cells around it, finest cell lambda/5 (r'_min = 0.1), GM / (chi c_s)
+= 0.01 (linear regime), gamma = 5/3.  The forces are differences of two runs
+(eq. 5): the heating force F(M,L,chi) - F(M,0,chi), the cold thermal force
+F(M,0,chi) - F(M,0,0).  Expected values are the closed forms of eq. 8 (times
+the perturber mass) and eq. 51, scaled by the finite-range fraction
+h(r'_max) - h(r'_min) of eq. 23."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import theory as T
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 5.0 / 3.0
+CHI = 0.1
+GM = 1e-3
+
+
+def _say(msg):
+    sys.stdout.write(msg + "\n")
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dfm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_03191_amd as m
+
+    return m
+
+
+def _force_at(dfm, mach, nlevels, n, L, chi, t_end):
+    lam = CHI / (GAMMA * mach)
+    dxf = lam / 5.0
+    r = dfm.Run(n, nlevels=nlevels, dx0=dxf * 2 ** (nlevels - 1), noise_amp=0.0, precision=dfm.DF_FP32)
+    r.set_perturber(GM, 0.0, L, mach, chi)
+    while True:
+        r.step(50)
+        f = r.force()
+        if f[3] >= t_end:
+            break
+    log = r.force_log()
+    k = int(np.searchsorted(log[:, 3], t_end))
+    return log[min(k, len(log) - 1)]
+
+
+def _fraction(mach, nlevels, n):
+    lam = CHI / (GAMMA * mach)
+    dxf = lam / 5.0
+    rmax = (n // 2) * dxf * 2 ** (nlevels - 1) / (2 * lam)
+    return float(T.h_fraction(rmax) - T.h_fraction(dxf / (2 * lam)))
+
+
+def test_low_mach_heating_force(dfm):
+    # Mach 0.1, L = 2e-4 (Sect. 4.1), 5 levels of 64^3: r' from 0.1 to 51.2;
+    # after 50 tau the heating force is within 5 % of M a(eq. 8) (h(r'max) - h(r'min))
+    mach, nl, n, L = 0.1, 5, 64, 2e-4
+    tau = T.response_time(CHI, GAMMA, mach)
+    hot = _force_at(dfm, mach, nl, n, L, CHI, 50 * tau)
+    cold = _force_at(dfm, mach, nl, n, 0.0, CHI, 50 * tau)
+    want = GM * T.heating_accel_lowmach(GAMMA, 1.0, L, CHI) * _fraction(mach, nl, n)
+    got = hot[0] - cold[0]
+    _say(f"[physics] heating force {got:.5e} vs {want:.5e} (ratio {got / want:.4f})")
+    assert got > 0.0
+    assert abs(got / want - 1.0) < 0.05
+
+
+def test_low_mach_cold_thermal_force(dfm):
+    # Mach 0.2, 6 levels of 64^3 (r'_max 102): the acoustic sphere reaches the
+    # box edge only after ~68 tau, so at 40 tau the cold thermal force is free
+    # of reflections (Sect. 4.2.2); it tends to -(gamma-1)/2 F0 (eq. 51)
+    mach, nl, n = 0.2, 6, 64
+    tau = T.response_time(CHI, GAMMA, mach)
+    diff = _force_at(dfm, mach, nl, n, 0.0, CHI, 40 * tau)
+    adi = _force_at(dfm, mach, nl, n, 0.0, 0.0, 40 * tau)
+    want = T.cold_thermal_force(GAMMA, 1.0, GM) * _fraction(mach, nl, n)
+    got = diff[0] - adi[0]
+    _say(f"[physics] cold thermal force {got:.5e} vs {want:.5e} (ratio {got / want:.4f})")
+    assert got < 0.0
+    assert abs(got / want - 1.0) < 0.08
