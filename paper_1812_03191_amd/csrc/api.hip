@@ -695,6 +695,9 @@ struct df_engine {
   std::vector<EngineJob> jobs;
   std::vector<std::pair<size_t, size_t>> freel;  // (offset, length), sorted, coalesced
   hipGraphExec_t exec = nullptr;
+  // replaced graphs whose launches may still run on the device: each is
+  // destroyed once the event recorded after its last launch has completed
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
   bool dirty = true;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -749,11 +752,32 @@ hipEvent_t engine_event(df_engine *E) {
   return e;
 }
 
+// destroy the retired graphs that the device has finished with (all of them
+// when wait is set)
+void engine_reap(df_engine *E, bool wait) {
+  size_t k = 0;
+  for (auto &r : E->retired) {
+    hipError_t q = wait ? hipEventSynchronize(r.second) : hipEventQuery(r.second);
+    if (q != hipSuccess) {
+      E->retired[k++] = r;
+      continue;
+    }
+    hipGraphExecDestroy(r.first);
+    E->ev_pool.push_back(r.second);
+  }
+  E->retired.resize(k);
+}
+
 int engine_capture(df_engine *E) {
   if (E->exec) {
-    hipGraphExecDestroy(E->exec);
+    // launches of the old graph may be in flight on the caller's stream
+    hipEvent_t ev = engine_event(E);
+    int rc = hip_check(hipEventRecord(ev, E->main), "event record");
+    if (rc) return rc;
+    E->retired.push_back({E->exec, ev});
     E->exec = nullptr;
   }
+  engine_reap(E, false);
   std::vector<int> act;
   for (int s = 0; s < (int)E->jobs.size(); ++s)
     if (E->jobs[s].used && E->jobs[s].active) act.push_back(s);
@@ -799,6 +823,7 @@ void engine_collect(df_engine *E, bool wait) {
     E->ev_pool.push_back(p.ev);
   }
   E->pending.erase(E->pending.begin(), E->pending.begin() + (long)k);
+  engine_reap(E, wait);
 }
 
 }  // namespace
@@ -1012,6 +1037,7 @@ int df_engine_stats(df_engine *E, int64_t out[2]) {
 int df_engine_destroy(df_engine *E) {
   if (!E) return fail(DF_EINVAL, "null engine");
   if (E->main) hipStreamSynchronize(E->main);
+  engine_reap(E, true);
   if (E->exec) hipGraphExecDestroy(E->exec);
   for (auto &J : E->jobs)
     if (J.used) delete J.run;

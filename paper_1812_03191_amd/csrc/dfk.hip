@@ -513,6 +513,135 @@ __global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs<T> A) 
   }
 }
 
+// Neighbour exchange inside a wave through the data-parallel-primitive lane
+// shifts: from_left gives every lane the value of the lane below it, from_right
+// that of the lane above it (the end lanes receive 0).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return dpp_t<DPP_WAVE_SHR1>(v); }
+
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return dpp_t<DPP_WAVE_SHL1>(v); }
+
+// Wave-tiled form of the x pass.  A wave holds 64 consecutive cells of one
+// row, of which lanes 2..61 own their cell (tiles overlap by 4 cells): every
+// lane forms the specific value of its cell and the limited difference there
+// once, takes its neighbours' through lane shifts, computes the transfer
+// through its left face, and the owning lanes take the right face's transfer
+// from the lane above.  Arithmetic and its order are those of k_pass.
+constexpr int XT = 60;
+
+__host__ __device__ inline Box xtile_box(const Box &b) {
+  Box v = b;
+  const int ex = b.hi[0] - b.lo[0];
+  v.lo[0] = 0;
+  v.hi[0] = ex > 0 ? ((ex + XT - 1) / XT) * BX : 0;
+  return v;
+}
+
+template <typename T, bool BC>
+__global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A) {
+  int iv, j, k;
+  if (!thread_cell(xtile_box(A.b), iv, j, k)) return;
+  const int lane = threadIdx.x;
+  const int x = A.b.lo[0] - 2 + (iv / BX) * XT + lane;
+  // lanes past the last cell's neighbours read that neighbour (never used)
+  const int xl = min(x, A.b.hi[0] + 1);
+  const bool owner = lane >= 2 && lane < 2 + XT && x < A.b.hi[0];
+  const T dt = (T)(A.fac * A.dtp[0]);
+  const T dx = (T)G.dx;
+  const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx);
+  const T rho0 = (T)P.rho0;
+  const T vb = (T)vback(P, 0);
+  idx_t c;
+  const bool in = cell_at<0, BC>(G, xl, j, k, 0, c);
+  const T dr = in ? gld(A.qi[0], c) : T(0);
+  const T irr = T(1) / (rho0 * (rho0 + dr));
+  // velocity departure on the left face (faces lo..hi are the ones used)
+  const T da = gld(A.v[0], lin(G, clampi(x, A.b.lo[0], A.b.hi[0]), j, k));
+  const T a = vb + da, nu = a * dt / dx;
+  const T M0 = rho0 * vb * mfac;
+  auto left_face = [&](T sv) -> T {
+    const T sm = from_left(sv), sp = from_right(sv);
+    const T d = vleer(sp - sv, sv - sm);
+    const T dm = from_left(d);
+    return (a > T(0)) ? sm + T(0.5) * dm * (T(1) - nu) : sv - T(0.5) * d * (T(1) + nu);
+  };
+  const T dM = (rho0 * da + left_face(dr) * a) * mfac;
+  const T M = M0 + dM;
+
+  // flux matching on the frontier of the finer level (its 4 faces over its 2
+  // sub-cycles replace this level's transfer) and this level's own frontier
+  bool fine_face = false;
+  int side = 0;
+  long fbase = 0, fnt = 0;
+  if (A.facc) {
+    const int a1 = j - G.n[1] / 4, a2 = k - G.n[2] / 4;
+    const int lo = G.n[0] / 4, hi = (3 * G.n[0]) / 4;
+    if (a1 >= 0 && a2 >= 0 && a1 < G.n[1] / 2 && a2 < G.n[2] / 2 && (x == lo || x == hi)) {
+      fine_face = true;
+      side = (x == hi);
+      fnt = (long)A.fn[1] * A.fn[2];
+      fbase = (long)(2 * a2) * A.fn[1] + 2 * a1;
+    }
+  }
+  long acc_i = -1, acc_nt = 0;
+  int acc_side = -1;
+  if (A.acc && owner && j >= 0 && k >= 0 && j < G.n[1] && k < G.n[2] &&
+      (x == 0 || x == G.n[0] - 1)) {
+    acc_nt = (long)G.n[1] * G.n[2];
+    acc_i = (long)k * G.n[1] + j;
+    acc_side = (x == 0) ? 0 : 1;
+  }
+  const idx_t co = lin(G, x, j, k);
+  auto finish = [&](int m, T own, T FL) {
+    if (fine_face) {
+      const T *f = A.facc + ((long)side * NQ + m) * fnt + fbase;
+      FL = (f[0] + f[1]) + (f[A.fn[1]] + f[A.fn[1] + 1]);
+    }
+    const T FR = from_right(FL);
+    if (acc_side == 0) A.acc[((long)0 * NQ + m) * acc_nt + acc_i] += FL;
+    if (acc_side == 1) A.acc[((long)1 * NQ + m) * acc_nt + acc_i] += FR;
+    if (owner) gst(A.qo[m], co, own - (FR - FL) * ivol);
+  };
+  finish(0, dr, dM);
+
+#pragma unroll 1
+  for (int m = 1; m < NQ; ++m) {
+    T sv, own;
+    if (m >= 2) {
+      // momentum P = rho v of a face velocity: its specific value is v itself
+      const int d = (m - 2) >> 1;
+      const idx_t off = (m & 1) ? dstride(G, d) : 0;
+      sv = in ? gld(A.v[d], c + off) : T(0);
+      own = rho0 * sv + dr * ((T)vback(P, d) + sv);
+    } else {
+      const T dq = in ? gld(A.qi[m], c) : T(0);
+      sv = (rho0 * dq - (T)qback(P, m) * dr) * irr;
+      own = dq;
+    }
+    finish(m, own, (T)sback(P, m) * dM + left_face(sv) * M);
+  }
+}
+
 // Streaming form of the y and z passes.  A thread owns one column segment
 // [c0, c1) along DIR (lanes along x, so every load is coalesced) and walks it
 // once: each cell is loaded once (one iteration ahead of its use), each limited
@@ -1222,9 +1351,9 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   A.facc = (G.has_fine && fine_acc) ? reinterpret_cast<const T *>(fine_acc) : nullptr;
   for (int d = 0; d < 3; ++d) A.fn[d] = Gf ? Gf->n[d] : 0;
   if (dir == 0) {
-    const dim3 gr = grid_of(A.b), bl(BX, BY);
-    if (G.bc) DFK_LAUNCH((k_pass<T, 0, true, true>), gr, bl, st, G, P, A);
-    else DFK_LAUNCH((k_pass<T, 0, false, true>), gr, bl, st, G, P, A);
+    const dim3 gr = grid_of(xtile_box(A.b)), bl(BX, BY);
+    if (G.bc) DFK_LAUNCH((k_xpass<T, true>), gr, bl, st, G, P, A);
+    else DFK_LAUNCH((k_xpass<T, false>), gr, bl, st, G, P, A);
     return;
   }
   MarchArgs<T> M;
