@@ -40,8 +40,7 @@ ALG_BYTES = {
     "pass_y": 8 * (9 + 8),        # read 8 transported + vy; write 8
     "pass_z": 8 * (9 + 8),        # read 8 transported + vz; write 8
     "rebuild_kick": 8 * (8 + 3),  # read 8 transported; write vx, vy, vz
-    "dt": 8 * 5,                  # read rho, e, vx, vy, vz
-    "force": 8 * 1,               # read rho
+    "force": 8 * 5,               # end-of-step pass: read rho, e, vx, vy, vz
 }
 
 

@@ -151,7 +151,11 @@ int df_debug_stage(df_run *run, int32_t stage, double dt);
  * stream around each of the next n kernel launches of df_step (0 disables and
  * frees them).  df_timing_read(run, ms, count, nkinds) synchronises, adds the
  * elapsed times by kernel kind into ms[kind] and the launch numbers into
- * count[kind] (kinds DF_K_*), and restarts the recording. */
+ * count[kind] (kinds DF_K_*), and restarts the recording.  DF_K_FORCE is the
+ * pass after each step that forms both the force partials and the next step's
+ * signal speeds, with the one-block kernel that logs the force and sets the
+ * next time step; DF_K_DT is the time step before the first step of a df_step
+ * call (with a signal pass if the state was changed by other calls). */
 enum {
   DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
   DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_NKINDS

@@ -65,6 +65,7 @@ struct df_run {
   int chunk = 16;      // column segment of the streaming passes
   bool bound = false;
   bool ready = false;
+  bool sig_valid = false;  // the signal-speed partials are those of the current state
   double eps = 0.0;
   // optional per-kernel-kind timing: event pairs around launches
   bool timing = false;
@@ -102,7 +103,7 @@ void carve(df_run *R, char *base) {
     B.acc = R->acc_n[l] ? (void *)c.take<char>(R->acc_n[l] * e) : nullptr;
     const Geo &G = R->geo[l];
     B.hw = c.take<double>((size_t)G.n[0] * G.n[1] * G.n[2]);
-    B.part = c.take<double>(3 * R->npart[l]);
+    B.part = c.take<double>(4 * R->npart[l]);
   }
   R->need = c.off;
 }
@@ -244,11 +245,31 @@ int check_run(const df_run *R, bool need_ready) {
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 // n coarse steps: device time step, recursive cycle, force into the log
+// signal-speed and force partials of the current state (post_partials)
+void post_reduce(df_run *R) {
+  for (int l = 0; l < R->nl; ++l) dfk::post_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->scal);
+  R->sig_valid = true;
+}
+
+// n coarse steps, each: time step from the signal speeds of the state,
+// cycle, force of the new state logged.  One pass after each step gives both
+// the force and the next step's signal speeds, and one block kernel between
+// two steps logs the force and sets the next time step.
 void enqueue_steps(df_run *R, int n) {
+  if (n <= 0) return;
+  if (!R->sig_valid) {
+    TScope t(R, K_DT);
+    post_reduce(R);
+  }
+  {
+    TScope t(R, K_DT);
+    dfk::step_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, R->flog, 0, 1);
+  }
   for (int s = 0; s < n; ++s) {
-    compute_dt(R, 1);
     cycle(R, 0);
-    force_reduce(R, 2);
+    TScope t(R, K_FORCE);
+    post_reduce(R);
+    dfk::step_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, R->flog, 1, s + 1 < n);
   }
 }
 
@@ -343,6 +364,7 @@ int df_bind(df_run *R, void *dev_ptr, size_t bytes, void *stream) {
   R->bytes = bytes;
   R->stream = (hipStream_t)stream;
   carve(R, R->base);
+  R->sig_valid = false;
   int rc = hip_check(hipMemsetAsync(R->base, 0, R->need, R->stream), "df_bind clear");
   if (rc) return rc;
   R->bound = true;
@@ -401,6 +423,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
   rc = hip_check(hipMemcpyAsync(R->scal, &zero, sizeof(Scal), hipMemcpyHostToDevice, st), "scalars");
   if (rc) return rc;
   sync_levels(R);
+  post_reduce(R);
   rc = launch_check("df_set_perturber");
   if (rc) return rc;
   rc = hip_check(hipStreamSynchronize(st), "df_set_perturber");
@@ -490,6 +513,7 @@ static int field_io(df_run *R, int l, int f, double *hout, const double *hin) {
         }
       }
   if (hin) {
+    R->sig_valid = false;
     rc = hip_check(hipMemcpyAsync(dev, raw.data(), raw.size(), hipMemcpyHostToDevice, R->stream), "field copy");
     if (rc) return rc;
     rc = hip_check(hipStreamSynchronize(R->stream), "field copy");
@@ -511,6 +535,7 @@ int df_sync_levels(df_run *R) {
   int rc = check_run(R, true);
   if (rc) return rc;
   sync_levels(R);
+  R->sig_valid = false;
   rc = launch_check("df_sync_levels");
   if (rc) return rc;
   return hip_check(hipStreamSynchronize(R->stream), "df_sync_levels");
@@ -540,6 +565,7 @@ int df_debug_stage(df_run *R, int32_t stage, double dt) {
   rc = hip_check(hipMemcpyAsync(&R->scal->dbg_dt, &dt, sizeof(double), hipMemcpyHostToDevice, st), "dt upload");
   if (rc) return rc;
   const double *dtp = &R->scal->dbg_dt;
+  R->sig_valid = false;
   const Geo &G = R->geo[0];
   LevBufs &B = R->buf[0];
   const Phys &P = R->phys;

@@ -63,7 +63,7 @@ struct LevBufs {
   double *hw;         // heat weights on a box of hw_n[0] x hw_n[1] x hw_n[2] cells
                       // centred on the perturber vertex (x fastest)
   int hw_n[3];        // box extent (0: no heat table)
-  double *part;       // reduction partials
+  double *part;       // reduction partials: 3 per block, then 1 signal speed per block
 };
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------
@@ -90,13 +90,22 @@ void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc,
             LevBufs &Bf, int curf);
 void commmean(hipStream_t st, const Geo &Gf, const Phys &P, LevBufs &Bf, int curf, const Geo &Gc,
               LevBufs &Bc, int curc);
-// per-block maxima of the signal speed of one level into B.part; health flag
+// per-block maxima of the signal speed of one level into the signal region of
+// B.part; health flag
 void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
 // dt of every level from the per-block maxima; t += dt0 if advance
 void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S,
               int advance);
 // force (3 FP64 sums) of one level into B.part, then the fixed-order final sum
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
+// force partials (as force_partials) and the signal-speed partials of the
+// next time step (as signal_speed) of the current state, in one pass
+void post_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
+// one block: with do_force the force of the partials of post_partials over
+// all levels, appended to the log; then with do_dt the time step from their
+// signal speeds, advancing the time
+void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P, Scal *S, double *flog,
+                int do_force, int do_dt);
 // slot 0: S->force; slot 1: S->totals; slot 2: S->force and the force log
 void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S,
                  int slot, double *flog);

@@ -970,7 +970,8 @@ template <typename T>
 struct RedArgs {
   Box b;
   const T *rho, *e, *v[3];
-  double *part;              // per-block partials
+  double *part;              // per-block partials (3 per block)
+  double *spart;             // per-block maximum signal speeds
   Scal *S;
   int cov_lo[3], cov_hi[3];  // covered cells (empty if no finer level)
 };
@@ -1063,15 +1064,36 @@ struct FinalArgs {
   double *flog;
 };
 
-__global__ void __launch_bounds__(256) k_final3(FinalArgs A) {
+// sum over b = t, t+256, ... < n of p[stride*b + q], in that order, with the
+// loads issued four at a time
+__device__ __forceinline__ double strided_sum(const double *p, int stride, int q, int n, double s) {
+  int b = threadIdx.x;
+  for (; b + 768 < n; b += 1024) {
+    const double x0 = p[(size_t)stride * b + q], x1 = p[(size_t)stride * (b + 256) + q];
+    const double x2 = p[(size_t)stride * (b + 512) + q], x3 = p[(size_t)stride * (b + 768) + q];
+    s += x0;
+    s += x1;
+    s += x2;
+    s += x3;
+  }
+  for (; b < n; b += 256) s += p[(size_t)stride * b + q];
+  return s;
+}
+
+__device__ __forceinline__ double strided_max(const double *p, int n, double m) {
+  int b = threadIdx.x;
+  for (; b + 768 < n; b += 1024)
+    m = fmax(fmax(m, fmax(p[b], p[b + 256])), fmax(p[b + 512], p[b + 768]));
+  for (; b < n; b += 256) m = fmax(m, p[b]);
+  return m;
+}
+
+__device__ void final3_body(const FinalArgs &A) {
   __shared__ double sh[3][4];
   double s[3] = {0.0, 0.0, 0.0};
   for (int l = 0; l < A.nl; ++l)
-    for (int b = threadIdx.x; b < A.npart[l]; b += 256) {
-      s[0] += A.part[l][3 * b + 0];
-      s[1] += A.part[l][3 * b + 1];
-      s[2] += A.part[l][3 * b + 2];
-    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s[q] = strided_sum(A.part[l], 3, q, A.npart[l], s[q]);
 #pragma unroll
   for (int q = 0; q < 3; ++q) s[q] = wave_sum(s[q]);
   const int w = threadIdx.x / 64;
@@ -1088,46 +1110,86 @@ __global__ void __launch_bounds__(256) k_final3(FinalArgs A) {
       A.S->nlog = n + 1;
     }
   }
+  __syncthreads();
 }
 
-// Largest signal speed c_s + |v| over the active cells and their faces (per
-// block, reduced by k_dt_final), and the health check (density and energy
-// positive and finite).
+__global__ void __launch_bounds__(256) k_final3(FinalArgs A) { final3_body(A); }
+
+// Signal speed c_s + |v| of an active cell, the largest over its six faces,
+// and whether its density and energy are positive and finite.
 template <typename T>
-__global__ void __launch_bounds__(BX * BY) k_signal(Geo G, Phys P, RedArgs<T> A) {
-  int i, j, k;
-  const bool ok = thread_cell(A.b, i, j, k);
-  double sig = 0.0;
-  int bad = 0;
-  if (ok) {
-    const idx_t c = lin(G, i, j, k);
-    const double r = P.rho0 + (double)A.rho[c], en = P.e0 + (double)A.e[c];
-    if (!(r > 0.0) || !(en > 0.0) || !isfinite(r) || !isfinite(en)) bad = 1;
-    const double cs = sqrt(P.gamma * P.gm1 * en / r);
-    double vm = 0.0;
+__device__ __forceinline__ double cell_signal(const Geo &G, const Phys &P, const RedArgs<T> &A, idx_t c,
+                                              int &bad) {
+  const double r = P.rho0 + (double)A.rho[c], en = P.e0 + (double)A.e[c];
+  if (!(r > 0.0) || !(en > 0.0) || !isfinite(r) || !isfinite(en)) bad = 1;
+  const double cs = sqrt(P.gamma * P.gm1 * en / r);
+  double vm = 0.0;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double a = fabs(vback(P, d) + (double)A.v[d][c]);
-      const double b = fabs(vback(P, d) + (double)A.v[d][c + dstride(G, d)]);
-      vm = fmax(vm, fmax(a, b));
-    }
-    sig = cs + vm;
-    if (!isfinite(sig)) bad = 1;
+  for (int d = 0; d < 3; ++d) {
+    const double a = fabs(vback(P, d) + (double)A.v[d][c]);
+    const double b = fabs(vback(P, d) + (double)A.v[d][c + dstride(G, d)]);
+    vm = fmax(vm, fmax(a, b));
   }
+  const double sig = cs + vm;
+  if (!isfinite(sig)) bad = 1;
+  return sig;
+}
+
+// block maximum of the signal speeds into spart[block]; a bad cell raises
+// the health flag
+__device__ void block_signal(double sig, int bad, double *spart, Scal *S) {
   sig = wave_max(bad ? 0.0 : sig);
   const bool anybad = __any(bad);
   __shared__ double sh[BX * BY / 64];
   const int t = threadIdx.y * BX + threadIdx.x;
   if ((t % 64) == 0) {
     sh[t / 64] = sig;
-    if (anybad) atomicOr(&A.S->health, 1);
+    if (anybad) atomicOr(&S->health, 1);
   }
   __syncthreads();
   if (t == 0) {
     double m = sh[0];
     for (int q = 1; q < BX * BY / 64; ++q) m = fmax(m, sh[q]);
-    A.part[blockIdx.x] = m;
+    spart[blockIdx.x] = m;
   }
+}
+
+// Largest signal speed over the active cells and their faces (per block,
+// reduced by the final kernel), and the health check.
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_signal(Geo G, Phys P, RedArgs<T> A) {
+  int i, j, k;
+  const bool ok = thread_cell(A.b, i, j, k);
+  double sig = 0.0;
+  int bad = 0;
+  if (ok) sig = cell_signal(G, P, A, lin(G, i, j, k), bad);
+  block_signal(sig, bad, A.spart, A.S);
+}
+
+// End of a step: the force partials of eq. 18 (as k_force) and the signal
+// speed partials of the next step's time step (as k_signal) in one pass over
+// the state, which both read.
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
+  int i, j, k;
+  const bool ok = thread_cell(A.b, i, j, k);
+  double fx = 0.0, fy = 0.0, fz = 0.0, sig = 0.0;
+  int bad = 0;
+  if (ok) {
+    const idx_t c = lin(G, i, j, k);
+    sig = cell_signal(G, P, A, c, bad);
+    if (!is_covered(A, i, j, k)) {
+      const double x = xcen<double>(G, 0, i), y = xcen<double>(G, 1, j), z = xcen<double>(G, 2, k);
+      const double d2 = x * x + y * y + z * z + P.eps2;
+      const double vol = G.dx * G.dx * G.dx;
+      const double w = P.GM * (double)A.rho[c] * vol / (d2 * sqrt(d2));
+      fx = w * x;
+      fy = w * y;
+      fz = w * z;
+    }
+  }
+  block_sum3(fx, fy, fz, A.part);
+  block_signal(sig, bad, A.spart, A.S);
 }
 
 struct DtArgs {
@@ -1139,12 +1201,11 @@ struct DtArgs {
 };
 
 // coarse step cfl * min_l 2^l min(dx_l / smax_l, dx_l^2 / (6 chi)) (eq. 55, xi = 2)
-__global__ void __launch_bounds__(256) k_dt_final(Phys P, DtArgs A, Scal *S) {
+__device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
   __shared__ double sh[4];
   __shared__ double smax[MAXLEV];
   for (int l = 0; l < A.nl; ++l) {
-    double m = 0.0;
-    for (int b = threadIdx.x; b < A.npart[l]; b += 256) m = fmax(m, A.part[l][b]);
+    double m = strided_max(A.part[l], A.npart[l], 0.0);
     m = wave_max(m);
     if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
     __syncthreads();
@@ -1162,6 +1223,16 @@ __global__ void __launch_bounds__(256) k_dt_final(Phys P, DtArgs A, Scal *S) {
   const double dt0 = P.cfl * best;
   for (int l = 0; l < A.nl; ++l) S->dt[l] = ldexp(dt0, -l);
   if (A.advance) S->t += dt0;
+}
+
+__global__ void __launch_bounds__(256) k_dt_final(Phys P, DtArgs A, Scal *S) { dt_body(P, A, S); }
+
+// between two steps: the force of the state just reached (logged at its
+// time), then the next step's time step from the same state's signal speeds
+__global__ void __launch_bounds__(256) k_step_final(Phys P, FinalArgs F, DtArgs D, Scal *S, int do_force,
+                                                     int do_dt) {
+  if (do_force) final3_body(F);
+  if (do_dt) dt_body(P, D, S);
 }
 
 __global__ void k_zero(unsigned int *p, size_t n) {
@@ -1453,6 +1524,7 @@ static RedArgs<T> red_args(const Geo &G, LevBufs &B, int cur, Scal *S) {
   A.e = tp<T>(B.q[cur][1]);
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.part = B.part;
+  A.spart = B.part + 3 * part_count(G);
   A.S = S;
   for (int d = 0; d < 3; ++d) {
     A.cov_lo[d] = G.has_fine ? G.n[d] / 4 : 0;
@@ -1471,16 +1543,55 @@ void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
   }
 }
 
-void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S, int advance) {
+static DtArgs dt_args(const Geo *G, const LevBufs *B, int nl, int advance) {
   DtArgs A;
   for (int l = 0; l < MAXLEV; ++l) {
     A.dx[l] = l < nl ? G[l].dx : 0.0;
-    A.part[l] = l < nl ? B[l].part : nullptr;
+    A.part[l] = l < nl ? B[l].part + 3 * part_count(G[l]) : nullptr;
     A.npart[l] = l < nl ? (int)part_count(G[l]) : 0;
   }
   A.nl = nl;
   A.advance = advance;
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, P, A, S);
+  return A;
+}
+
+void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S, int advance) {
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, P, dt_args(G, B, nl, advance), S);
+}
+
+void post_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S) {
+  if (P.fp32) {
+    RedArgs<float> A = red_args<float>(G, B, cur, S);
+    DFK_LAUNCH(k_post<float>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  } else {
+    RedArgs<double> A = red_args<double>(G, B, cur, S);
+    DFK_LAUNCH(k_post<double>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  }
+}
+
+static FinalArgs final_args(double *const *parts, const int *nparts, int nl, Scal *S, int slot, double *flog) {
+  FinalArgs A;
+  for (int l = 0; l < MAXLEV; ++l) {
+    A.part[l] = l < nl ? parts[l] : nullptr;
+    A.npart[l] = l < nl ? nparts[l] : 0;
+  }
+  A.nl = nl;
+  A.out = slot == 1 ? S->totals : S->force;
+  A.S = S;
+  A.flog = slot == 2 ? flog : nullptr;
+  return A;
+}
+
+void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P, Scal *S, double *flog,
+                int do_force, int do_dt) {
+  double *parts[MAXLEV];
+  int np[MAXLEV];
+  for (int l = 0; l < nl; ++l) {
+    parts[l] = B[l].part;
+    np[l] = (int)part_count(G[l]);
+  }
+  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(256), 0, st, P, final_args(parts, np, nl, S, 2, flog),
+                     dt_args(G, B, nl, 1), S, do_force, do_dt);
 }
 
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {
@@ -1507,16 +1618,7 @@ int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int
 
 void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S, int slot,
                  double *flog) {
-  FinalArgs A;
-  for (int l = 0; l < MAXLEV; ++l) {
-    A.part[l] = l < nl ? parts[l] : nullptr;
-    A.npart[l] = l < nl ? nparts[l] : 0;
-  }
-  A.nl = nl;
-  A.out = slot == 1 ? S->totals : S->force;
-  A.S = S;
-  A.flog = slot == 2 ? flog : nullptr;
-  hipLaunchKernelGGL(k_final3, dim3(1), dim3(256), 0, st, A);
+  hipLaunchKernelGGL(k_final3, dim3(1), dim3(256), 0, st, final_args(parts, nparts, nl, S, slot, flog));
 }
 
 }  // namespace dfk
