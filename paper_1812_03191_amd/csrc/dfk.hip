@@ -1054,7 +1054,7 @@ __global__ void __launch_bounds__(BX * BY) k_totals(Geo G, Phys P, RedArgs<T> A)
   block_sum3(m, ei, ek, A.part);
 }
 
-// fixed-order sum of the partials of all levels (one block of 256 threads)
+// fixed-order sum of the partials of all levels (one block)
 struct FinalArgs {
   const double *part[MAXLEV];
   int npart[MAXLEV];
@@ -1064,44 +1064,54 @@ struct FinalArgs {
   double *flog;
 };
 
-// sum over b = t, t+256, ... < n of p[stride*b + q], in that order, with the
-// loads issued four at a time
-__device__ __forceinline__ double strided_sum(const double *p, int stride, int q, int n, double s) {
-  int b = threadIdx.x;
-  for (; b + 768 < n; b += 1024) {
-    const double x0 = p[(size_t)stride * b + q], x1 = p[(size_t)stride * (b + 256) + q];
-    const double x2 = p[(size_t)stride * (b + 512) + q], x3 = p[(size_t)stride * (b + 768) + q];
-    s += x0;
-    s += x1;
-    s += x2;
-    s += x3;
-  }
-  for (; b < n; b += 256) s += p[(size_t)stride * b + q];
-  return s;
-}
-
-__device__ __forceinline__ double strided_max(const double *p, int n, double m) {
-  int b = threadIdx.x;
-  for (; b + 768 < n; b += 1024)
-    m = fmax(fmax(m, fmax(p[b], p[b + 256])), fmax(p[b + 512], p[b + 768]));
-  for (; b < n; b += 256) m = fmax(m, p[b]);
-  return m;
-}
+// The one-block kernels that finish a reduction run FT threads: each reads
+// its partials (blocks t, t+FT, ...) eight at a time, so that all partials
+// of a 128^3 level are in flight at once; the order of the sum is fixed.
+constexpr int FT = 1024;
+constexpr int FW = FT / 64;
 
 __device__ void final3_body(const FinalArgs &A) {
-  __shared__ double sh[3][4];
-  double s[3] = {0.0, 0.0, 0.0};
-  for (int l = 0; l < A.nl; ++l)
+  __shared__ double sh[3][FW];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int l = 0; l < A.nl; ++l) {
+    const double *p = A.part[l];
+    const int n = A.npart[l];
+    int b = threadIdx.x;
+    for (; b + 7 * FT < n; b += 8 * FT) {
+      double x[8][3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) s[q] = strided_sum(A.part[l], 3, q, A.npart[l], s[q]);
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
-  for (int q = 0; q < 3; ++q) s[q] = wave_sum(s[q]);
+        for (int q = 0; q < 3; ++q) x[u][q] = p[3 * (size_t)(b + u * FT) + q];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        s0 += x[u][0];
+        s1 += x[u][1];
+        s2 += x[u][2];
+      }
+    }
+    for (; b < n; b += FT) {
+      s0 += p[3 * (size_t)b + 0];
+      s1 += p[3 * (size_t)b + 1];
+      s2 += p[3 * (size_t)b + 2];
+    }
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
   const int w = threadIdx.x / 64;
-  if (threadIdx.x % 64 == 0)
-    for (int q = 0; q < 3; ++q) sh[q][w] = s[q];
+  if (threadIdx.x % 64 == 0) {
+    sh[0][w] = s0;
+    sh[1][w] = s1;
+    sh[2][w] = s2;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 0; q < 3; ++q) A.out[q] = (sh[q][0] + sh[q][1]) + (sh[q][2] + sh[q][3]);
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+      for (int v = 0; v < FW; ++v) t += sh[q][v];
+      A.out[q] = t;
+    }
     if (A.flog) {
       const unsigned int n = A.S->nlog;
       double *e = A.flog + 4 * (size_t)(n % FLOG);
@@ -1113,7 +1123,7 @@ __device__ void final3_body(const FinalArgs &A) {
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(256) k_final3(FinalArgs A) { final3_body(A); }
+__global__ void __launch_bounds__(FT) k_final3(FinalArgs A) { final3_body(A); }
 
 // Signal speed c_s + |v| of an active cell, the largest over its six faces,
 // and whether its density and energy are positive and finite.
@@ -1202,14 +1212,29 @@ struct DtArgs {
 
 // coarse step cfl * min_l 2^l min(dx_l / smax_l, dx_l^2 / (6 chi)) (eq. 55, xi = 2)
 __device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
-  __shared__ double sh[4];
+  __shared__ double sh[FW];
   __shared__ double smax[MAXLEV];
   for (int l = 0; l < A.nl; ++l) {
-    double m = strided_max(A.part[l], A.npart[l], 0.0);
+    const double *p = A.part[l];
+    const int n = A.npart[l];
+    double m = 0.0;
+    int b = threadIdx.x;
+    for (; b + 7 * FT < n; b += 8 * FT) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = p[b + u * FT];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) m = fmax(m, x[u]);
+    }
+    for (; b < n; b += FT) m = fmax(m, p[b]);
     m = wave_max(m);
     if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = m;
     __syncthreads();
-    if (threadIdx.x == 0) smax[l] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    if (threadIdx.x == 0) {
+      double t = sh[0];
+      for (int v = 1; v < FW; ++v) t = fmax(t, sh[v]);
+      smax[l] = t;
+    }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
@@ -1225,11 +1250,11 @@ __device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
   if (A.advance) S->t += dt0;
 }
 
-__global__ void __launch_bounds__(256) k_dt_final(Phys P, DtArgs A, Scal *S) { dt_body(P, A, S); }
+__global__ void __launch_bounds__(FT) k_dt_final(Phys P, DtArgs A, Scal *S) { dt_body(P, A, S); }
 
 // between two steps: the force of the state just reached (logged at its
 // time), then the next step's time step from the same state's signal speeds
-__global__ void __launch_bounds__(256) k_step_final(Phys P, FinalArgs F, DtArgs D, Scal *S, int do_force,
+__global__ void __launch_bounds__(FT) k_step_final(Phys P, FinalArgs F, DtArgs D, Scal *S, int do_force,
                                                      int do_dt) {
   if (do_force) final3_body(F);
   if (do_dt) dt_body(P, D, S);
@@ -1556,7 +1581,7 @@ static DtArgs dt_args(const Geo *G, const LevBufs *B, int nl, int advance) {
 }
 
 void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S, int advance) {
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, st, P, dt_args(G, B, nl, advance), S);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FT), 0, st, P, dt_args(G, B, nl, advance), S);
 }
 
 void post_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S) {
@@ -1590,7 +1615,7 @@ void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P,
     parts[l] = B[l].part;
     np[l] = (int)part_count(G[l]);
   }
-  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(256), 0, st, P, final_args(parts, np, nl, S, 2, flog),
+  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(FT), 0, st, P, final_args(parts, np, nl, S, 2, flog),
                      dt_args(G, B, nl, 1), S, do_force, do_dt);
 }
 
@@ -1618,7 +1643,7 @@ int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int
 
 void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S, int slot,
                  double *flog) {
-  hipLaunchKernelGGL(k_final3, dim3(1), dim3(256), 0, st, final_args(parts, nparts, nl, S, slot, flog));
+  hipLaunchKernelGGL(k_final3, dim3(1), dim3(FT), 0, st, final_args(parts, nparts, nl, S, slot, flog));
 }
 
 }  // namespace dfk
