@@ -190,6 +190,60 @@ def copy_probe(nbytes=1 << 30):
     print(json.dumps({"copy_probe_bytes_each_way": nbytes, "launches": 3}), file=sys.stderr)
 
 
+# kernel kind of each kernel name in a counter file (FP64 and FP32 alike)
+PMC_KINDS = (("k_kick<", "true, false", "kick"), ("k_kick<", "true, true", "rebuild_kick"),
+             ("k_compress<", "", "compress"), ("k_diffuse_heat<", "", "diffuse_heat"),
+             ("k_xpass<", "", "pass_x"), ("k_march<", ", 1,", "pass_y"), ("k_march<", ", 2,", "pass_z"),
+             ("k_post<", "", "force"), ("k_step_final", "", "force"))
+
+
+def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
+    """HBM bytes per launch of each kernel kind from a FETCH_SIZE and a
+    WRITE_SIZE pass of rocprofv3 over `bench.py ... --copy-probe`.  Both
+    counters read in KiB per dispatch; each is scaled by what it reads for the
+    1 GiB plain copies of the probe.  Writes profiles/pmc_traffic_config2.json
+    (tagged with the kernel source hash) and prints a markdown table."""
+    import collections
+    import csv
+
+    def load(path):
+        rows = collections.defaultdict(list)
+        probe = []
+        for r in csv.DictReader(open(path)):
+            n, v, g = r["Kernel_Name"], float(r["Counter_Value"]), int(r["Grid_Size"])
+            if "copyBuffer" in n:
+                probe.append((g, v))
+            rows[n].append(v)
+        gmax = max(g for g, _ in probe)
+        pv = [v for g, v in probe if g == gmax]
+        return rows, (1 << 20) / (sum(pv) / len(pv))
+
+    F, kf = load(fetch_csv)
+    W, kw = load(write_csv)
+    kinds = collections.defaultdict(lambda: [0.0, 0.0])
+    for n in F:
+        for pre, sub, kind in PMC_KINDS:
+            short = n.replace("dfk::(anonymous namespace)::", "")
+            if pre in short and sub in short:
+                # per step: mean per dispatch, kernels of one kind summed
+                kinds[kind][0] += sum(F[n]) / len(F[n]) * kf * 1024
+                kinds[kind][1] += (sum(W[n]) / len(W[n]) * kw * 1024) if n in W else 0.0
+                break
+    out = {"source_hash": dfk_hash(), "fetch_scale": round(kf, 4), "write_scale": round(kw, 4),
+           "workload": "128^3 single level FP64 (the bench workload)",
+           "kernels": {k: {"fetch_bytes": int(f), "write_bytes": int(w), "bytes_per_launch": int(f + w)}
+                       for k, (f, w) in sorted(kinds.items())}}
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic_config2.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    cells = workload()[0]["nx"] * workload()[0]["ny"] * workload()[0]["nz"]
+    print(f"scale factors: FETCH_SIZE x{kf:.3f}, WRITE_SIZE x{kw:.3f} (1 GiB copy probe)\n")
+    print("| kind | fetch MiB | write MiB | total MiB | algorithmic MiB |")
+    print("|---|---:|---:|---:|---:|")
+    for k, (f, w) in sorted(kinds.items()):
+        alg = ALG_BYTES.get(k, 0) * cells / 2**20
+        print(f"| {k} | {f / 2**20:.1f} | {w / 2**20:.1f} | {(f + w) / 2**20:.1f} | {alg:.1f} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +255,12 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--serve-jobs", type=int, default=100,
                     help="jobs of the served workload to run (400 is the whole stream; 0 skips)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/pmc_traffic_config2.json from two counter passes and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(each run is independent; see DESIGN.md for how the update would shard)",

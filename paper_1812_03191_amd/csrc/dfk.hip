@@ -642,6 +642,193 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   }
 }
 
+// Row form of the x pass for level 0 when a row has at most 64 R cells and R
+// divides it: one wave holds a whole row, lane l the R consecutive cells
+// R l .. R l + R - 1, so the neighbours of a cell are in its own lane or, at
+// the lane's ends, in the adjacent lane (one lane shift per exchanged value
+// for R cells).  The boundary conditions give what lies beyond the row: at
+// x_min the outflow copy (the specific value of cell -1 is that of cell 0,
+// the limited difference there is zero); at x_max, cells n, n+1 hold zero
+// departures and the injection face carries no departure transfer.  Cells
+// past n inside the wave are those ghost cells.  Arithmetic and its order are
+// those of k_xpass.
+__host__ __device__ inline Box xrow_box(const Box &b) {
+  Box v = b;
+  v.lo[0] = 0;
+  v.hi[0] = (b.hi[0] > b.lo[0]) ? BX : 0;
+  return v;
+}
+
+// lane shift with a fill value for the lane that has no source
+template <int CTRL>
+__device__ __forceinline__ float dpp_fill(float v, float fill) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, fill),
+                                                               __builtin_bit_cast(int, v), CTRL, 0xf, 0xf,
+                                                               false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_fill(double v, double fill) {
+  const long long b = __builtin_bit_cast(long long, v), f = __builtin_bit_cast(long long, fill);
+  const int lo = __builtin_amdgcn_update_dpp((int)f, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(f >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// the value of the cell before each of the lane's R cells (fill for cell -1)
+template <typename T, int R>
+__device__ __forceinline__ void row_left(const T (&v)[R], T (&out)[R], T fill) {
+  out[0] = dpp_fill<DPP_WAVE_SHR1>(v[R - 1], fill);
+#pragma unroll
+  for (int r = 1; r < R; ++r) out[r] = v[r - 1];
+}
+
+// the value of the cell after each of the lane's R cells (fill past the wave)
+template <typename T, int R>
+__device__ __forceinline__ void row_right(const T (&v)[R], T (&out)[R], T fill) {
+#pragma unroll
+  for (int r = 0; r + 1 < R; ++r) out[r] = v[r + 1];
+  out[R - 1] = dpp_fill<DPP_WAVE_SHL1>(v[0], fill);
+}
+
+// R consecutive entries from an R-aligned index (R a power of two)
+template <typename T, int R>
+__device__ __forceinline__ void row_load(const T *p, idx_t c, T (&out)[R]) {
+  typedef T vec __attribute__((ext_vector_type(R)));
+  const vec w = *reinterpret_cast<const vec *>(reinterpret_cast<const char *>(p) +
+                                                (unsigned)c * (unsigned)sizeof(T));
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[r] = w[r];
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void row_store(T *p, idx_t c, const T (&v)[R]) {
+  typedef T vec __attribute__((ext_vector_type(R)));
+  vec w;
+#pragma unroll
+  for (int r = 0; r < R; ++r) w[r] = v[r];
+  *reinterpret_cast<vec *>(reinterpret_cast<char *>(p) + (unsigned)c * (unsigned)sizeof(T)) = w;
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) {
+  int lane, j, k;
+  if (!thread_cell(xrow_box(A.b), lane, j, k)) return;
+  const int n = G.n[0];
+  const int x0 = R * lane;
+  const bool live = x0 < n;  // the lane's cells are active (R divides n)
+  const T dt = (T)(A.fac * A.dtp[0]);
+  const T dx = (T)G.dx;
+  const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx);
+  const T rho0 = (T)P.rho0;
+  const T vb = (T)vback(P, 0);
+  const T M0 = rho0 * vb * mfac;
+  const idx_t c = lin(G, x0, j, k);
+  T dr[R], irr[R], da[R], a[R], nu[R], dM[R], M[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    dr[r] = T(0);
+    da[r] = T(0);
+  }
+  if (live) {
+    row_load<T, R>(A.qi[0], c, dr);
+    row_load<T, R>(A.v[0], c, da);  // left faces x0 .. x0+R-1 (all <= n - 1)
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    irr[r] = T(1) / (rho0 * (rho0 + dr[r]));
+    a[r] = vb + da[r];
+    nu[r] = a[r] * dt / dx;
+  }
+  // left-face value of the upwind van Leer reconstruction of s, per cell
+  auto left_faces = [&](const T (&sv)[R], T (&fv)[R]) {
+    T sl[R], sr[R], d[R], dl[R];
+    row_left<T, R>(sv, sl, sv[0]);
+    row_right<T, R>(sv, sr, T(0));
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[r] = vleer(sr[r] - sv[r], sv[r] - sl[r]);
+    row_left<T, R>(d, dl, T(0));
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      fv[r] = (a[r] > T(0)) ? sl[r] + T(0.5) * dl[r] * (T(1) - nu[r]) : sv[r] - T(0.5) * d[r] * (T(1) + nu[r]);
+  };
+  {
+    T fv[R];
+    left_faces(dr, fv);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      dM[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
+      M[r] = M0 + dM[r];
+    }
+  }
+  // flux matching on the frontier of the finer level
+  const bool ov = A.facc && j - G.n[1] / 4 >= 0 && k - G.n[2] / 4 >= 0 && j - G.n[1] / 4 < G.n[1] / 2 &&
+                  k - G.n[2] / 4 < G.n[2] / 2;
+  const int flo = n / 4, fhi = (3 * n) / 4;
+  const long fnt = (long)A.fn[1] * A.fn[2];
+  const long fbase = (long)(2 * (k - G.n[2] / 4)) * A.fn[1] + 2 * (j - G.n[1] / 4);
+  auto finish = [&](int m, const T (&own)[R], T (&FL)[R]) {
+    if (ov) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int x = x0 + r;
+        if (x == flo || x == fhi) {
+          const T *f = A.facc + ((long)(x == fhi) * NQ + m) * fnt + fbase;
+          FL[r] = (f[0] + f[1]) + (f[A.fn[1]] + f[A.fn[1] + 1]);
+        }
+      }
+    }
+    T FR[R], out[R];
+    row_right<T, R>(FL, FR, T(0));
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = own[r] - (FR[r] - FL[r]) * ivol;
+    if (live) row_store<T, R>(A.qo[m], c, out);
+  };
+  {
+    T F[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] = dM[r];
+    finish(0, dr, F);
+  }
+
+#pragma unroll 1
+  for (int m = 1; m < NQ; ++m) {
+    T sv[R], own[R];
+    if (m >= 2) {
+      // momentum P = rho v of a face velocity: its specific value is v itself
+      const int d = (m - 2) >> 1;
+      if (d == 0 && (m & 1)) {
+        // right faces x0+1 .. x0+R: the next cell's left face (zero at x_max)
+        row_right<T, R>(da, sv, T(0));
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) sv[r] = T(0);
+        if (live) row_load<T, R>(A.v[d], c + ((m & 1) ? dstride(G, d) : 0), sv);
+      }
+      const T vbd = (T)vback(P, d);
+#pragma unroll
+      for (int r = 0; r < R; ++r) own[r] = rho0 * sv[r] + dr[r] * (vbd + sv[r]);
+    } else {
+      T dq[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) dq[r] = T(0);
+      if (live) row_load<T, R>(A.qi[m], c, dq);
+      const T q0 = (T)qback(P, m);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sv[r] = (rho0 * dq[r] - q0 * dr[r]) * irr[r];
+        own[r] = dq[r];
+      }
+    }
+    T fv[R], F[R];
+    left_faces(sv, fv);
+    const T s0 = (T)sback(P, m);
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] = s0 * dM[r] + fv[r] * M[r];
+    finish(m, own, F);
+  }
+}
+
 // Streaming form of the y and z passes.  A thread owns one column segment
 // [c0, c1) along DIR (lanes along x, so every load is coalesced) and walks it
 // once: each cell is loaded once (one iteration ahead of its use), each limited
@@ -1447,9 +1634,13 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   A.facc = (G.has_fine && fine_acc) ? reinterpret_cast<const T *>(fine_acc) : nullptr;
   for (int d = 0; d < 3; ++d) A.fn[d] = Gf ? Gf->n[d] : 0;
   if (dir == 0) {
-    const dim3 gr = grid_of(xtile_box(A.b)), bl(BX, BY);
-    if (G.bc) DFK_LAUNCH((k_xpass<T, true>), gr, bl, st, G, P, A);
-    else DFK_LAUNCH((k_xpass<T, false>), gr, bl, st, G, P, A);
+    const dim3 bl(BX, BY);
+    const int n = G.n[0];
+    if (G.bc && n <= BX) DFK_LAUNCH((k_xrow<T, 1>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
+    else if (G.bc && n <= 2 * BX && n % 2 == 0) DFK_LAUNCH((k_xrow<T, 2>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
+    else if (G.bc && n <= 4 * BX && n % 4 == 0) DFK_LAUNCH((k_xrow<T, 4>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
+    else if (G.bc) DFK_LAUNCH((k_xpass<T, true>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    else DFK_LAUNCH((k_xpass<T, false>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
     return;
   }
   MarchArgs<T> M;

@@ -107,6 +107,23 @@ def test_stage_parity(dfm, stage, dt, n):
     assert worst < 1e-13, {k: v for k, v in errs.items() if v > 1e-14}
 
 
+# The x pass takes one of several launch forms by row length on level 0:
+# whole rows per wave with 1, 2 or 4 cells per lane (a row exactly filling the
+# wave, a partly filled one), and the overlapping-tile form otherwise.
+XROW_SHAPES = [(64, 8, 6), (128, 6, 8), (96, 6, 6), (200, 6, 4), (130, 6, 4), (256, 4, 4)]
+
+
+@pytest.mark.parametrize("n", XROW_SHAPES)
+@pytest.mark.parametrize("stage,dt", [("transport", 2e-3), ("level_step", 2e-3)])
+def test_x_pass_launch_forms(dfm, stage, dt, n):
+    _say(f"[x pass forms] {stage} n={n}")
+    o, g = _random_pair(dfm, n, seed=29)
+    o.stage(stage, dt)
+    g.stage(stage, dt)
+    errs = _field_errors(o, g, 1)
+    assert max(errs.values()) < 1e-13, {k: v for k, v in errs.items() if v > 1e-14}
+
+
 # ------------------------------------------------------- full single level
 
 def test_config1_parity_100_steps(dfm):
