@@ -70,8 +70,8 @@ typedef struct df_run df_run;
  *  seed, noise_amp : every active density is multiplied by 1 + noise_amp (2U-1),
  *               U uniform in [0,1) from a counter-based SplitMix64 stream;
  *  tile_chunk : cells per column segment of the streaming y and z transport
- *               passes (0 selects 16; 2..256), a launch-shape parameter that
- *               does not change results. */
+ *               passes (0 selects 32 for FP64 and 16 for FP32 storage; 2..256),
+ *               a launch-shape parameter that does not change results. */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t nlevels;
@@ -214,6 +214,14 @@ int df_engine_release(df_engine *eng, int32_t slot);
 int df_engine_stats(df_engine *eng, int64_t out[2]);
 
 int df_engine_destroy(df_engine *eng);
+
+/* Measurement reference (no part of the method): a plain device copy of
+ * `bytes` bytes from src to dst on `stream` (a hipStream_t, or NULL), by a
+ * grid-stride kernel with 16-byte loads and stores, asynchronous.  Both
+ * pointers must be 16-byte aligned device memory and bytes a multiple of 16
+ * (DF_EINVAL otherwise); the ranges must not overlap.  Its rate is the
+ * attainable HBM bandwidth the kernels' rooflines are set beside. */
+int df_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
 const char *df_strerror(int code);
 const char *df_last_error(void);

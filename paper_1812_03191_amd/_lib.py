@@ -69,6 +69,7 @@ def _load():
         "df_force_log": [vp, dp, i32, ctypes.POINTER(i32)],
         "df_timing_enable": [vp, i32],
         "df_timing_read": [vp, dp, ctypes.POINTER(i32), i32],
+        "df_stream_copy": [vp, vp, ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -186,6 +187,18 @@ def timing_read(h) -> dict:
     cnt = (ctypes.c_int32 * nk)()
     _ck(_load().df_timing_read(h, _dp(ms), cnt, nk))
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def stream_copy(dst, src, stream=None) -> None:
+    """plain device copy (measurement reference) between two torch tensors of
+    the same byte size, 16-byte aligned, on `stream` (default: the current)"""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("sizes differ")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _ck(_load().df_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))
 
 
 # ------------------------------------------------------------------ Run

@@ -317,7 +317,7 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   R->desc = *d;
   R->nl = d->nlevels;
   R->esz = d->precision == DF_FP32 ? 4 : 8;
-  R->chunk = d->tile_chunk ? d->tile_chunk : 16;
+  R->chunk = d->tile_chunk ? d->tile_chunk : (d->precision == DF_FP32 ? 16 : 32);
   R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
@@ -662,6 +662,16 @@ int df_timing_read(df_run *R, double *ms, int32_t *count, int32_t nkinds) {
   }
   R->ev_used = 0;
   return DF_OK;
+}
+
+int df_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {
+  if (!dst || !src) return fail(DF_EINVAL, "null pointer");
+  if (((uintptr_t)dst | (uintptr_t)src | bytes) % 16) return fail(DF_EINVAL, "copy needs 16-byte alignment");
+  const char *d = (const char *)dst, *s = (const char *)src;
+  if (d < s + bytes && s < d + bytes) return fail(DF_EINVAL, "overlapping copy ranges");
+  if (bytes / 16 / 1024 >= (1u << 31)) return fail(DF_EINVAL, "copy larger than 32 TiB");
+  dfk::stream_copy((hipStream_t)stream, dst, src, bytes / 16);
+  return launch_check("df_stream_copy");
 }
 
 int df_destroy(df_run *R) {

@@ -111,5 +111,7 @@ void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl
                  int slot, double *flog);
 int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
 size_t part_count(const Geo &G);
+// plain copy of n 16-byte words (measurement reference)
+void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16);
 
 }  // namespace dfk

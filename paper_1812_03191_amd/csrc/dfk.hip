@@ -1680,6 +1680,26 @@ void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBuf
   else transport_pass_t<double>(st, dir, G, P, B, src, dtp, fac, Gf, fine_acc, chunk);
 }
 
+// each thread moves four 16-byte words (loads first), block b the words
+// [1024 b, 1024 b + 1024)
+__global__ void __launch_bounds__(256) k_copy16(uint4 *dst, const uint4 *src, size_t n) {
+  const size_t base = (size_t)blockIdx.x * 1024 + threadIdx.x;
+  uint4 w[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (base + 256 * u < n) w[u] = src[base + 256 * u];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+    if (base + 256 * u < n) dst[base + 256 * u] = w[u];
+}
+
+void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16) {
+  if (n16 == 0) return;
+  const size_t blocks = (n16 + 1023) / 1024;
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4 *>(dst),
+                     reinterpret_cast<const uint4 *>(src), n16);
+}
+
 void zero(hipStream_t st, void *p, size_t bytes) {
   const size_t n = bytes / 4;
   if (n == 0 || !p) return;
