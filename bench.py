@@ -73,25 +73,35 @@ def traffic_from_profiles(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, budget_s=15.0):
+def cpu_baseline(cfg, budget_s=12.0):
+    """the FP64 oracle on the host: a bounded number of coarse steps of the
+    same 128^3 workload, with all OpenMP threads and with one thread"""
     nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
-    os.environ["OMP_NUM_THREADS"] = str(nthreads)
     from oracle.oracle import Oracle
 
-    o = Oracle(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
-               gamma=cfg["gamma"], cfl=cfg["cfl"], seed=cfg["seed"], noise_amp=cfg["noise_amp"],
-               GM=cfg["GM"], eps=cfg["eps"], L=cfg["L"], mach=cfg["mach"], chi=cfg["chi"])
-    t0 = time.perf_counter()
-    o.step(1)
-    t1 = time.perf_counter() - t0
-    n = max(2, min(60, int(budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    o.step(n)
-    el = time.perf_counter() - t0
     cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
-    return {"value": cells * n / el, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
+
+    def rate(threads, budget):
+        o = Oracle(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
+                   gamma=cfg["gamma"], cfl=cfg["cfl"], seed=cfg["seed"], noise_amp=cfg["noise_amp"],
+                   GM=cfg["GM"], eps=cfg["eps"], L=cfg["L"], mach=cfg["mach"], chi=cfg["chi"],
+                   threads=threads)
+        t0 = time.perf_counter()
+        o.step(1)
+        t1 = time.perf_counter() - t0
+        n = max(1, min(60, int(budget / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        o.step(n)
+        el = time.perf_counter() - t0
+        return cells * n / el, n, el
+
+    v, n, el = rate(nthreads, budget_s)
+    v1, n1, el1 = rate(1, budget_s / 2)
+    return {"value": v, "unit": "cell-updates/s", "cores": nthreads, "kind": "oracle",
             "sample": f"128^3 single level FP64, {n} coarse steps after one untimed step "
-                      f"({el:.1f} s, OpenMP threads={nthreads})"}
+                      f"({el:.1f} s, OpenMP threads={nthreads})",
+            "value_1thread": v1,
+            "sample_1thread": f"{n1} coarse steps after one untimed step ({el1:.1f} s, 1 thread)"}
 
 
 def fp32_single(cfg, K, W):
@@ -113,6 +123,43 @@ def fp32_single(cfg, K, W):
     ms = e0.elapsed_time(e1)
     cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
     return {"cell_updates_per_s": cells * K / (ms / 1e3), "ms_per_step": ms / K, "force": run.force()[:3].tolist()}
+
+
+def nested(steps=None, warm=2):
+    """4 levels of 128^3 (Mach 0.3, GM 1e-3, chi 0.1, L 1e-3, 100 coarse
+    steps, seed 3) in FP64 and with FP32 departures: cell-updates/s over all
+    levels (level l advances 2^l sub-steps per coarse step) and the FP32
+    force error against the FP64 run"""
+    import torch
+
+    import paper_1812_03191_amd as dfm
+    from tests import inputs
+
+    cfg, K = inputs.config3()
+    K = steps or K
+    cells = cfg["nx"] * cfg["ny"] * cfg["nz"] * sum(2 ** l for l in range(cfg["nlevels"]))
+    out = {"workload": "4 levels of 128^3, Mach 0.3, GM 1e-3, chi 0.1, L 1e-3, 100 coarse steps, seed 3"}
+    forces = {}
+    for name, prec in (("fp64", dfm.DF_FP64), ("fp32", dfm.DF_FP32)):
+        run = dfm.Run(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
+                      seed=cfg["seed"], noise_amp=cfg["noise_amp"], precision=prec)
+        run.set_perturber(cfg["GM"], cfg["eps"], cfg["L"], cfg["mach"], cfg["chi"])
+        run.step(warm)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(run.stream)
+        run.step(K)
+        e1.record(run.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        forces[name] = run.force()
+        out[name] = {"cell_updates_per_s": cells * K / (ms / 1e3), "ms_per_coarse_step": ms / K}
+        del run
+        torch.cuda.empty_cache()
+    f64, f32 = forces["fp64"], forces["fp32"]
+    out["fp32_force_rel_err_vs_fp64"] = float(abs(f32[0] - f64[0]) / abs(f64[0]))
+    out["cell_updates_per_coarse_step"] = cells
+    return out
 
 
 def batched_sweep(warm=2):
@@ -351,6 +398,8 @@ def main():
         extra["fp32_single"] = fp32_single(cfg, K, W)
         print("[bench] batched sweep (64 jobs, FP32 and FP64)", file=sys.stderr, flush=True)
         extra["batched"] = batched_sweep()
+        print("[bench] nested 4 x 128^3 (FP64 and FP32)", file=sys.stderr, flush=True)
+        extra["nested"] = nested()
     if args.serve_jobs > 0:
         print(f"[bench] serving {args.serve_jobs} jobs", file=sys.stderr, flush=True)
         extra["serving"] = serving(args.serve_jobs)

@@ -27,6 +27,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define DFO_MAXLEV 16
 #define NSTATE 5 /* rho, e, vx, vy, vz */
@@ -938,6 +941,15 @@ void dfo_step(void *h, int n) {
 
 double dfo_time(void *h) { return ((run_t *)h)->t; }
 double dfo_dt(void *h) { return dt_rule((run_t *)h); }
+
+/* OpenMP threads of the cell loops (timing only; results do not depend on it) */
+void dfo_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 void dfo_force(void *h, double out[3]) { force((run_t *)h, out); }
 void dfo_totals(void *h, double out[4]) { totals((run_t *)h, out); }
 

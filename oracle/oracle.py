@@ -73,6 +73,8 @@ def _load():
         lib.dfo_prolong_all.argtypes = [vp, ip]
         lib.dfo_stage.argtypes = [vp, ip, ctypes.c_double]
         lib.dfo_heat_weights.argtypes = [vp, ip, dp]
+        lib.dfo_set_threads.argtypes = [ip]
+        lib.dfo_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -98,6 +100,7 @@ class Oracle:
             raise ValueError("dx0 is required")
         if threads is not None:
             os.environ["OMP_NUM_THREADS"] = str(threads)
+            _load().dfo_set_threads(int(threads))
         self._lib = _load()
         self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
                          noise_amp, GM, eps, L, mach, chi)
