@@ -179,7 +179,9 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
   { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
-  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true); }
+  // a single-level step ends here: the same launch forms the force and the
+  // next step's signal-speed partials
+  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true, R->nl == 1 ? R->scal : nullptr); }
   R->cur[l] = 1 - c;
 }
 
@@ -268,9 +270,10 @@ void enqueue_steps(df_run *R, int n) {
   for (int s = 0; s < n; ++s) {
     cycle(R, 0);
     TScope t(R, K_FORCE);
-    post_reduce(R);
+    if (R->nl > 1) post_reduce(R);  // single level: formed by the last kick
     dfk::step_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, R->flog, 1, s + 1 < n);
   }
+  R->sig_valid = true;
 }
 
 }  // namespace

@@ -71,9 +71,11 @@ void init_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur
                 double amp);
 void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
           double fac);
-// face velocities from the transported momenta of q[src], then an optional kick
+// face velocities from the transported momenta of q[src], then an optional
+// kick; with post (level 0 with a kick) the same launch also forms the force
+// and signal-speed partials of post_partials for the new state
 void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src,
-                  const double *dtp, double fac, bool do_kick);
+                  const double *dtp, double fac, bool do_kick, Scal *post = nullptr);
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
               double fac);
 // writes etmp; the caller swaps etmp and q[cur][1]

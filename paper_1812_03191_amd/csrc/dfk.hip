@@ -1389,6 +1389,112 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
   block_signal(sig, bad, A.spart, A.S);
 }
 
+// Level-0 form of the kick: one thread per active cell computes the faces on
+// the low side of its cell and, for the last cell along a dimension, also the
+// boundary face n there (the injection face at x_max carries the wind), so the
+// grid is exactly the active box.  With POST (the last kernel of a
+// single-level step) it also forms the end-of-step reductions of k_post: the
+// force partials of its cell, and the signal speed c_s + |v| of every pair of
+// an active cell and one of its faces, taken at the face's owner (the cell on
+// its high side, or the last cell for face n), which holds both adjacent cells'
+// densities and energies.
+template <typename T, bool REBUILD, bool KICK, bool POST>
+__global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
+  int i, j, k;
+  const bool ok = thread_cell(A.b, i, j, k);
+  double fx = 0.0, fy = 0.0, fz = 0.0, sig = 0.0;
+  int bad = 0;
+  if (ok) {
+    const T h = (T)(A.fac * A.dtp[0]);
+    const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
+    const T *rho = A.q[0], *e = A.q[1];
+    const int id[3] = {i, j, k};
+    const idx_t c = lin(G, i, j, k);
+    const T drc = rho[c], dec = e[c];
+    const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
+    const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
+    const T dcen = sqrt(r2c);
+    // signal speed of a cell from its density and energy departures (FP64)
+    auto sound = [&](T dr, T de) -> double {
+      const double r = P.rho0 + (double)dr, en = P.e0 + (double)de;
+      if (!(r > 0.0) || !(en > 0.0) || !isfinite(r) || !isfinite(en)) bad = 1;
+      return sqrt(P.gamma * P.gm1 * en / r);
+    };
+    double cs_own = 0.0;
+    if (POST) cs_own = sound(drc, dec);
+    // face on the low side of cell p (p = own cell, or the virtual cell n past
+    // the last one along d), with the own cell's values when p is the own cell
+    auto face = [&](int d, bool last) {
+      const int pi = i + (last && d == 0), pj = j + (last && d == 1), pk = k + (last && d == 2);
+      const idx_t cf = last ? lin(G, pi, pj, pk) : c;
+      if (last && d == 0) {
+        A.v[0][cf] = T(0);  // injection face at x_max carries the wind
+        if (POST) sig = fmax(sig, fabs(vback(P, 0)) + cs_own);
+        return;
+      }
+      T dcr = drc, der = dec, xr = xc[d], r2r = r2c, dr_ = dcen;
+      if (last) {
+        dcr = cread(rho, G, pi, pj, pk);
+        der = cread(e, G, pi, pj, pk);
+        xr = xcen<T>(G, d, id[d] + 1);
+        r2r = r2c - xc[d] * xc[d] + xr * xr;
+        dr_ = sqrt(r2r);
+      }
+      const int im = pi - (d == 0), jm = pj - (d == 1), km = pk - (d == 2);
+      const T drm = cread(rho, G, im, jm, km), dem = cread(e, G, im, jm, km);
+      T vf;
+      if (REBUILD) {
+        const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
+        const T ppm = cread(pp, G, im, jm, km), pmc = cread(pm, G, pi, pj, pk);
+        const T vb = (T)vback(P, d);
+        vf = (ppm + pmc - vb * (drm + dcr)) / (T(2) * rho0 + drm + dcr);
+      } else {
+        vf = A.v[d][cf];
+      }
+      if (KICK) {
+        const T rface = rho0 + T(0.5) * (drm + dcr);
+        const T gradp = gm1 * (der - dem) / (dx * rface);
+        const T xm = xr - dx;
+        const T dm = sqrt(r2r - xr * xr + xm * xm);
+        const T gradphi = GM * (xr + xm) / (dm * dr_ * (dm + dr_));
+        vf = vf - h * (gradp + gradphi);
+      }
+      A.v[d][cf] = vf;
+      if (POST) {
+        const double a = fabs(vback(P, d) + (double)vf);
+        // the active cells beside the face: the one below (own cell for the
+        // boundary face, cell id-1 otherwise) and the own cell for a low face
+        if (last) {
+          sig = fmax(sig, a + cs_own);
+        } else {
+          sig = fmax(sig, a + cs_own);
+          if (id[d] > 0) sig = fmax(sig, a + sound(drm, dem));
+        }
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      face(d, false);
+      if (id[d] == G.n[d] - 1) face(d, true);
+    }
+    if (POST) {
+      // force of the gas in this cell on the perturber, eq. 18 (FP64)
+      const double x = xcen<double>(G, 0, i), y = xcen<double>(G, 1, j), z = xcen<double>(G, 2, k);
+      const double d2 = x * x + y * y + z * z + P.eps2;
+      const double vol = G.dx * G.dx * G.dx;
+      const double w = P.GM * (double)drc * vol / (d2 * sqrt(d2));
+      fx = w * x;
+      fy = w * y;
+      fz = w * z;
+      if (!isfinite(sig)) bad = 1;
+    }
+  }
+  if (POST) {
+    block_sum3(fx, fy, fz, R.part);
+    block_signal(sig, bad, R.spart, R.S);
+  }
+}
+
 struct DtArgs {
   double dx[MAXLEV];
   const double *part[MAXLEV];  // per-block maximum signal speeds of each level
@@ -1516,8 +1622,11 @@ void init_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur
 }
 
 template <typename T>
+static RedArgs<T> red_args(const Geo &G, LevBufs &B, int cur, Scal *S);
+
+template <typename T>
 static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, void *const *v, const double *dtp,
-                   double fac, bool rebuild, bool do_kick) {
+                   double fac, bool rebuild, bool do_kick, LevBufs *post = nullptr, Scal *S = nullptr) {
   KickArgs<T> A;
   for (int d = 0; d < 3; ++d)
     for (int e = 0; e < 3; ++e) {
@@ -1540,12 +1649,21 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(v[d]);
   A.dtp = dtp;
   A.fac = fac;
-  const dim3 gr = grid_of(A.b), bl(BX, BY);
+  const dim3 bl(BX, BY);
   if (G.bc) {
-    if (rebuild && do_kick) DFK_LAUNCH((k_kick<T, true, true, true>), gr, bl, st, G, P, A);
-    else if (rebuild) DFK_LAUNCH((k_kick<T, true, true, false>), gr, bl, st, G, P, A);
-    else DFK_LAUNCH((k_kick<T, true, false, true>), gr, bl, st, G, P, A);
-  } else {
+    // level 0: one thread per active cell (boundary faces by the last cells)
+    A.b = active_box(G);
+    const dim3 gr = grid_of(A.b);
+    RedArgs<T> R{};
+    if (post) R = red_args<T>(G, *post, 0, S);
+    if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, true, true, true>), gr, bl, st, G, P, A, R);
+    else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, true, true, false>), gr, bl, st, G, P, A, R);
+    else if (rebuild) DFK_LAUNCH((k_kick0<T, true, false, false>), gr, bl, st, G, P, A, R);
+    else DFK_LAUNCH((k_kick0<T, false, true, false>), gr, bl, st, G, P, A, R);
+    return;
+  }
+  const dim3 gr = grid_of(A.b);
+  {
     if (rebuild && do_kick) DFK_LAUNCH((k_kick<T, false, true, true>), gr, bl, st, G, P, A);
     else if (rebuild) DFK_LAUNCH((k_kick<T, false, true, false>), gr, bl, st, G, P, A);
     else DFK_LAUNCH((k_kick<T, false, false, true>), gr, bl, st, G, P, A);
@@ -1558,9 +1676,10 @@ void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, cons
 }
 
 void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
-                  double fac, bool do_kick) {
-  if (P.fp32) kick_t<float>(st, G, P, B.q[src], B.v, dtp, fac, true, do_kick);
-  else kick_t<double>(st, G, P, B.q[src], B.v, dtp, fac, true, do_kick);
+                  double fac, bool do_kick, Scal *post) {
+  LevBufs *pb = (post && G.bc && do_kick) ? &B : nullptr;
+  if (P.fp32) kick_t<float>(st, G, P, B.q[src], B.v, dtp, fac, true, do_kick, pb, post);
+  else kick_t<double>(st, G, P, B.q[src], B.v, dtp, fac, true, do_kick, pb, post);
 }
 
 template <typename T>
