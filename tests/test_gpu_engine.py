@@ -161,3 +161,34 @@ def test_engine_completion_reported_once(dfm):
     assert eng.active()[0] == 0
     f = eng.force(long_)
     assert abs(f[3] - eng.force(short)[3] * 10 / 4) < 1e-9 * f[3]  # same dt, 10 vs 4 steps
+
+
+def test_batched_sweep_subset_against_oracle(dfm):
+    # the 64-job sweep, one job per mesh size (stratified subset of 4), run
+    # together by the engine in FP32 and in FP64 for the sweep's 200 steps:
+    # each job's force against the FP64 oracle
+    from oracle.oracle import Oracle
+
+    jobs, steps = inputs.config4()
+    subset, seen = [], set()
+    for c in jobs:
+        if c["nx"] not in seen:
+            seen.add(c["nx"])
+            subset.append(c)
+    _say(f"[engine] sweep subset {[c['nx'] for c in subset]} x {steps} steps vs oracle")
+    want = []
+    for c in subset:
+        o = Oracle(c["nx"], c["ny"], c["nz"], nlevels=1, dx0=c["dx0"], gamma=c["gamma"], cfl=c["cfl"],
+                   seed=c["seed"], noise_amp=c["noise_amp"], GM=c["GM"], eps=c["eps"], L=c["L"],
+                   mach=c["mach"], chi=c["chi"])
+        o.step(steps)
+        want.append(o.force()[0])
+    for prec, tol in ((1, 1e-4), (0, 1e-9)):
+        eng = dfm.Engine(2 << 30)
+        slots = [eng.admit(c, steps, precision=prec) for c in subset]
+        eng.step(steps // 2)
+        assert set(_wait_done(eng, slots)) >= set(slots)
+        for c, s, w in zip(subset, slots, want):
+            got = eng.force(s)[0]
+            _say(f"[engine] n={c['nx']} mach={c['mach']:.3f} prec={prec} rel err {abs(got - w) / abs(w):.2e}")
+            assert abs(got - w) <= tol * abs(w), (c["nx"], prec, got, w)

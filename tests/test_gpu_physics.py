@@ -87,3 +87,46 @@ def test_low_mach_cold_thermal_force(dfm):
     _say(f"[physics] cold thermal force {got:.5e} vs {want:.5e} (ratio {got / want:.4f})")
     assert got < 0.0
     assert abs(got / want - 1.0) < 0.08
+
+
+def _heating_at(dfm, mach, nl, n, dxf, t_end, L=2e-4):
+    # hot minus cold force at t_end; both runs share the mesh, so their time
+    # steps (diffusion-limited here) and log times coincide
+    r = {}
+    for lum in (L, 0.0):
+        run = dfm.Run(n, nlevels=nl, dx0=dxf * 2 ** (nl - 1), noise_amp=0.0, precision=dfm.DF_FP32)
+        run.set_perturber(GM, 0.0, lum, mach, CHI)
+        while run.force()[3] < t_end:
+            run.step(50)
+        log = run.force_log()
+        r[lum] = log[int(np.searchsorted(log[:, 3], t_end))]
+    assert abs(r[L][3] - r[0.0][3]) < 1e-12 * r[L][3]
+    return r[L][0] - r[0.0][0]
+
+
+def test_high_mach_heating_force_inverse_square(dfm):
+    # Sect. 4.1.2: with the mesh fixed in units of lambda (finest cell lambda/5,
+    # so r_min V / 4 chi is the same), eq. 10 depends on V only through V^-2
+    got = {}
+    for mach in (2.0, 3.0):
+        lam = CHI / (GAMMA * mach)
+        tau = T.response_time(CHI, GAMMA, mach)
+        got[mach] = _heating_at(dfm, mach, 3, 48, lam / 5.0, 40 * tau)
+    ratio = got[2.0] / got[3.0]
+    _say(f"[physics] F_heat(M=2) / F_heat(M=3) = {ratio:.4f} (V^-2 law: 2.25)")
+    assert got[3.0] > 0.0 and abs(ratio / 2.25 - 1.0) < 0.05
+
+
+def test_high_mach_resolution_increment(dfm):
+    # Sect. 4.1.2, eq. 24: at Mach 3, adding a finer level (same box, finest
+    # cell halved) raises the heating force by (gamma-1) G M L log2 / (chi V^2)
+    # in the limit r_min V / 4 chi -> 0; at the finest cells used here (r_min
+    # V / 4 chi = 0.015-0.03) eq. 10's f gives 0.80-0.87 of that increment
+    mach = 3.0
+    lam = CHI / (GAMMA * mach)
+    tau = T.response_time(CHI, GAMMA, mach)
+    f3 = _heating_at(dfm, mach, 3, 48, lam / 5.0, 40 * tau)
+    f4 = _heating_at(dfm, mach, 4, 48, lam / 10.0, 40 * tau)
+    inc = T.heating_increment_per_doubling(GAMMA, 1.0, GM, 2e-4, CHI, mach)
+    _say(f"[physics] Mach 3 increment {f4 - f3:.4e} vs eq. 24 {inc:.4e} (ratio {(f4 - f3) / inc:.3f})")
+    assert 0.72 < (f4 - f3) / inc < 0.97
