@@ -40,8 +40,11 @@ ALG_BYTES = {
     "pass_y": 8 * (9 + 8),        # read 8 transported + vy; write 8
     "pass_z": 8 * (9 + 8),        # read 8 transported + vz; write 8
     "rebuild_kick": 8 * (8 + 3),  # read 8 transported; write vx, vy, vz
-    "force": 8 * 5,               # end-of-step pass: read rho, e, vx, vy, vz
+    # single level: the one-block kernel that sums the partials (the rebuild
+    # kick forms them from the fields it already reads)
+    "force": 0,
 }
+POST_BYTES = 8 * 5  # the separate end-of-step pass of nested runs: read rho, e, vx, vy, vz
 
 
 def workload():
@@ -260,11 +263,14 @@ def attainable_bandwidth(nbytes=1 << 30, reps=10):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-# kernel kind of each kernel name in a counter file (FP64 and FP32 alike)
-PMC_KINDS = (("k_kick<", "true, false", "kick"), ("k_kick<", "true, true", "rebuild_kick"),
-             ("k_compress<", "", "compress"), ("k_diffuse_heat<", "", "diffuse_heat"),
-             ("k_xpass<", "", "pass_x"), ("k_march<", ", 1,", "pass_y"), ("k_march<", ", 2,", "pass_z"),
-             ("k_post<", "", "force"), ("k_step_final", "", "force"))
+# kernel kind of each kernel name in a counter file (FP64 and FP32 alike):
+# every listed substring must occur in the demangled name
+PMC_KINDS = ((("k_kick0<", ", false, true, false>"), "kick"), (("k_kick<", ", false, true>"), "kick"),
+             (("k_kick0<", ", true, true, "), "rebuild_kick"), (("k_kick<", ", true, true>"), "rebuild_kick"),
+             (("k_compress<",), "compress"), (("k_diffuse_heat<",), "diffuse_heat"),
+             (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
+             (("k_march<", ", 1, "), "pass_y"), (("k_march<", ", 2, "), "pass_z"),
+             (("k_step_final",), "force"), (("k_post<",), "post"))
 
 
 def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
@@ -292,9 +298,8 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
     W, kw = load(write_csv)
     kinds = collections.defaultdict(lambda: [0.0, 0.0])
     for n in F:
-        for pre, sub, kind in PMC_KINDS:
-            short = n.replace("dfk::(anonymous namespace)::", "")
-            if pre in short and sub in short:
+        for subs, kind in PMC_KINDS:
+            if all(x in n for x in subs):
                 # per step: mean per dispatch, kernels of one kind summed
                 kinds[kind][0] += sum(F[n]) / len(F[n]) * kf * 1024
                 kinds[kind][1] += (sum(W[n]) / len(W[n]) * kw * 1024) if n in W else 0.0
@@ -310,7 +315,7 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
     print("| kind | fetch MiB | write MiB | total MiB | algorithmic MiB |")
     print("|---|---:|---:|---:|---:|")
     for k, (f, w) in sorted(kinds.items()):
-        alg = ALG_BYTES.get(k, 0) * cells / 2**20
+        alg = (POST_BYTES if k == "post" else ALG_BYTES.get(k, 0)) * cells / 2**20
         print(f"| {k} | {f / 2**20:.1f} | {w / 2**20:.1f} | {(f + w) / 2**20:.1f} | {alg:.1f} |")
 
 
@@ -376,7 +381,7 @@ def main():
         run.step(K)
         kern = dfm.timing_read(run.handle)
         dfm.timing_enable(run.handle, 0)
-        busy = {k: v for k, v in kern.items() if v[1] > 0 and k in ALG_BYTES}
+        busy = {k: v for k, v in kern.items() if v[1] > 0 and ALG_BYTES.get(k, 0) > 0}
         dom = max(busy, key=lambda k: busy[k][0])
         avg_ms = busy[dom][0] / busy[dom][1]
         per_launch = ALG_BYTES[dom] * cells
