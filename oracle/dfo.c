@@ -47,6 +47,7 @@ typedef struct {
   uint64_t seed;      /* density-noise seed                                */
   double noise_amp;   /* relative amplitude of the density noise           */
   double GM, eps, L, mach, chi; /* perturber and gas parameters            */
+  int subcycle;       /* 0: two sub-steps per level; 1: App. A criterion    */
 } dfo_params;
 
 typedef struct {
@@ -66,6 +67,7 @@ typedef struct {
   lev_t lev[DFO_MAXLEV];
   double t, dt_last, bflux, e0, V;
   long nsteps;
+  int xi[DFO_MAXLEV];    /* sub-steps of level l+1 per step of level l       */
 } run_t;
 
 /* ------------------------------------------------------------------ index */
@@ -700,8 +702,8 @@ static void cycle(run_t *R, int lvl, double dt) {
       for (int side = 0; side < 2; ++side)
         for (int iq = 0; iq < NQ; ++iq) memset(F->acc[d][side][iq], 0, na * sizeof(double));
     }
-    cycle(R, lvl + 1, 0.5 * dt);
-    cycle(R, lvl + 1, 0.5 * dt);
+    /* xi sub-steps of the finer level, each of dt / xi */
+    for (int sub = 0; sub < R->xi[lvl]; ++sub) cycle(R, lvl + 1, R->xi[lvl] == 2 ? 0.5 * dt : dt);
   }
   hydro_step(R, lvl, dt);
   if (lvl < R->nl - 1) {
@@ -711,13 +713,11 @@ static void cycle(run_t *R, int lvl, double dt) {
 }
 
 /* ------------------------------------------------------------- time step */
-/* Time step: the Courant limit on each level, dx / max(c_s + |v|) over the
- * active cells and their face velocities, c_s = sqrt(gamma (gamma-1) e/rho),
+/* Time-step limit of each level: the Courant limit dx / max(c_s + |v|) over
+ * the active cells and their face velocities, c_s = sqrt(gamma (gamma-1) e/rho),
  * and (reading: the paper does not state it) the explicit-diffusion limit
- * dx^2 / (6 chi); with two sub-cycles per level the coarse step is
- * cfl * min_l 2^l dt_l (eq. 55 with xi = 2). */
-static double dt_rule(run_t *R) {
-  double best = INFINITY;
+ * dx^2 / (6 chi), times the Courant factor: dtl[l] = cfl * min(...). */
+static void level_limits(run_t *R, double *dtl) {
   double gg = R->p.gamma * (R->p.gamma - 1.0);
   for (int l = 0; l < R->nl; ++l) {
     lev_t *L = &R->lev[l];
@@ -735,15 +735,59 @@ static double dt_rule(run_t *R) {
             if (sig > smax) smax = sig;
           }
         }
-    double dtl = L->dx / smax;
+    double dt = L->dx / smax;
     if (R->p.chi > 0.0) {
       double dd = L->dx * L->dx / (6.0 * R->p.chi);
-      if (dd < dtl) dtl = dd;
+      if (dd < dt) dt = dd;
     }
-    dtl *= (double)(1L << l);
-    if (dtl < best) best = dtl;
+    dtl[l] = R->p.cfl * dt;
   }
-  return R->p.cfl * best;
+}
+
+/* Coarse step of a schedule xi (eq. 55): min over levels of dtl[l] times the
+ * product of xi[m] for m < l. */
+static double schedule_dt(int nl, const double *dtl, const int *xi) {
+  double best = INFINITY, prod = 1.0;
+  for (int l = 0; l < nl; ++l) {
+    double v = dtl[l] * prod;
+    if (v < best) best = v;
+    if (l < nl - 1) prod *= (double)xi[l];
+  }
+  return best;
+}
+
+/* Sub-cycling criterion of App. A: among the 2^(n-1) words xi in {1,2}^(n-1)
+ * the one of largest coarse step (eq. 55) per cost (eq. 56, the cost of a level
+ * step taken as its active cell count); words are tried from all-2 downwards
+ * (xi[m] = 2 where bit m of the word is set) and a later word must do strictly
+ * better, so ties keep the most sub-cycling.  Without the criterion xi = 2. */
+static void choose_schedule(int nl, const double *dtl, const double *cost, int use_criterion, int *xi) {
+  for (int m = 0; m < nl - 1; ++m) xi[m] = 2;
+  if (!use_criterion || nl < 2) return;
+  double best = -1.0;
+  int cand[DFO_MAXLEV];
+  for (long w = (1L << (nl - 1)) - 1; w >= 0; --w) {
+    for (int m = 0; m < nl - 1; ++m) cand[m] = (w >> m) & 1 ? 2 : 1;
+    double c = 0.0, prod = 1.0;
+    for (int l = 0; l < nl; ++l) {
+      c += cost[l] * prod;
+      if (l < nl - 1) prod *= (double)cand[l];
+    }
+    double r = schedule_dt(nl, dtl, cand) / c;
+    if (r > best) {
+      best = r;
+      for (int m = 0; m < nl - 1; ++m) xi[m] = cand[m];
+    }
+  }
+}
+
+/* Coarse step of the current state; sets R->xi. */
+static double dt_rule(run_t *R) {
+  double dtl[DFO_MAXLEV], cost[DFO_MAXLEV];
+  level_limits(R, dtl);
+  for (int l = 0; l < R->nl; ++l) cost[l] = (double)R->lev[l].n[0] * R->lev[l].n[1] * R->lev[l].n[2];
+  choose_schedule(R->nl, dtl, cost, R->p.subcycle, R->xi);
+  return schedule_dt(R->nl, dtl, R->xi);
 }
 
 /* ---------------------------------------------------------------- force */
@@ -883,6 +927,7 @@ void *dfo_create(const dfo_params *p) {
   run_t *R = (run_t *)calloc(1, sizeof(run_t));
   R->p = *p;
   R->nl = p->nlevels;
+  for (int m = 0; m < DFO_MAXLEV; ++m) R->xi[m] = 2;
   R->V = p->mach * p->cs;
   R->e0 = p->rho0 * p->cs * p->cs / (p->gamma * (p->gamma - 1.0));
   for (int l = 0; l < R->nl; ++l) {
@@ -941,6 +986,17 @@ void dfo_step(void *h, int n) {
 
 double dfo_time(void *h) { return ((run_t *)h)->t; }
 double dfo_dt(void *h) { return dt_rule((run_t *)h); }
+
+/* sub-steps per level of the last coarse step (nl-1 entries) */
+void dfo_schedule(void *h, int *xi) {
+  run_t *R = (run_t *)h;
+  for (int m = 0; m < R->nl - 1; ++m) xi[m] = R->xi[m];
+}
+
+/* the criterion alone, for given per-level limits and costs (tests) */
+void dfo_choose_schedule(int nl, const double *dtl, const double *cost, int use_criterion, int *xi) {
+  choose_schedule(nl, dtl, cost, use_criterion, xi);
+}
 
 /* OpenMP threads of the cell loops (timing only; results do not depend on it) */
 void dfo_set_threads(int n) {

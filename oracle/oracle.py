@@ -40,6 +40,7 @@ class _Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("GM", ctypes.c_double), ("eps", ctypes.c_double), ("L", ctypes.c_double),
         ("mach", ctypes.c_double), ("chi", ctypes.c_double),
+        ("subcycle", ctypes.c_int),
     ]
 
 
@@ -75,6 +76,10 @@ def _load():
         lib.dfo_heat_weights.argtypes = [vp, ip, dp]
         lib.dfo_set_threads.argtypes = [ip]
         lib.dfo_set_threads.restype = None
+        lib.dfo_schedule.argtypes = [vp, ctypes.POINTER(ip)]
+        lib.dfo_schedule.restype = None
+        lib.dfo_choose_schedule.argtypes = [ip, dp, dp, ip, ctypes.POINTER(ip)]
+        lib.dfo_choose_schedule.restype = None
         _lib = lib
     return _lib
 
@@ -93,7 +98,7 @@ class Oracle:
 
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0=None, gamma=5.0 / 3.0,
                  cfl=0.4, rho0=1.0, cs=1.0, seed=1, noise_amp=1e-6, GM=0.01, eps=0.0,
-                 L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None):
+                 L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None, subcycle=0):
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         if dx0 is None:
@@ -103,7 +108,7 @@ class Oracle:
             _load().dfo_set_threads(int(threads))
         self._lib = _load()
         self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
-                         noise_amp, GM, eps, L, mach, chi)
+                         noise_amp, GM, eps, L, mach, chi, int(subcycle))
         self.n = (nx, ny, nz)
         self.nlevels = nlevels
         self.g = [g0] + [gf] * (nlevels - 1)
@@ -127,6 +132,12 @@ class Oracle:
 
     def dt(self) -> float:
         return self._lib.dfo_dt(self._h)
+
+    def schedule(self) -> list:
+        """sub-steps of level l+1 per step of level l in the last coarse step"""
+        xi = (ctypes.c_int * max(1, self.nlevels - 1))()
+        self._lib.dfo_schedule(self._h, xi)
+        return list(xi)[: self.nlevels - 1]
 
     @property
     def time(self) -> float:
@@ -213,3 +224,14 @@ class Oracle:
 
     def state(self, level: int = 0, ghosts: bool = False) -> dict:
         return {k: self.field(level, k, ghosts) for k in FIELDS}
+
+
+def choose_schedule(dtl, cost, use_criterion=True) -> list:
+    """App. A: the word xi in {1,2}^(n-1) maximising the coarse step (eq. 55)
+    per cost (eq. 56) for per-level limits dtl and per-level-step costs"""
+    nl = len(dtl)
+    xi = (ctypes.c_int * max(1, nl - 1))()
+    a = np.ascontiguousarray(dtl, dtype=np.float64)
+    c = np.ascontiguousarray(cost, dtype=np.float64)
+    _load().dfo_choose_schedule(nl, _dp(a), _dp(c), int(use_criterion), xi)
+    return list(xi)[: nl - 1]

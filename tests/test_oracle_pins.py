@@ -408,3 +408,62 @@ def test_contact_advection_converges():
     e1, e2 = _advection_error(64), _advection_error(128)
     assert e2 < 0.03
     assert e1 / e2 > 2.5, (e1, e2)
+
+
+# ------------------------------------------------- sub-cycling criterion (App. A)
+
+@pytest.mark.parametrize("K,flat", [(0.55, False), (0.6, False), (0.65, False), (0.68, True), (0.8, True),
+                                    (0.95, True)])
+def test_subcycling_criterion_two_level_threshold(K, flat):
+    # App. A's example: one refinement level of the same cost, fine limit
+    # K dt0 with 1/2 < K < 1: sub-cycling gives dt0 / 3C, the flat step K dt0 /
+    # 2C, so the flat step is chosen exactly when K > 2/3
+    from oracle.oracle import choose_schedule
+
+    assert choose_schedule([1.0, K], [1.0, 1.0]) == ([1] if flat else [2])
+    assert choose_schedule([1.0, K], [1.0, 1.0], use_criterion=False) == [2]
+
+
+def test_subcycling_criterion_keeps_two_on_the_nested_setup():
+    # on the paper's kind of setup (limits halving level by level) the
+    # criterion falls back to two sub-steps everywhere (end of App. A): the run
+    # is bitwise the one without the criterion
+    kw = dict(nlevels=3, dx0=0.32, GM=1e-3, eps=0.0, L=5e-4, mach=0.3, chi=0.1, noise_amp=1e-4, seed=5)
+    a = Oracle(16, 16, 16, subcycle=1, **kw)
+    b = Oracle(16, 16, 16, subcycle=0, **kw)
+    for _ in range(3):
+        a.step(1)
+        b.step(1)
+        assert a.schedule() == [2, 2]
+    for lev in range(3):
+        for name in ("rho", "e", "vx"):
+            assert np.array_equal(a.field(lev, name), b.field(lev, name))
+
+
+def _fast_coarse_pair(subcycle):
+    # adiabatic two-level run whose level 0 carries an extra -1 in vx outside
+    # the refined box: its signal speed 2.5 against 1.5 on level 1 makes the
+    # fine limit 0.83 of the coarse one, so the criterion takes one fine step
+    o = Oracle(16, 16, 16, nlevels=2, dx0=0.16, GM=0.01, eps=0.04, L=0.0, mach=0.5, chi=0.0,
+               noise_amp=1e-3, seed=13, subcycle=subcycle)
+    vx = o.full_field(0, "vx")
+    vx[:, :, :3] -= 1.0
+    o.set_full_field(0, "vx", vx)
+    return o
+
+
+def test_flat_step_chosen_and_conserves_composite_mass():
+    o = _fast_coarse_pair(1)
+    m0 = o.totals()[0]
+    o.step(3)
+    assert o.schedule() == [1]
+    m1, _, _, inflow = o.totals()
+    assert abs((m1 - m0) - inflow) < 1e-14 * m0 * 16, (m1 - m0, inflow)
+
+
+def test_flat_step_is_the_fine_limit():
+    # eq. 55 with xi = 1: the coarse step is min(dt0, dt1) = dt1 = K dt0 here,
+    # against dt0 with sub-cycling (K ~ 0.83 from the signal speeds)
+    flat, sub = _fast_coarse_pair(1), _fast_coarse_pair(0)
+    r = flat.dt() / sub.dt()
+    assert 0.78 < r < 0.88, r
