@@ -140,6 +140,23 @@ int df_sync_levels(df_run *run);
 /* The coarse time step the next df_step would take (synchronises). */
 int df_get_dt(df_run *run, double *dt);
 
+/* Sub-cycling of the nested levels (App. A, eqs. 55-56).  mode 0 (default):
+ * every level takes two steps per step of the next coarser one (xi = 2).
+ * mode 1: at the start of each coarse step the per-level step limits
+ * dt_l = cfl min(dx_l / max(c_s + |v|), dx_l^2 / (6 chi)) are read back and the
+ * word xi in {1,2}^(nlevels-1) of largest coarse step min_l dt_l prod_{m<l}
+ * xi_m per cost sum_l C_l prod_{m<l} xi_m is taken, C_l being the active cell
+ * count of level l; words are tried from all-2 down (xi_m = 2 where bit m of
+ * the word is set) and a later word must do strictly better.  In mode 1
+ * df_step synchronises once per coarse step (the engine's jobs always use
+ * mode 0).  DF_EINVAL for other modes. */
+int df_set_subcycling(df_run *run, int32_t mode);
+
+/* xi_l (sub-steps of level l+1 per step of level l) of the last coarse step
+ * into xi[0 .. nlevels-2]; n is the capacity of xi (DF_EINVAL if below
+ * nlevels-1). */
+int df_get_schedule(df_run *run, int32_t *xi, int32_t n);
+
 /* Run one stage of the level update on a single-level run, with step dt:
  *  1 velocity kick over dt, 2 compressional heating, 3 thermal diffusion,
  *  4 heat release, 5 transport, 6 stages 2-4, 7 a whole level step.

@@ -70,6 +70,8 @@ def _load():
         "df_timing_enable": [vp, i32],
         "df_timing_read": [vp, dp, ctypes.POINTER(i32), i32],
         "df_stream_copy": [vp, vp, ctypes.c_size_t, vp],
+        "df_set_subcycling": [vp, i32],
+        "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -250,6 +252,17 @@ class Run:
 
     def dt(self):
         return get_dt(self._h)
+
+    def set_subcycling(self, mode: int) -> None:
+        """0: two sub-steps per level; 1: the criterion of App. A each coarse step"""
+        _ck(_load().df_set_subcycling(self._h, int(mode)))
+
+    def schedule(self) -> list:
+        """sub-steps of level l+1 per step of level l in the last coarse step"""
+        n = max(1, self.nlevels - 1)
+        xi = (ctypes.c_int32 * n)()
+        _ck(_load().df_get_schedule(self._h, xi, n))
+        return list(xi)[: self.nlevels - 1]
 
     def force_log(self, cap=4096):
         return force_log(self._h, cap)

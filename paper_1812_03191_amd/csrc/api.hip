@@ -9,6 +9,7 @@
 // Every launch goes to the caller's stream; nothing in df_step waits on the
 // device, so a sequence of steps can be captured into a HIP graph.
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -66,6 +67,9 @@ struct df_run {
   bool bound = false;
   bool ready = false;
   bool sig_valid = false;  // the signal-speed partials are those of the current state
+  int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
+  int xi[MAXLEV];          // sub-steps of level l+1 per step of level l (last coarse step)
+  double up[MAXLEV + 1];   // staging of the host-chosen step lengths and time
   double eps = 0.0;
   // optional per-kernel-kind timing: event pairs around launches
   bool timing = false;
@@ -188,8 +192,7 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
 void cycle(df_run *R, int l) {
   if (l + 1 < R->nl) {
     { TScope t(R, K_ZERO); dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1] * R->esz); }
-    cycle(R, l + 1);
-    cycle(R, l + 1);
+    for (int sub = 0; sub < R->xi[l]; ++sub) cycle(R, l + 1);
   }
   level_step(R, l, &R->scal->dt[l], 1.0);
   if (l + 1 < R->nl) {
@@ -251,6 +254,57 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 void post_reduce(df_run *R) {
   for (int l = 0; l < R->nl; ++l) dfk::post_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->scal);
   R->sig_valid = true;
+}
+
+// Sub-cycling criterion of App. A on the host: for per-level limits dtl and
+// costs of one level step taken as its active cells, the word xi in {1,2}^(nl-1)
+// of largest coarse step min_l dtl[l] prod_{m<l} xi[m] (eq. 55) per cost
+// sum_l C_l prod_{m<l} xi[m] (eq. 56).  Words are tried from all-2 down (bit m
+// set: xi[m] = 2) and a later word must do strictly better.  Returns the
+// coarse step.
+double schedule_criterion(const df_run *R, const double *dtl, int *xi) {
+  const int nl = R->nl;
+  double best_ratio = -1.0, best_dt = 0.0;
+  for (long w = (1L << (nl - 1)) - 1; w >= 0; --w) {
+    double dt = INFINITY, cost = 0.0, mult = 1.0;
+    for (int l = 0; l < nl; ++l) {
+      dt = fmin(dt, dtl[l] * mult);
+      cost += (double)R->geo[l].n[0] * R->geo[l].n[1] * R->geo[l].n[2] * mult;
+      if (l + 1 < nl) mult *= ((w >> l) & 1) ? 2.0 : 1.0;
+    }
+    const double ratio = dt / cost;
+    if (ratio > best_ratio) {
+      best_ratio = ratio;
+      best_dt = dt;
+      for (int m = 0; m + 1 < nl; ++m) xi[m] = ((w >> m) & 1) ? 2 : 1;
+    }
+  }
+  return best_dt;
+}
+
+static_assert(offsetof(Scal, t) == MAXLEV * sizeof(double), "the step lengths and the time are uploaded together");
+
+// one coarse step under the criterion: read the per-level limits back, choose
+// the schedule, upload the step lengths and the new time, advance, log the force
+int criterion_step(df_run *R) {
+  if (!R->sig_valid) post_reduce(R);
+  dfk::step_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, R->flog, 0, 2);
+  Scal h;
+  int rc = hip_check(hipMemcpyAsync(&h, R->scal, sizeof(Scal), hipMemcpyDeviceToHost, R->stream), "limits copy");
+  if (!rc) rc = hip_check(hipStreamSynchronize(R->stream), "limits copy");
+  if (rc) return rc;
+  const double dt0 = schedule_criterion(R, h.dtl, R->xi);
+  for (int l = 0; l < MAXLEV; ++l) R->up[l] = 0.0;
+  R->up[0] = dt0;
+  for (int l = 1; l < R->nl; ++l) R->up[l] = R->xi[l - 1] == 2 ? 0.5 * R->up[l - 1] : R->up[l - 1];
+  R->up[MAXLEV] = h.t + dt0;  // dt[] and t are adjacent in Scal
+  rc = hip_check(hipMemcpyAsync(R->scal->dt, R->up, sizeof(R->up), hipMemcpyHostToDevice, R->stream),
+                 "step upload");
+  if (rc) return rc;
+  cycle(R, 0);
+  post_reduce(R);
+  dfk::step_final(R->stream, R->geo, R->buf, R->nl, R->phys, R->scal, R->flog, 1, 0);
+  return launch_check("df_step");
 }
 
 // n coarse steps, each: time step from the signal speeds of the state,
@@ -321,6 +375,7 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   R->nl = d->nlevels;
   R->esz = d->precision == DF_FP32 ? 4 : 8;
   R->chunk = d->tile_chunk ? d->tile_chunk : (d->precision == DF_FP32 ? 16 : 32);
+  for (int m = 0; m < MAXLEV; ++m) R->xi[m] = 2;
   R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
@@ -439,8 +494,32 @@ int df_step(df_run *R, int32_t n) {
   int rc = check_run(R, true);
   if (rc) return rc;
   if (n < 0) return fail(DF_EINVAL, "negative step count");
+  if (R->subcycle == 1 && R->nl > 1) {
+    for (int s = 0; s < n; ++s) {
+      rc = criterion_step(R);
+      if (rc) return rc;
+    }
+    return DF_OK;
+  }
   enqueue_steps(R, n);
   return launch_check("df_step");
+}
+
+int df_set_subcycling(df_run *R, int32_t mode) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (mode != 0 && mode != 1) return fail(DF_EINVAL, "sub-cycling mode must be 0 or 1");
+  R->subcycle = mode;
+  for (int m = 0; m < MAXLEV; ++m) R->xi[m] = 2;
+  return DF_OK;
+}
+
+int df_get_schedule(df_run *R, int32_t *xi, int32_t n) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (!xi || n < R->nl - 1) return fail(DF_EINVAL, "schedule output needs nlevels-1 entries");
+  for (int m = 0; m + 1 < R->nl; ++m) xi[m] = R->xi[m];
+  return DF_OK;
 }
 
 static int reduce3(df_run *R, int slot, double out[4]) {
@@ -556,6 +635,10 @@ int df_get_dt(df_run *R, double *dt) {
   if (rc) return rc;
   rc = hip_check(hipStreamSynchronize(R->stream), "dt copy");
   *dt = h.dt[0];
+  if (R->subcycle == 1 && R->nl > 1) {
+    int xi[MAXLEV];
+    *dt = schedule_criterion(R, h.dtl, xi);
+  }
   return rc;
 }
 

@@ -50,6 +50,7 @@ struct Scal {
   double totals[3];
   int health;                // bit 0: a non-positive or non-finite rho or e seen
   unsigned int nlog;         // force-log entries written so far
+  double dtl[MAXLEV];        // per-level step limits cfl min(dx/smax, dx^2/6chi) of the last time step
 };
 
 constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
@@ -104,8 +105,9 @@ int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int 
 // next time step (as signal_speed) of the current state, in one pass
 void post_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);
 // one block: with do_force the force of the partials of post_partials over
-// all levels, appended to the log; then with do_dt the time step from their
-// signal speeds, advancing the time
+// all levels, appended to the log; then with do_dt = 1 the time step from
+// their signal speeds (two sub-steps per level), advancing the time, with
+// do_dt = 2 only each level's own step limit into S->dtl
 void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P, Scal *S, double *flog,
                 int do_force, int do_dt);
 // slot 0: S->force; slot 1: S->totals; slot 2: S->force and the force log

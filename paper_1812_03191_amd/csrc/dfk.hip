@@ -1496,6 +1496,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
 }
 
 struct DtArgs {
+  // advance: 0 set dt, 1 set dt and advance the time, 2 per-level limits only
   double dx[MAXLEV];
   const double *part[MAXLEV];  // per-block maximum signal speeds of each level
   int npart[MAXLEV];
@@ -1535,9 +1536,11 @@ __device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
   for (int l = 0; l < A.nl; ++l) {
     double dtl = A.dx[l] / smax[l];
     if (P.chi > 0.0) dtl = fmin(dtl, A.dx[l] * A.dx[l] / (6.0 * P.chi));
+    S->dtl[l] = P.cfl * dtl;  // the level's own limit (for the sub-cycling criterion)
     dtl = ldexp(dtl, l);
     best = fmin(best, dtl);
   }
+  if (A.advance == 2) return;  // limits only: the host sets the schedule
   const double dt0 = P.cfl * best;
   for (int l = 0; l < A.nl; ++l) S->dt[l] = ldexp(dt0, -l);
   if (A.advance) S->t += dt0;
@@ -1946,7 +1949,7 @@ void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P,
     np[l] = (int)part_count(G[l]);
   }
   hipLaunchKernelGGL(k_step_final, dim3(1), dim3(FT), 0, st, P, final_args(parts, np, nl, S, 2, flog),
-                     dt_args(G, B, nl, 1), S, do_force, do_dt);
+                     dt_args(G, B, nl, do_dt == 2 ? 2 : 1), S, do_force, do_dt);
 }
 
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {

@@ -183,6 +183,62 @@ def test_nested_parity(dfm, nl, n, steps):
     assert fe < 1e-9, (fg, fo)
 
 
+# ------------------------------------------- sub-cycling criterion (App. A)
+
+def _fast_coarse(dfm, nl, steps):
+    # adiabatic nested run whose level 0 carries an extra -1 in vx outside the
+    # refined box (signal speed 2.5 against 1.5 on the finer levels): the
+    # criterion takes one level-1 step per coarse step
+    from oracle.oracle import Oracle
+
+    kw = dict(nlevels=nl, dx0=0.16, GM=0.01, eps=0.04, L=0.0, mach=0.5, chi=0.0, noise_amp=1e-3, seed=13)
+    o = Oracle(16, 16, 16, subcycle=1, **kw)
+    g = dfm.Run(16, 16, 16, nlevels=nl, dx0=0.16, seed=13, noise_amp=1e-3)
+    g.set_perturber(0.01, 0.04, 0.0, 0.5, 0.0)
+    g.set_subcycling(1)
+    vx = o.full_field(0, "vx")
+    vx[:, :, :3] -= 1.0
+    o.set_full_field(0, "vx", vx)
+    g.set_field(0, "vx", vx)
+    sched = []
+    for _ in range(steps):
+        o.step(1)
+        g.step(1)
+        assert g.schedule() == o.schedule()
+        sched.append(o.schedule())
+    return o, g, sched
+
+
+@pytest.mark.parametrize("nl,want", [(2, [1]), (3, [1, 2])])
+def test_subcycling_criterion_parity(dfm, nl, want):
+    _say(f"[parity] sub-cycling criterion, {nl} levels")
+    o, g, sched = _fast_coarse(dfm, nl, 3)
+    assert sched[0] == want, sched
+    errs = _field_errors(o, g, nl)
+    assert max(errs.values()) < 1e-11, {k: v for k, v in errs.items() if v > 1e-13}
+    fe, fg, fo = _force_err(o, g)
+    assert fe < 1e-9, (fg, fo)
+    assert abs(g.force()[3] - o.time) < 1e-14 * o.time
+
+
+def test_subcycling_criterion_keeps_two_on_nested_setup(dfm):
+    # limits halving level by level: the criterion keeps xi = 2 and the run is
+    # bitwise the default one
+    cfg = inputs.job(16, 3, 0.3, 1e-3, 0.1, 1e-3, seed=3)
+    _say("[parity] sub-cycling criterion on the nested setup")
+    _, a = _pair(dfm, cfg)
+    _, b = _pair(dfm, cfg)
+    a.set_subcycling(1)
+    for _ in range(3):
+        a.step(1)
+        b.step(1)
+        assert a.schedule() == [2, 2]
+    for lev in range(3):
+        for name in FIELD_NAMES:
+            assert np.array_equal(a.field(lev, name), b.field(lev, name)), (lev, name)
+    assert np.array_equal(a.force(), b.force())
+
+
 def test_nested_wider_ghosts_parity(dfm):
     cfg = inputs.job(16, 2, 0.6, 5e-3, 0.1, 1e-3, seed=8)
     _say("[parity] nested ghost width 12")
