@@ -60,18 +60,71 @@ def _fraction(mach, nlevels, n):
     return float(T.h_fraction(rmax) - T.h_fraction(dxf / (2 * lam)))
 
 
-def test_low_mach_heating_force(dfm):
-    # Mach 0.1, L = 2e-4 (Sect. 4.1), 5 levels of 64^3: r' from 0.1 to 51.2;
-    # after 50 tau the heating force is within 5 % of M a(eq. 8) (h(r'max) - h(r'min))
-    mach, nl, n, L = 0.1, 5, 64, 2e-4
+LOW = dict(mach=0.1, nl=5, n=64, L=2e-4)
+
+
+@pytest.fixture(scope="module")
+def low_mach_pair(dfm):
+    # Mach 0.1, L = 2e-4 (Sect. 4.1), 5 levels of 64^3 (r' from 0.1 to 51.2):
+    # the hot and the cold run at 50 tau, force logs and finest-level densities
+    mach, nl, n = LOW["mach"], LOW["nl"], LOW["n"]
+    lam = CHI / (GAMMA * mach)
     tau = T.response_time(CHI, GAMMA, mach)
-    hot = _force_at(dfm, mach, nl, n, L, CHI, 50 * tau)
-    cold = _force_at(dfm, mach, nl, n, 0.0, CHI, 50 * tau)
-    want = GM * T.heating_accel_lowmach(GAMMA, 1.0, L, CHI) * _fraction(mach, nl, n)
+    out = {}
+    for lum in (LOW["L"], 0.0):
+        r = dfm.Run(n, nlevels=nl, dx0=lam / 5.0 * 2 ** (nl - 1), noise_amp=0.0, precision=dfm.DF_FP32)
+        r.set_perturber(GM, 0.0, lum, mach, CHI)
+        while r.force()[3] < 50 * tau:
+            r.step(50)
+        log = r.force_log()
+        out[lum] = (log[min(int(np.searchsorted(log[:, 3], 50 * tau)), len(log) - 1)], r.field(nl - 1, "rho"))
+    return out
+
+
+def test_low_mach_heating_force(dfm, low_mach_pair):
+    # after 50 tau the heating force is within 5 % of M a(eq. 8) (h(r'max) - h(r'min))
+    hot, cold = low_mach_pair[LOW["L"]][0], low_mach_pair[0.0][0]
+    want = GM * T.heating_accel_lowmach(GAMMA, 1.0, LOW["L"], CHI) * _fraction(LOW["mach"], LOW["nl"], LOW["n"])
     got = hot[0] - cold[0]
     _say(f"[physics] heating force {got:.5e} vs {want:.5e} (ratio {got / want:.4f})")
     assert got > 0.0
     assert abs(got / want - 1.0) < 0.05
+
+
+def test_low_mach_density_profile_cuts(dfm, low_mach_pair):
+    # Sect. 4.1.1, Fig. 8: the hot-minus-cold density on the finest level along
+    # the flow axis and across it follows eq. 6: an inverse law downstream, a
+    # cut-off exp(-r / lambda) upstream and exp(-r / 2 lambda) transversally.
+    # The gas moves along -x here (eq. 6's z is -x); each cut averages the four
+    # cells around its axis and eq. 6 is averaged over the same four centres.
+    mach, nl, n, L = LOW["mach"], LOW["nl"], LOW["n"], LOW["L"]
+    lam = CHI / (GAMMA * mach)
+    dx = lam / 5.0
+    d = low_mach_pair[L][1] - low_mach_pair[0.0][1]  # (z, y, x)
+    c = n // 2
+    xs = (np.arange(n) - n / 2 + 0.5) * dx
+    h = dx / 2
+
+    def eq6(x, y, z):  # our coordinates; eq. 6's z axis is -x
+        return T.heating_density_lowmach(y, z, -x, GAMMA, L, CHI, mach)
+
+    worst = {"downstream": 0.0, "upstream": 0.0, "transverse": 0.0}
+    for i in range(n):
+        x = xs[i]
+        got = 0.25 * (d[c - 1, c - 1, i] + d[c - 1, c, i] + d[c, c - 1, i] + d[c, c, i])
+        want = eq6(x, h, h)
+        if -4.8 * lam < x < -1.4 * lam:
+            worst["downstream"] = max(worst["downstream"], abs(got / want - 1.0))
+        if 0.8 * lam < x < 2.0 * lam:
+            worst["upstream"] = max(worst["upstream"], abs(got / want - 1.0))
+    for j in range(c, n):
+        y = xs[j]
+        got = 0.25 * (d[c - 1, j, c - 1] + d[c - 1, j, c] + d[c, j, c - 1] + d[c, j, c])
+        want = 0.5 * (eq6(-h, y, h) + eq6(h, y, h))
+        if 0.8 * lam < y < 5.0 * lam:
+            worst["transverse"] = max(worst["transverse"], abs(got / want - 1.0))
+    _say(f"[physics] eq. 6 cuts, largest relative deviation {worst}")
+    assert worst["downstream"] < 0.01 and worst["upstream"] < 0.035 and worst["transverse"] < 0.03, worst
 
 
 def test_low_mach_cold_thermal_force(dfm):
