@@ -48,6 +48,7 @@ typedef struct {
   double noise_amp;   /* relative amplitude of the density noise           */
   double GM, eps, L, mach, chi; /* perturber and gas parameters            */
   int subcycle;       /* 0: two sub-steps per level; 1: App. A criterion    */
+  int bcmode;         /* level-0 boundaries: 0 inflow/outflow; 1 Sect. 3.4  */
 } dfo_params;
 
 typedef struct {
@@ -136,37 +137,90 @@ static box_t box_cells_1(const lev_t *L, int lvl) {
 }
 
 /* --------------------------------------------------- boundary conditions */
-/* Level-0 boundaries (reading of Sect. 3.4 for a full box with the gas
+/* Level-0 boundaries, mode 0 (reading of Sect. 3.4 for a full box with the gas
  * entering through x_max): the upstream ghosts hold the unperturbed inflow
  * state (rho0, -V, 0, 0, e0); every other ghost copies the nearest active
  * cell (centred fields and tangential velocities) or the boundary face
- * (normal velocity), i.e. zero-gradient outflow. */
+ * (normal velocity), i.e. zero-gradient outflow.
+ * Mode 1 (the boundary list of Sect. 3.4, with the flow along x and the full
+ * box, of which the paper's quadrant is one quarter by symmetry): at both
+ * flow ends the ghosts hold rho0, -V (normal velocity) and e0 and the
+ * tangential velocities are mirror-symmetric; at the four transverse walls
+ * every field is mirror-symmetric except the normal velocity, which is
+ * antisymmetric (zero on the wall). */
 
-/* centred field; qin = inflow value */
-static void bc_centred(const run_t *R, lev_t *L, double *a, double qin) {
-  (void)R;
+/* mirror index of a ghost across the low (idx < 0) or high (idx >= n) side */
+static inline int mirror(int idx, int n) { return idx < 0 ? -1 - idx : (idx >= n ? 2 * n - 1 - idx : idx); }
+
+/* centred field; qin = the value held at the flow ends (inflow in mode 0);
+ * xdir: mode 1 holds qin at both flow ends (else mirror-symmetric there) */
+static void bc_centred_x(const run_t *R, lev_t *L, double *a, double qin, int xdir) {
   int g = L->g, nx = L->n[0], ny = L->n[1], nz = L->n[2];
+  int m1 = R->p.bcmode == 1;
   for (int k = -g; k < nz + g; ++k)
     for (int j = -g; j < ny + g; ++j) {
-      for (int i = nx; i < nx + g; ++i) a[IX(L, i, j, k)] = qin;
-      for (int i = -g; i < 0; ++i) a[IX(L, i, j, k)] = a[IX(L, 0, j, k)];
+      for (int i = nx; i < nx + g; ++i)
+        a[IX(L, i, j, k)] = (m1 && !xdir) ? a[IX(L, mirror(i, nx), j, k)] : qin;
+      for (int i = -g; i < 0; ++i)
+        a[IX(L, i, j, k)] = m1 ? (xdir ? qin : a[IX(L, mirror(i, nx), j, k)]) : a[IX(L, 0, j, k)];
     }
   for (int k = -g; k < nz + g; ++k)
     for (int i = -g; i < nx + g; ++i) {
-      for (int j = -g; j < 0; ++j) a[IX(L, i, j, k)] = a[IX(L, i, 0, k)];
-      for (int j = ny; j < ny + g; ++j) a[IX(L, i, j, k)] = a[IX(L, i, ny - 1, k)];
+      for (int j = -g; j < 0; ++j) a[IX(L, i, j, k)] = a[IX(L, i, m1 ? mirror(j, ny) : 0, k)];
+      for (int j = ny; j < ny + g; ++j) a[IX(L, i, j, k)] = a[IX(L, i, m1 ? mirror(j, ny) : ny - 1, k)];
     }
   for (int j = -g; j < ny + g; ++j)
     for (int i = -g; i < nx + g; ++i) {
-      for (int k = -g; k < 0; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, 0)];
-      for (int k = nz; k < nz + g; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, nz - 1)];
+      for (int k = -g; k < 0; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, m1 ? mirror(k, nz) : 0)];
+      for (int k = nz; k < nz + g; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, m1 ? mirror(k, nz) : nz - 1)];
     }
 }
+
+static void bc_centred(const run_t *R, lev_t *L, double *a, double qin) { bc_centred_x(R, L, a, qin, 1); }
 
 /* velocity normal to faces of dimension dn; active faces are 0..n[dn] */
 static void bc_face(const run_t *R, lev_t *L, double *a, int dn) {
   int g = L->g, n[3] = {L->n[0], L->n[1], L->n[2]};
   int i, j, k;
+  if (R->p.bcmode == 1) {
+    /* x: flow ends */
+    for (k = -g; k < n[2] + g; ++k)
+      for (j = -g; j < n[1] + g; ++j) {
+        if (dn == 0) {
+          for (i = n[0]; i < n[0] + g; ++i) a[IX(L, i, j, k)] = -R->V;
+          for (i = -g; i < 0; ++i) a[IX(L, i, j, k)] = -R->V;
+        } else {
+          for (i = n[0]; i < n[0] + g; ++i) a[IX(L, i, j, k)] = a[IX(L, mirror(i, n[0]), j, k)];
+          for (i = -g; i < 0; ++i) a[IX(L, i, j, k)] = a[IX(L, mirror(i, n[0]), j, k)];
+        }
+      }
+    /* y, z: walls */
+    for (k = -g; k < n[2] + g; ++k)
+      for (i = -g; i < n[0] + g; ++i) {
+        if (dn == 1) {
+          a[IX(L, i, 0, k)] = 0.0;
+          a[IX(L, i, n[1], k)] = 0.0;
+          for (j = -g; j < 0; ++j) a[IX(L, i, j, k)] = -a[IX(L, i, -j, k)];
+          for (j = n[1] + 1; j < n[1] + g; ++j) a[IX(L, i, j, k)] = -a[IX(L, i, 2 * n[1] - j, k)];
+        } else {
+          for (j = -g; j < 0; ++j) a[IX(L, i, j, k)] = a[IX(L, i, mirror(j, n[1]), k)];
+          for (j = n[1]; j < n[1] + g; ++j) a[IX(L, i, j, k)] = a[IX(L, i, mirror(j, n[1]), k)];
+        }
+      }
+    for (j = -g; j < n[1] + g; ++j)
+      for (i = -g; i < n[0] + g; ++i) {
+        if (dn == 2) {
+          a[IX(L, i, j, 0)] = 0.0;
+          a[IX(L, i, j, n[2])] = 0.0;
+          for (k = -g; k < 0; ++k) a[IX(L, i, j, k)] = -a[IX(L, i, j, -k)];
+          for (k = n[2] + 1; k < n[2] + g; ++k) a[IX(L, i, j, k)] = -a[IX(L, i, j, 2 * n[2] - k)];
+        } else {
+          for (k = -g; k < 0; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, mirror(k, n[2]))];
+          for (k = n[2]; k < n[2] + g; ++k) a[IX(L, i, j, k)] = a[IX(L, i, j, mirror(k, n[2]))];
+        }
+      }
+    return;
+  }
   /* x */
   for (k = -g; k < n[2] + g; ++k)
     for (j = -g; j < n[1] + g; ++j) {
@@ -209,16 +263,59 @@ static double q_inflow(const run_t *R, int iq) {
   if (iq == 2 || iq == 3) return R->p.rho0 * (-R->V);
   return 0.0;
 }
-static void bc_q(run_t *R) {
-  lev_t *L = &R->lev[0];
-  for (int iq = 0; iq < NQ; ++iq) bc_centred(R, L, L->q[iq], q_inflow(R, iq));
+
+/* mode 1: the pair of momenta normal to a wall (P- = rho v(low face), P+ = rho
+ * v(high face)): the mirror of a cell has its faces swapped and the normal
+ * velocity reversed, so P-(ghost) = -P+(mirror cell) and P+(ghost) = -P-(mirror) */
+static void bc_wall_pair(lev_t *L, double *pm, double *pp, int d) {
+  int g = L->g, n[3] = {L->n[0], L->n[1], L->n[2]};
+  for (int a2 = -g; a2 < n[(d + 2) % 3] + g; ++a2)
+    for (int a1 = -g; a1 < n[(d + 1) % 3] + g; ++a1)
+      for (int side = 0; side < 2; ++side)
+        for (int t = 0; t < g; ++t) {
+          int id[3], im[3];
+          id[(d + 1) % 3] = im[(d + 1) % 3] = a1;
+          id[(d + 2) % 3] = im[(d + 2) % 3] = a2;
+          id[d] = side ? n[d] + t : -1 - t;
+          im[d] = mirror(id[d], n[d]);
+          size_t c = IX(L, id[0], id[1], id[2]), m = IX(L, im[0], im[1], im[2]);
+          pm[c] = -pp[m];
+          pp[c] = -pm[m];
+        }
 }
 
-/* reset the upstream (inflow) face of level 0 to the injection velocity */
+static void bc_q(run_t *R) {
+  lev_t *L = &R->lev[0];
+  if (R->p.bcmode != 1) {
+    for (int iq = 0; iq < NQ; ++iq) bc_centred(R, L, L->q[iq], q_inflow(R, iq));
+    return;
+  }
+  /* rho, e, P-x, P+x: background at the flow ends; the tangential momenta
+   * mirror-symmetric there; every quantity mirror-symmetric at the walls,
+   * then the wall-normal momentum pairs replaced by their reversed mirrors */
+  for (int iq = 0; iq < NQ; ++iq) bc_centred_x(R, L, L->q[iq], q_inflow(R, iq), iq < 4);
+  bc_wall_pair(L, L->q[4], L->q[5], 1);
+  bc_wall_pair(L, L->q[6], L->q[7], 2);
+}
+
+/* reset the upstream (inflow) face of level 0 to the injection velocity;
+ * mode 1 also holds the wall faces at zero normal velocity */
 static void reset_inflow_face(run_t *R) {
   lev_t *L = &R->lev[0];
   for (int k = -L->g; k < L->n[2] + L->g; ++k)
     for (int j = -L->g; j < L->n[1] + L->g; ++j) L->st[S_VX][IX(L, L->n[0], j, k)] = -R->V;
+  if (R->p.bcmode == 1) {
+    for (int k = -L->g; k < L->n[2] + L->g; ++k)
+      for (int i = -L->g; i < L->n[0] + L->g; ++i) {
+        L->st[S_VY][IX(L, i, 0, k)] = 0.0;
+        L->st[S_VY][IX(L, i, L->n[1], k)] = 0.0;
+      }
+    for (int j = -L->g; j < L->n[1] + L->g; ++j)
+      for (int i = -L->g; i < L->n[0] + L->g; ++i) {
+        L->st[S_VZ][IX(L, i, j, 0)] = 0.0;
+        L->st[S_VZ][IX(L, i, j, L->n[2])] = 0.0;
+      }
+  }
 }
 
 /* ------------------------------------------------------------------ kick */

@@ -467,3 +467,78 @@ def test_flat_step_is_the_fine_limit():
     flat, sub = _fast_coarse_pair(1), _fast_coarse_pair(0)
     r = flat.dt() / sub.dt()
     assert 0.78 < r < 0.88, r
+
+
+# --------------------------------------- the paper's boundary list (Sect. 3.4)
+
+def test_wall_boundaries_keep_uniform_flow():
+    # background state at both flow ends, mirror walls: uniform flow stays
+    # uniform bitwise on one and on two levels
+    for nl in (1, 2):
+        o = Oracle(16, 16, 16, nlevels=nl, dx0=0.05, GM=0.0, L=0.0, noise_amp=0.0, mach=0.7, chi=0.1,
+                   bcmode=1)
+        s0 = o.state()
+        o.step(10)
+        s1 = o.state()
+        for k in s0:
+            assert np.array_equal(s0[k], s1[k]), (nl, k)
+
+
+def _mirror_pair(ny, seed):
+    # state of the wide box (2 ny cells in y), mirror-symmetric about its
+    # centre plane: rho, e, vx, vz even, vy odd (zero on the plane)
+    rng = np.random.default_rng(seed)
+    nz, nx = 12, 16
+    half = {k: rng.uniform(-1, 1, size=(nz, ny, nx)) for k in ("rho", "e", "vx", "vz")}
+    vyh = rng.uniform(-1, 1, size=(nz, ny + 1, nx))
+    vyh[:, 0, :] = 0.0
+    vyh[:, -1, :] = 0.0
+    wide = {}
+    for k, a in half.items():
+        wide[k] = np.concatenate([a[:, ::-1, :], a], axis=1)
+    wide["vy"] = np.concatenate([-vyh[:, :0:-1, :], vyh], axis=1)  # faces 0..2ny
+    base = {"rho": 1.0, "e": E0, "vx": -0.6, "vz": 0.0}
+    amp = {"rho": 1e-3, "e": 1e-3, "vx": 1e-3, "vz": 1e-3}
+    full = {}
+    for k in ("rho", "e", "vx", "vz"):
+        w = base[k] + amp[k] * wide[k]
+        if k == "vx":  # faces along x: nx + 1, last face carries the wind
+            w = np.concatenate([w, np.full((nz, 2 * ny, 1), -0.6)], axis=2)
+        if k == "vz":
+            w = np.concatenate([w, w[-1:, :, :] * 0.0], axis=0)  # top wall face: zero
+        full[k] = w
+    full["vy"] = 1e-3 * wide["vy"]
+    return full
+
+
+def test_wall_is_a_mirror_plane():
+    # a box with a reflecting wall at y_min evolves exactly as the upper half of
+    # a box twice as wide with the mirror-image state (Sect. 3.4's symmetric /
+    # antisymmetric conditions, checked through the second ghost layer)
+    ny = 8
+    full = _mirror_pair(ny, 21)
+    kw = dict(dx0=0.05, GM=0.0, L=0.0, noise_amp=0.0, mach=0.6, chi=0.1, bcmode=1)
+    wide = Oracle(16, 2 * ny, 12, **kw)
+    half = Oracle(16, ny, 12, **kw)
+    for k, a in full.items():
+        wide.set_full_field(0, k, a)
+        if k == "vy":
+            half.set_full_field(0, k, a[:, ny:, :])
+        else:
+            half.set_full_field(0, k, a[:, ny:, :])
+    wide.step(6)
+    half.step(6)
+    for k in ("rho", "e", "vx", "vy", "vz"):
+        w = wide.full_field(0, k)[:, ny:, :]
+        h = half.full_field(0, k)
+        assert np.max(np.abs(w - h)) < 1e-15, (k, np.max(np.abs(w - h)))
+
+
+def test_wall_boundaries_mass_accounting():
+    # walls carry no mass; the change equals the net flow through the two ends
+    o = Oracle(16, 16, 16, dx0=0.06, GM=0.02, eps=0.12, L=2e-3, mach=0.9, chi=0.1, noise_amp=1e-3, seed=7,
+               bcmode=1)
+    m0 = o.totals()[0]
+    o.step(12)
+    m1, _, _, inflow = o.totals()
+    assert abs((m1 - m0) - inflow) < 2e-15 * m0 * 16
