@@ -152,6 +152,18 @@ int df_get_dt(df_run *run, double *dt);
  * mode 0).  DF_EINVAL for other modes. */
 int df_set_subcycling(df_run *run, int32_t mode);
 
+/* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
+ * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
+ * every other boundary is zero-gradient outflow.  mode 1: the paper's list,
+ * with the flow along x and the full box (of which the paper's quadrant is a
+ * quarter by symmetry): ghosts beyond both flow ends hold rho0, -V (normal
+ * velocity) and e0, with the tangential velocities mirror-symmetric; the
+ * four transverse boundaries are walls across which every field is
+ * mirror-symmetric except the normal velocity, which is antisymmetric (zero
+ * on the wall).  Takes effect from the next call that advances or reduces;
+ * DF_EINVAL for other modes. */
+int df_set_boundaries(df_run *run, int32_t mode);
+
 /* xi_l (sub-steps of level l+1 per step of level l) of the last coarse step
  * into xi[0 .. nlevels-2]; n is the capacity of xi (DF_EINVAL if below
  * nlevels-1). */

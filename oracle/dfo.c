@@ -290,10 +290,24 @@ static void bc_q(run_t *R) {
     for (int iq = 0; iq < NQ; ++iq) bc_centred(R, L, L->q[iq], q_inflow(R, iq));
     return;
   }
-  /* rho, e, P-x, P+x: background at the flow ends; the tangential momenta
-   * mirror-symmetric there; every quantity mirror-symmetric at the walls,
-   * then the wall-normal momentum pairs replaced by their reversed mirrors */
+  /* rho, e, P-x, P+x: background at the flow ends; every quantity
+   * mirror-symmetric at the walls, then the wall-normal momentum pairs
+   * replaced by their reversed mirrors.  The tangential momenta at the flow
+   * ends are those of the ghost's own state: the background density times the
+   * mirror cell's velocity, P = rho0 (P_m / rho_m) (Sect. 3.4 sets the
+   * primitive variables in the ghost zones). */
   for (int iq = 0; iq < NQ; ++iq) bc_centred_x(R, L, L->q[iq], q_inflow(R, iq), iq < 4);
+  int g = L->g, nx = L->n[0];
+  for (int iq = 4; iq < NQ; ++iq)
+    for (int k = -g; k < L->n[2] + g; ++k)
+      for (int j = -g; j < L->n[1] + g; ++j)
+        for (int t = 0; t < g; ++t)
+          for (int side = 0; side < 2; ++side) {
+            int i = side ? nx + t : -1 - t, im = mirror(i, nx);
+            int jm = mirror(j, L->n[1]), km = mirror(k, L->n[2]);
+            size_t c = IX(L, i, j, k), m = IX(L, im, jm, km);
+            L->q[iq][c] = L->q[0][c] * (L->q[iq][m] / L->q[0][m]);
+          }
   bc_wall_pair(L, L->q[4], L->q[5], 1);
   bc_wall_pair(L, L->q[6], L->q[7], 2);
 }

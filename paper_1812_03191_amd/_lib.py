@@ -71,6 +71,7 @@ def _load():
         "df_timing_read": [vp, dp, ctypes.POINTER(i32), i32],
         "df_stream_copy": [vp, vp, ctypes.c_size_t, vp],
         "df_set_subcycling": [vp, i32],
+        "df_set_boundaries": [vp, i32],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
     }
     for name, args in sig.items():
@@ -256,6 +257,10 @@ class Run:
     def set_subcycling(self, mode: int) -> None:
         """0: two sub-steps per level; 1: the criterion of App. A each coarse step"""
         _ck(_load().df_set_subcycling(self._h, int(mode)))
+
+    def set_boundaries(self, mode: int) -> None:
+        """0: inflow at x_max, outflow elsewhere; 1: the boundary list of Sect. 3.4"""
+        _ck(_load().df_set_boundaries(self._h, int(mode)))
 
     def schedule(self) -> list:
         """sub-steps of level l+1 per step of level l in the last coarse step"""

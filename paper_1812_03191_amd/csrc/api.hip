@@ -514,6 +514,15 @@ int df_set_subcycling(df_run *R, int32_t mode) {
   return DF_OK;
 }
 
+int df_set_boundaries(df_run *R, int32_t mode) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (mode != 0 && mode != 1) return fail(DF_EINVAL, "boundary mode must be 0 or 1");
+  R->geo[0].bc = mode == 1 ? 2 : 1;
+  R->sig_valid = false;
+  return DF_OK;
+}
+
 int df_get_schedule(df_run *R, int32_t *xi, int32_t n) {
   int rc = check_run(R, false);
   if (rc) return rc;

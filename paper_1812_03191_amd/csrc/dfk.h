@@ -25,7 +25,8 @@ struct Geo {
   long off;
   double dx;
   int level;
-  int bc;        // 1: level 0, outer boundary conditions applied on read
+  int bc;        // level 0 reads its outer boundary conditions: 1 inflow at x_max and outflow elsewhere,
+                 // 2 the boundary list of Sect. 3.4 (background at both flow ends, mirror walls); 0 finer levels
   int has_fine;  // a finer level covers the central half
 };
 

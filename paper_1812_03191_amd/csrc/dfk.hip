@@ -113,11 +113,23 @@ __device__ __forceinline__ T vleer(T a, T b) {
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Level-0 read of a centred departure with the outer boundary conditions:
-// zero departure (the inflow state) beyond x_max, the nearest active cell
-// elsewhere (zero-gradient outflow).
+// mirror image of a ghost index across the low (idx < 0) or high (idx >= n) side
+__device__ __forceinline__ int mirror_idx(int idx, int n) {
+  return idx < 0 ? -1 - idx : (idx >= n ? 2 * n - 1 - idx : idx);
+}
+
+// Level-0 read of a centred departure with the outer boundary conditions.
+// bc 1: zero departure (the inflow state) beyond x_max, the nearest active
+// cell elsewhere (zero-gradient outflow).  bc 2: zero departure (the
+// background) beyond both flow ends, mirror images across the walls.  (For
+// momenta only the ones normal to x read ghosts here, which hold the
+// background at the flow ends in both modes.)
 template <typename T>
 __device__ __forceinline__ T cread(const T *q, const Geo &G, int i, int j, int k) {
+  if (G.bc == 2) {
+    if (i < 0 || i >= G.n[0]) return T(0);
+    return q[lin(G, i, mirror_idx(j, G.n[1]), mirror_idx(k, G.n[2]))];
+  }
   if (i >= G.n[0]) return T(0);
   i = i < 0 ? 0 : i;
   j = clampi(j, 0, G.n[1] - 1);
@@ -126,9 +138,31 @@ __device__ __forceinline__ T cread(const T *q, const Geo &G, int i, int j, int k
 }
 
 // Level-0 read of the velocity departure normal to faces of dimension d
-// (active faces 0..n along d): zero beyond x_max, copies elsewhere.
+// (active faces 0..n along d).  bc 1: zero beyond x_max, copies elsewhere.
+// bc 2: zero (the wind) beyond both flow ends for x faces, mirror images
+// across the flow ends for the tangential ones; across a wall the normal
+// velocity is reversed (zero on the wall) and the tangential ones mirrored.
 template <typename T>
 __device__ __forceinline__ T fread_bc(const T *v, const Geo &G, int d, int i, int j, int k) {
+  if (G.bc == 2) {
+    T sgn = T(1);
+    if (d == 0) {
+      if (i < 0 || i > G.n[0]) return T(0);
+    } else {
+      i = mirror_idx(i, G.n[0]);
+    }
+    int id[3] = {i, j, k};
+#pragma unroll
+    for (int e = 1; e < 3; ++e) {
+      if (d == e) {
+        if (id[e] < 0) { id[e] = -id[e]; sgn = -sgn; }
+        else if (id[e] > G.n[e]) { id[e] = 2 * G.n[e] - id[e]; sgn = -sgn; }
+      } else {
+        id[e] = mirror_idx(id[e], G.n[e]);
+      }
+    }
+    return sgn * v[lin(G, id[0], id[1], id[2])];
+  }
   if (d == 0) {
     if (i > G.n[0]) return T(0);
   } else if (i >= G.n[0]) {
@@ -392,125 +426,17 @@ struct PassArgs {
   int fn[3];         // finer level's active cells (accumulator strides)
 };
 
-template <int DIR, bool BC>
-__device__ __forceinline__ bool cell_at(const Geo &G, int i, int j, int k, int o, idx_t &c) {
-  int ii = i + (DIR == 0 ? o : 0), jj = j + (DIR == 1 ? o : 0), kk = k + (DIR == 2 ? o : 0);
+// Cell of the x pass at row (j, k) and x: false where level 0's boundary
+// holds the background (beyond x_max; under bc 2 beyond both flow ends), else
+// the cell to read (the nearest active one under bc 1).
+template <bool BC>
+__device__ __forceinline__ bool xcell_at(const Geo &G, int x, int j, int k, idx_t &c) {
   if (BC) {
-    if (ii >= G.n[0]) return false;
-    ii = ii < 0 ? 0 : ii;
-    jj = clampi(jj, 0, G.n[1] - 1);
-    kk = clampi(kk, 0, G.n[2] - 1);
+    if (x >= G.n[0] || (G.bc == 2 && x < 0)) return false;
+    x = x < 0 ? 0 : x;
   }
-  c = lin(G, ii, jj, kk);
+  c = lin(G, x, j, k);
   return true;
-}
-
-// One dimensional pass of the van Leer upwind transport along DIR for the cell
-// (i,j,k), the x pass (FIRST) building the momenta from the face velocities.
-// Transfers through a face (area and time integrated): mass M = face(rho) a dt
-// dx^2 and face(q/rho) M for the other quantities; q -= (right - left)/dx^3.
-// In departures: with a = a0 + da and the background transfer M0 = rho0 a0 dt
-// dx^2 (the same through every face), dM = (rho0 da + face(drho) a) dt dx^2 and
-// dT = s0 dM + face(ds) (M0 + dM), where ds = (rho0 dq - q0 drho)/(rho0 rho) is
-// the departure of q/rho.  The quantities are processed one at a time so that
-// only the densities and the mass transfers stay live across the loop.
-template <typename T, int DIR, bool BC, bool FIRST>
-__global__ void __launch_bounds__(BX * BY) k_pass(Geo G, Phys P, PassArgs<T> A) {
-  int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
-  const T dt = (T)(A.fac * A.dtp[0]);
-  const T dx = (T)G.dx;
-  const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx);
-  const T rho0 = (T)P.rho0;
-  const T vb = (T)vback(P, DIR);
-  idx_t cc[5];
-  bool in[5];
-#pragma unroll
-  for (int o = 0; o < 5; ++o) in[o] = cell_at<DIR, BC>(G, i, j, k, o - 2, cc[o]);
-  T dr[5], irr[5];
-#pragma unroll
-  for (int o = 0; o < 5; ++o) {
-    dr[o] = in[o] ? A.qi[0][cc[o]] : T(0);
-    irr[o] = T(1) / (rho0 * (rho0 + dr[o]));
-  }
-  const idx_t c = lin(G, i, j, k);
-  const idx_t st = dstride(G, DIR);
-  const T daL = A.v[DIR][c], daR = A.v[DIR][c + st];
-  const T aL = vb + daL, aR = vb + daR;
-  const T nuL = aL * dt / dx, nuR = aR * dt / dx;
-  const T M0 = rho0 * vb * mfac;
-  const T dML = (rho0 * daL + face_value(dr[0], dr[1], dr[2], dr[3], aL, nuL) * aL) * mfac;
-  const T dMR = (rho0 * daR + face_value(dr[1], dr[2], dr[3], dr[4], aR, nuR) * aR) * mfac;
-  const T ML = M0 + dML, MR = M0 + dMR;
-
-  const int id[3] = {i, j, k};
-  constexpr int T1 = (DIR == 0) ? 1 : 0;
-  constexpr int T2 = (DIR == 2) ? 1 : 2;
-  const int cd = id[DIR];
-  // flux matching on the frontier of the finer level: the sum of its 4 faces
-  // over its 2 sub-cycles replaces this level's transfers there
-  int side_L = -1, side_R = -1;
-  long fbase = 0, fnt = 0;
-  if (A.facc) {
-    const int a1 = id[T1] - G.n[T1] / 4, a2 = id[T2] - G.n[T2] / 4;
-    if (a1 >= 0 && a2 >= 0 && a1 < G.n[T1] / 2 && a2 < G.n[T2] / 2) {
-      const int lo = G.n[DIR] / 4, hi = (3 * G.n[DIR]) / 4;
-      if (cd == lo || cd == hi) side_L = (cd == hi);
-      if (cd + 1 == lo || cd + 1 == hi) side_R = (cd + 1 == hi);
-      fnt = (long)A.fn[T1] * A.fn[T2];
-      fbase = (long)(2 * a2) * A.fn[T1] + 2 * a1;
-    }
-  }
-  auto fine_sum = [&](int side, int m) -> T {
-    const T *a = A.facc + ((long)(DIR * 2 + side) * NQ + m) * fnt + fbase;
-    return (a[0] + a[1]) + (a[A.fn[T1]] + a[A.fn[T1] + 1]);
-  };
-  // this (fine) level's own frontier: accumulate its transfers there
-  long acc_i = -1, acc_nt = 0;
-  int acc_side = -1;
-  if (A.acc) {
-    const int t1 = id[T1], t2 = id[T2];
-    if (t1 >= 0 && t2 >= 0 && t1 < G.n[T1] && t2 < G.n[T2] && (cd == 0 || cd == G.n[DIR] - 1)) {
-      acc_nt = (long)G.n[T1] * G.n[T2];
-      acc_i = (long)t2 * G.n[T1] + t1;
-      acc_side = (cd == 0) ? 0 : 1;
-    }
-  }
-  auto finish = [&](int m, T own, T FL, T FR) {
-    if (side_L >= 0) FL = fine_sum(side_L, m);
-    if (side_R >= 0) FR = fine_sum(side_R, m);
-    if (acc_side == 0) A.acc[((long)(DIR * 2 + 0) * NQ + m) * acc_nt + acc_i] += FL;
-    if (acc_side == 1) A.acc[((long)(DIR * 2 + 1) * NQ + m) * acc_nt + acc_i] += FR;
-    A.qo[m][c] = own - (FR - FL) * ivol;
-  };
-  finish(0, dr[2], dML, dMR);
-
-#pragma unroll 1
-  for (int m = 1; m < NQ; ++m) {
-    T ds[5], own;
-    if (FIRST && m >= 2) {
-      // momentum P = rho v of a face velocity: its specific value is v itself
-      const int d = (m - 2) >> 1;
-      const idx_t off = (m & 1) ? dstride(G, d) : 0;
-      const T *vd = A.v[d];
-#pragma unroll
-      for (int o = 0; o < 5; ++o) ds[o] = in[o] ? vd[cc[o] + off] : T(0);
-      own = rho0 * ds[2] + dr[2] * ((T)vback(P, d) + ds[2]);
-    } else {
-      const T *q = A.qi[m];
-      const T q0 = (T)qback(P, m);
-      T dq[5];
-#pragma unroll
-      for (int o = 0; o < 5; ++o) dq[o] = in[o] ? q[cc[o]] : T(0);
-#pragma unroll
-      for (int o = 0; o < 5; ++o) ds[o] = (rho0 * dq[o] - q0 * dr[o]) * irr[o];
-      own = dq[2];
-    }
-    const T s0 = (T)sback(P, m);
-    const T FL = s0 * dML + face_value(ds[0], ds[1], ds[2], ds[3], aL, nuL) * ML;
-    const T FR = s0 * dMR + face_value(ds[1], ds[2], ds[3], ds[4], aR, nuR) * MR;
-    finish(m, own, FL, FR);
-  }
 }
 
 // Neighbour exchange inside a wave through the data-parallel-primitive lane
@@ -572,7 +498,14 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   const T rho0 = (T)P.rho0;
   const T vb = (T)vback(P, 0);
   idx_t c;
-  const bool in = cell_at<0, BC>(G, xl, j, k, 0, c);
+  const bool in = xcell_at<BC>(G, xl, j, k, c);
+  // momenta tangential to x beyond a flow end under bc 2: the mirror cell's
+  idx_t ct = c;
+  bool int_ = in;
+  if (BC && G.bc == 2 && !in) {
+    ct = lin(G, mirror_idx(xl, G.n[0]), j, k);
+    int_ = true;
+  }
   const T dr = in ? gld(A.qi[0], c) : T(0);
   const T irr = T(1) / (rho0 * (rho0 + dr));
   // velocity departure on the left face (faces lo..hi are the ones used)
@@ -631,7 +564,8 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
       // momentum P = rho v of a face velocity: its specific value is v itself
       const int d = (m - 2) >> 1;
       const idx_t off = (m & 1) ? dstride(G, d) : 0;
-      sv = in ? gld(A.v[d], c + off) : T(0);
+      if (d == 0) sv = in ? gld(A.v[d], c + off) : T(0);
+      else sv = int_ ? gld(A.v[d], ct + off) : T(0);
       own = rho0 * sv + dr * ((T)vback(P, d) + sv);
     } else {
       const T dq = in ? gld(A.qi[m], c) : T(0);
@@ -923,25 +857,37 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   // face c (F0); raw departures of cells c, c+1, c+2 (w0, w1, w2) and the
   // velocity departure on face c+1 (va), all loaded at least one iteration
   // ahead of their use
+  // bc 2: across a wall (DIR is y or z) every quantity takes its mirror
+  // image, and the two momenta normal to the wall swap and change sign
+  const bool walls = BC && G.bc == 2;
+  constexpr int pa = (DIR == 1) ? 0 : 2;  // P-, P+ normal to DIR in group 1
+  auto ld = [&](int u, int c) -> T {      // u < 0: the density
+    const T *q = u < 0 ? A.qi[0] : qin[u];
+    if (walls && (c < 0 || c >= G.n[DIR])) {
+      const idx_t m = base + mirror_idx(c, G.n[DIR]) * st;
+      if (GRP == 1 && (u == pa || u == pa + 1)) return -gld(qin[u ^ 1], m);
+      return gld(q, m);
+    }
+    return gld(q, cidx(c));
+  };
+
   T s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
   T va;
   {
     T sm2[5], sm1[5];
-    const idx_t im2 = cidx(c0 - 2), im1 = cidx(c0 - 1), i0 = cidx(c0), ip1 = cidx(c0 + 1);
-    const T r_m2 = gld(A.qi[0], im2), r_m1 = gld(A.qi[0], im1);
-    w0[0] = gld(A.qi[0], i0);
-    w1[0] = gld(A.qi[0], ip1);
+    const T r_m2 = ld(-1, c0 - 2), r_m1 = ld(-1, c0 - 1);
+    w0[0] = ld(-1, c0);
+    w1[0] = ld(-1, c0 + 1);
     const T ir_m2 = T(1) / (rho0 * (rho0 + r_m2)), ir_m1 = T(1) / (rho0 * (rho0 + r_m1));
     const T ir_0 = T(1) / (rho0 * (rho0 + w0[0])), ir_p1 = T(1) / (rho0 * (rho0 + w1[0]));
     sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = w0[0]; s1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (u >= nq) break;
-      const T *q = qin[u];
-      w0[u + 1] = gld(q, i0);
-      w1[u + 1] = gld(q, ip1);
-      sm2[u + 1] = (rho0 * gld(q, im2) - q0[u] * r_m2) * ir_m2;
-      sm1[u + 1] = (rho0 * gld(q, im1) - q0[u] * r_m1) * ir_m1;
+      w0[u + 1] = ld(u, c0);
+      w1[u + 1] = ld(u, c0 + 1);
+      sm2[u + 1] = (rho0 * ld(u, c0 - 2) - q0[u] * r_m2) * ir_m2;
+      sm1[u + 1] = (rho0 * ld(u, c0 - 1) - q0[u] * r_m1) * ir_m1;
       s0[u + 1] = (rho0 * w0[u + 1] - q0[u] * w0[0]) * ir_0;
       s1[u + 1] = (rho0 * w1[u + 1] - q0[u] * w1[0]) * ir_p1;
     }
@@ -962,21 +908,20 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
         F0[u] = fix(c0, mq[u - 1], sb[u - 1] * dM + fv * M);
       }
     }
-    const idx_t ip2 = cidx(c0 + 2);
-    w2[0] = gld(A.qi[0], ip2);
+    w2[0] = ld(-1, c0 + 2);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) w2[u + 1] = gld(qin[u], ip2);
+      if (u < nq) w2[u + 1] = ld(u, c0 + 2);
     va = gld(A.v, base + (c0 + 1) * st);
   }
   for (int c = c0; c < c1; ++c) {
-    const idx_t ic = cidx(c), ip3 = cidx(c + 3);
+    const idx_t ic = cidx(c);
     // next iteration's loads: cell c+3 and face c+2
     T nn[5];
-    nn[0] = gld(A.qi[0], ip3);
+    nn[0] = ld(-1, c + 3);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) nn[u + 1] = gld(qin[u], ip3);
+      if (u < nq) nn[u + 1] = ld(u, c + 3);
     const T vn = gld(A.v, base + min(c + 2, c1) * st);
     const T ir2 = T(1) / (rho0 * (rho0 + w2[0]));
     T s2[5];
@@ -1432,6 +1377,11 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
         if (POST) sig = fmax(sig, fabs(vback(P, 0)) + cs_own);
         return;
       }
+      if (d > 0 && G.bc == 2 && (last || id[d] == 0)) {
+        A.v[d][cf] = T(0);  // a wall: no normal velocity
+        if (POST) sig = fmax(sig, cs_own);
+        return;
+      }
       T dcr = drc, der = dec, xr = xc[d], r2r = r2c, dr_ = dcen;
       if (last) {
         dcr = cread(rho, G, pi, pj, pk);
@@ -1758,7 +1708,8 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   if (dir == 0) {
     const dim3 bl(BX, BY);
     const int n = G.n[0];
-    if (G.bc && n <= BX) DFK_LAUNCH((k_xrow<T, 1>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
+    if (G.bc == 2) DFK_LAUNCH((k_xpass<T, true>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    else if (G.bc && n <= BX) DFK_LAUNCH((k_xrow<T, 1>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= 2 * BX && n % 2 == 0) DFK_LAUNCH((k_xrow<T, 2>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= 4 * BX && n % 4 == 0) DFK_LAUNCH((k_xrow<T, 4>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc) DFK_LAUNCH((k_xpass<T, true>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
