@@ -38,10 +38,13 @@ def dfm():
     return m
 
 
-def _force_at(dfm, mach, nlevels, n, L, chi, t_end):
-    lam = CHI / (GAMMA * mach)
+def _force_at(dfm, mach, nlevels, n, L, chi, t_end, gamma=GAMMA, walls=False):
+    lam = CHI / (gamma * mach)
     dxf = lam / 5.0
-    r = dfm.Run(n, nlevels=nlevels, dx0=dxf * 2 ** (nlevels - 1), noise_amp=0.0, precision=dfm.DF_FP32)
+    r = dfm.Run(n, nlevels=nlevels, dx0=dxf * 2 ** (nlevels - 1), gamma=gamma, noise_amp=0.0,
+                precision=dfm.DF_FP32)
+    if walls:
+        r.set_boundaries(1)
     r.set_perturber(GM, 0.0, L, mach, chi)
     while True:
         r.step(50)
@@ -53,8 +56,8 @@ def _force_at(dfm, mach, nlevels, n, L, chi, t_end):
     return log[min(k, len(log) - 1)]
 
 
-def _fraction(mach, nlevels, n):
-    lam = CHI / (GAMMA * mach)
+def _fraction(mach, nlevels, n, gamma=GAMMA):
+    lam = CHI / (gamma * mach)
     dxf = lam / 5.0
     rmax = (n // 2) * dxf * 2 ** (nlevels - 1) / (2 * lam)
     return float(T.h_fraction(rmax) - T.h_fraction(dxf / (2 * lam)))
@@ -138,6 +141,25 @@ def test_low_mach_cold_thermal_force(dfm):
     want = T.cold_thermal_force(GAMMA, 1.0, GM) * _fraction(mach, nl, n)
     got = diff[0] - adi[0]
     _say(f"[physics] cold thermal force {got:.5e} vs {want:.5e} (ratio {got / want:.4f})")
+    assert got < 0.0
+    assert abs(got / want - 1.0) < 0.08
+
+
+def test_paper_setup_cold_thermal_force(dfm):
+    # the paper's own setup (Sect. 3.4): gamma 1.4, eps 0, heat split over the
+    # 8 cells, background state at both flow ends and mirror walls; at Mach
+    # 0.2 (6 levels of 64^3, 40 tau, before the acoustic sphere reaches the
+    # box) the cold thermal force tends to -(gamma-1)/2 F0 = -0.2 F0 (eq. 51,
+    # Fig. 12) times the h-fraction of the finite range
+    mach, nl, n, gamma = 0.2, 6, 64, 1.4
+    tau = T.response_time(CHI, gamma, mach)
+    diff = _force_at(dfm, mach, nl, n, 0.0, CHI, 40 * tau, gamma=gamma, walls=True)
+    adi = _force_at(dfm, mach, nl, n, 0.0, 0.0, 40 * tau, gamma=gamma, walls=True)
+    F0 = T.F0(1.0, GM)
+    want = T.cold_thermal_force(gamma, 1.0, GM) * _fraction(mach, nl, n, gamma)
+    got = diff[0] - adi[0]
+    _say(f"[physics] paper setup: cold thermal force {got / F0:.4f} F0 vs {want / F0:.4f} F0 (ratio {got / want:.4f})")
+    assert abs(T.cold_thermal_force(gamma, 1.0, GM) / F0 + 0.2) < 1e-12
     assert got < 0.0
     assert abs(got / want - 1.0) < 0.08
 
