@@ -49,6 +49,7 @@ typedef struct {
   double GM, eps, L, mach, chi; /* perturber and gas parameters            */
   int subcycle;       /* 0: two sub-steps per level; 1: App. A criterion    */
   int bcmode;         /* level-0 boundaries: 0 inflow/outflow; 1 Sect. 3.4  */
+  double visc;        /* artificial-viscosity coefficient C2 (0: off)       */
 } dfo_params;
 
 typedef struct {
@@ -387,6 +388,62 @@ static void compress(run_t *R, int lvl, double dt) {
       }
 }
 
+/* ------------------------------------------------- artificial viscosity */
+/* SubStep2 of the staging list (Sect. 3.3), which the paper names without
+ * giving it: the von Neumann-Richtmyer viscosity of ZEUS (Stone & Norman
+ * 1992, ApJS 80, 753), opt-in with coefficient C2 = p.visc (0: off, the
+ * default).  Per dimension d and cell c, with dv = v_d(high face) - v_d(low
+ * face): q_d(c) = C2 rho(c) dv^2 where dv < 0 (compression), else 0.  Each face
+ * velocity v_d -= dt (q_d(c) - q_d(c-1)) / (dx rho_face) with rho_face the
+ * mean of the two cells, and e(c) -= dt sum_d q_d(c) dv_d(c) / dx, all from
+ * the values before the stage.  On level 0 the faces reset by the boundary
+ * conditions (the inflow face, walls) keep their values. */
+static double visc_q(const lev_t *L, const double *rho, const double *v, size_t c, long s, double c2) {
+  double dv = v[c + s] - v[c];
+  return dv < 0.0 ? c2 * rho[c] * dv * dv : 0.0;
+}
+
+static void viscosity(run_t *R, int lvl, double dt) {
+  const double c2 = R->p.visc;
+  if (!(c2 > 0.0)) return;
+  lev_t *L = &R->lev[lvl];
+  const double dx = L->dx, *rho = L->st[S_RHO];
+  double *e = L->st[S_E];
+  /* energy, from the pre-stage velocities */
+  box_t cb = box_cells_r(L, lvl);
+#pragma omp parallel for schedule(static)
+  for (int k = cb.lo[2]; k < cb.hi[2]; ++k)
+    for (int j = cb.lo[1]; j < cb.hi[1]; ++j)
+      for (int i = cb.lo[0]; i < cb.hi[0]; ++i) {
+        size_t c = IX(L, i, j, k);
+        double de = 0.0;
+        for (int d = 0; d < 3; ++d) {
+          const double *v = L->st[S_VX + d];
+          long s = STR(L, d);
+          de += visc_q(L, rho, v, c, s, c2) * (v[c + s] - v[c]);
+        }
+        e[c] -= dt * de / dx;
+      }
+  /* face velocities, new values into tmp then copied back (Jacobi) */
+  for (int d = 0; d < 3; ++d) {
+    double *v = L->st[S_VX + d];
+    long s = STR(L, d);
+    box_t b = box_faces(L, lvl, d);
+    if (lvl > 0) { b.lo[d] = -L->g + 1; for (int e2 = 0; e2 < 3; ++e2) b.hi[e2] = L->n[e2] + L->g - 1; }
+    memcpy(L->tmp, v, L->vol * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int k = b.lo[2]; k < b.hi[2]; ++k)
+      for (int j = b.lo[1]; j < b.hi[1]; ++j)
+        for (int i = b.lo[0]; i < b.hi[0]; ++i) {
+          size_t c = IX(L, i, j, k), m = c - (size_t)s;
+          double qc = visc_q(L, rho, v, c, s, c2), qm = visc_q(L, rho, v, m, s, c2);
+          L->tmp[c] = v[c] - dt * (qc - qm) / (dx * 0.5 * (rho[m] + rho[c]));
+        }
+    memcpy(v, L->tmp, L->vol * sizeof(double));
+  }
+  if (lvl == 0) reset_inflow_face(R);
+}
+
 /* ------------------------------------------------------------- diffusion */
 /* Thermal diffusion, eqs. 19-22: face energy fluxes proportional to chi rho0
  * times the difference of e/rho across the face, times the face area over the
@@ -679,6 +736,8 @@ static void hydro_step(run_t *R, int lvl, double dt) {
   int l0 = (lvl == 0);
   if (l0) bc_state(R);
   kick(R, lvl, 0.5 * dt);
+  if (l0) bc_state(R);
+  viscosity(R, lvl, dt);
   if (l0) bc_state(R);
   compress(R, lvl, dt);
   if (l0) bc_state(R);
@@ -1203,6 +1262,7 @@ int dfo_stage(void *h, int stage, double dt) {
     case 5: bc_state(R); transport(R, 0, dt); break;
     case 6: bc_state(R); compress(R, 0, dt); bc_state(R); diffuse(R, 0, dt); heat(R, 0, dt); break;
     case 7: if (R->nl != 1) return -1; hydro_step(R, 0, dt); R->t += dt; break;
+    case 8: bc_state(R); viscosity(R, 0, dt); break;
     default: return -1;
   }
   bc_state(R);

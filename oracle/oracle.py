@@ -40,7 +40,7 @@ class _Params(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("GM", ctypes.c_double), ("eps", ctypes.c_double), ("L", ctypes.c_double),
         ("mach", ctypes.c_double), ("chi", ctypes.c_double),
-        ("subcycle", ctypes.c_int), ("bcmode", ctypes.c_int),
+        ("subcycle", ctypes.c_int), ("bcmode", ctypes.c_int), ("visc", ctypes.c_double),
     ]
 
 
@@ -94,11 +94,11 @@ class Oracle:
     ``ghosts=True``."""
 
     STAGES = {"kick": 1, "compress": 2, "diffuse": 3, "heat": 4, "transport": 5,
-              "sources": 6, "level_step": 7}
+              "sources": 6, "level_step": 7, "viscosity": 8}
 
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0=None, gamma=5.0 / 3.0,
                  cfl=0.4, rho0=1.0, cs=1.0, seed=1, noise_amp=1e-6, GM=0.01, eps=0.0,
-                 L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None, subcycle=0, bcmode=0):
+                 L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None, subcycle=0, bcmode=0, visc=0.0):
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         if dx0 is None:
@@ -108,7 +108,7 @@ class Oracle:
             _load().dfo_set_threads(int(threads))
         self._lib = _load()
         self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
-                         noise_amp, GM, eps, L, mach, chi, int(subcycle), int(bcmode))
+                         noise_amp, GM, eps, L, mach, chi, int(subcycle), int(bcmode), float(visc))
         self.n = (nx, ny, nz)
         self.nlevels = nlevels
         self.g = [g0] + [gf] * (nlevels - 1)
