@@ -152,6 +152,15 @@ int df_get_dt(df_run *run, double *dt);
  * mode 0).  DF_EINVAL for other modes. */
 int df_set_subcycling(df_run *run, int32_t mode);
 
+/* Artificial viscosity: the SubStep2 that the staging list of Sect. 3.3 names
+ * without giving it, taken as the von Neumann-Richtmyer viscosity of ZEUS
+ * (Stone & Norman 1992): per dimension d and cell, dv = v_d(high face) -
+ * v_d(low face), q_d = c2 rho dv^2 in compression (dv < 0), else 0; the face
+ * velocities lose dt (q_d(c) - q_d(c-1)) / (dx rho_face) and the energy
+ * dt sum_d q_d dv / dx, applied after the first kick of each level step.  c2 = 0
+ * (the default) switches it off; DF_EINVAL for negative or non-finite c2. */
+int df_set_viscosity(df_run *run, double c2);
+
 /* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
  * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
  * every other boundary is zero-gradient outflow.  mode 1: the paper's list,
@@ -171,7 +180,8 @@ int df_get_schedule(df_run *run, int32_t *xi, int32_t n);
 
 /* Run one stage of the level update on a single-level run, with step dt:
  *  1 velocity kick over dt, 2 compressional heating, 3 thermal diffusion,
- *  4 heat release, 5 transport, 6 stages 2-4, 7 a whole level step.
+ *  4 heat release, 5 transport, 6 stages 2-4, 7 a whole level step,
+ *  8 artificial viscosity (df_set_viscosity).
  * Used by the parity tests.  DF_EINVAL for other stages or nested runs. */
 int df_debug_stage(df_run *run, int32_t stage, double dt);
 
@@ -187,7 +197,7 @@ int df_debug_stage(df_run *run, int32_t stage, double dt);
  * call (with a signal pass if the state was changed by other calls). */
 enum {
   DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
-  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_NKINDS
+  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_NKINDS
 };
 int df_timing_enable(df_run *run, int32_t max_launches);
 int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);

@@ -14,7 +14,7 @@ _LIB_PATH = os.path.join(_HERE, "libdfmesh.so")
 DF_FP64, DF_FP32 = 0, 1
 FIELDS = {"rho": 0, "e": 1, "vx": 2, "vy": 3, "vz": 4}
 STAGES = {"kick": 1, "compress": 2, "diffuse": 3, "heat": 4, "transport": 5, "sources": 6,
-          "level_step": 7}
+          "level_step": 7, "viscosity": 8}
 
 
 class DFError(RuntimeError):
@@ -72,6 +72,7 @@ def _load():
         "df_stream_copy": [vp, vp, ctypes.c_size_t, vp],
         "df_set_subcycling": [vp, i32],
         "df_set_boundaries": [vp, i32],
+        "df_set_viscosity": [vp, ctypes.c_double],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
     }
     for name, args in sig.items():
@@ -177,7 +178,7 @@ def force_log(h, cap: int = 4096) -> np.ndarray:
 
 
 KERNEL_KINDS = ("kick", "compress", "diffuse_heat", "pass_x", "pass_y", "pass_z", "rebuild_kick",
-                "commup", "commmean", "dt", "force", "zero")
+                "commup", "commmean", "dt", "force", "zero", "viscosity")
 
 
 def timing_enable(h, max_launches: int) -> None:
@@ -257,6 +258,10 @@ class Run:
     def set_subcycling(self, mode: int) -> None:
         """0: two sub-steps per level; 1: the criterion of App. A each coarse step"""
         _ck(_load().df_set_subcycling(self._h, int(mode)))
+
+    def set_viscosity(self, c2: float) -> None:
+        """artificial-viscosity coefficient (0: off)"""
+        _ck(_load().df_set_viscosity(self._h, float(c2)))
 
     def set_boundaries(self, mode: int) -> None:
         """0: inflow at x_max, outflow elsewhere; 1: the boundary list of Sect. 3.4"""

@@ -68,6 +68,7 @@ struct df_run {
   bool ready = false;
   bool sig_valid = false;  // the signal-speed partials are those of the current state
   int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
+  double visc = 0.0;       // artificial-viscosity coefficient (kept across df_set_perturber)
   int xi[MAXLEV];          // sub-steps of level l+1 per step of level l (last coarse step)
   double up[MAXLEV + 1];   // staging of the host-chosen step lengths and time
   double eps = 0.0;
@@ -145,7 +146,7 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
 // ---------------------------------------------------------------- timing
 // Kernel kinds timed by df_timing_read (the order of the DF_K_* list in df.h).
 enum { K_KICK = 0, K_COMPRESS, K_DIFFUSE, K_PASSX, K_PASSY, K_PASSZ, K_REBUILD, K_COMMUP, K_COMMMEAN,
-       K_DT, K_FORCE, K_ZERO, K_NKINDS };
+       K_DT, K_FORCE, K_ZERO, K_VISC, K_NKINDS };
 
 struct TScope {
   df_run *R;
@@ -174,6 +175,7 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
   const void *facc = Gf ? R->buf[l + 1].acc : nullptr;
   { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale); }
+  if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, G, P, B, c, dtp, scale); }
   { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale); }
   { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
   // the x pass reads the new energy from the diffusion output; every buffer
@@ -450,6 +452,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
   P.e0 = P.rho0 * cs * cs / (d.gamma * (d.gamma - 1.0));
   P.cfl = d.cfl;
   P.fp32 = d.precision == DF_FP32;
+  P.visc = R->visc;
   R->eps = eps;
   hipStream_t st = R->stream;
   // heat tables
@@ -511,6 +514,15 @@ int df_set_subcycling(df_run *R, int32_t mode) {
   if (mode != 0 && mode != 1) return fail(DF_EINVAL, "sub-cycling mode must be 0 or 1");
   R->subcycle = mode;
   for (int m = 0; m < MAXLEV; ++m) R->xi[m] = 2;
+  return DF_OK;
+}
+
+int df_set_viscosity(df_run *R, double c2) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (!std::isfinite(c2) || c2 < 0.0) return fail(DF_EINVAL, "viscosity coefficient must be finite and >= 0");
+  R->visc = c2;
+  R->phys.visc = c2;
   return DF_OK;
 }
 
@@ -683,6 +695,7 @@ int df_debug_stage(df_run *R, int32_t stage, double dt) {
       std::swap(B.etmp, B.q[c][1]);
       break;
     case 7: level_step(R, 0, dtp, 1.0); break;
+    case 8: dfk::viscosity(st, G, P, B, c, dtp, 1.0); break;
     default: return fail(DF_EINVAL, "unknown stage");
   }
   rc = launch_check("df_debug_stage");

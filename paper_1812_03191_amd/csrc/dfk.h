@@ -40,6 +40,7 @@ struct Phys {
   double chi, rho0, e0;
   double cfl;
   int fp32;            // storage type: float (1) or double (0)
+  double visc;         // artificial-viscosity coefficient C2 (0: off)
 };
 
 // Device-resident scalars of a run (one small array in the arena).
@@ -80,6 +81,11 @@ void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int s
                   const double *dtp, double fac, bool do_kick, Scal *post = nullptr);
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
               double fac);
+// artificial viscosity over fac dt: e in place; the face velocities through
+// the three momentum arrays of q[1-cur] as scratch (they are free before the
+// x pass writes them)
+void viscosity(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+               double fac);
 // writes etmp; the caller swaps etmp and q[cur][1]
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur,
                   const double *dtp, double fac, bool do_diff, bool do_heat);

@@ -313,6 +313,88 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
   }
 }
 
+// ------------------------------------------------- artificial viscosity
+
+template <typename T>
+struct ViscArgs {
+  int lo[3], hi[3];          // union of the ranges below
+  int elo[3], ehi[3];        // cells whose energy changes
+  int flo[3][3], fhi[3][3];  // [normal dir][dim] faces that change
+  const T *rho;
+  T *e;
+  const T *v[3];
+  T *vn[3];                  // new face velocities
+  const double *dtp;
+  double fac;
+};
+
+// Von Neumann-Richtmyer viscosity of ZEUS (Stone & Norman 1992) as the
+// SubStep2 that the staging list of Sect. 3.3 names: per dimension d and cell
+// c, dv = v_d(high face) - v_d(low face) and q_d = C2 rho dv^2 where dv < 0,
+// else 0; e -= dt sum_d q_d dv / dx; v_d(face) -= dt (q_d(c) - q_d(c-1)) /
+// (dx rho_face).  All from the values before the stage: the new velocities go
+// to vn.  On level 0 the boundary faces (the injection face, walls under bc 2)
+// keep their values, and cells and faces past the boundary read its ghosts.
+template <typename T, bool BC>
+__global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) {
+  int id[3];
+  if (!thread_cell(Box{{A.lo[0], A.lo[1], A.lo[2]}, {A.hi[0], A.hi[1], A.hi[2]}}, id[0], id[1], id[2])) return;
+  const T dt = (T)(A.fac * A.dtp[0]);
+  const T c2 = (T)P.visc, rho0 = (T)P.rho0, dx = (T)G.dx;
+  auto rho_at = [&](int i, int j, int k) -> T { return BC ? cread(A.rho, G, i, j, k) : A.rho[lin(G, i, j, k)]; };
+  auto v_at = [&](int d, int i, int j, int k) -> T {
+    return BC ? fread_bc(A.v[d], G, d, i, j, k) : A.v[d][lin(G, i, j, k)];
+  };
+  // q_d and dv_d of the cell at p
+  auto qd = [&](int d, const int *p, T &dv) -> T {
+    const T lo = v_at(d, p[0], p[1], p[2]);
+    const T hi = v_at(d, p[0] + (d == 0), p[1] + (d == 1), p[2] + (d == 2));
+    dv = hi - lo;
+    return dv < T(0) ? c2 * (rho0 + rho_at(p[0], p[1], p[2])) * dv * dv : T(0);
+  };
+  const idx_t c = lin(G, id[0], id[1], id[2]);
+  bool ecell = true;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) ecell = ecell && id[e] >= A.elo[e] && id[e] < A.ehi[e];
+  if (ecell) {
+    T de = T(0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      T dv;
+      const T q = qd(d, id, dv);
+      de += q * dv;
+    }
+    A.e[c] = A.e[c] - dt * de / dx;
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    bool in = true;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) in = in && id[e] >= A.flo[d][e] && id[e] < A.fhi[d][e];
+    if (!in) continue;
+    const T vold = A.v[d][c];
+    T vnew = vold;
+    const bool fixed = BC && ((d == 0 && id[0] == G.n[0]) ||
+                              (G.bc == 2 && d > 0 && (id[d] == 0 || id[d] == G.n[d])));
+    if (!fixed) {
+      int m[3] = {id[0] - (d == 0), id[1] - (d == 1), id[2] - (d == 2)};
+      T dvc, dvm;
+      const T qc = qd(d, id, dvc), qm = qd(d, m, dvm);
+      const T rface = rho0 + T(0.5) * (rho_at(m[0], m[1], m[2]) + rho_at(id[0], id[1], id[2]));
+      vnew = vold - dt * (qc - qm) / (dx * rface);
+    }
+    A.vn[d][c] = vnew;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_copy_faces(Geo G, Box b, T *dst, const T *src) {
+  int i, j, k;
+  if (!thread_cell(b, i, j, k)) return;
+  const idx_t c = lin(G, i, j, k);
+  dst[c] = src[c];
+}
+
 // ------------------------------------------------------------ compression
 
 template <typename T>
@@ -1649,6 +1731,59 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac) {
   if (P.fp32) compress_t<float>(st, G, P, B, cur, dtp, fac);
   else compress_t<double>(st, G, P, B, cur, dtp, fac);
+}
+
+template <typename T>
+static void viscosity_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+                        double fac) {
+  ViscArgs<T> A;
+  for (int e = 0; e < 3; ++e) {
+    A.elo[e] = G.bc ? 0 : -G.g;
+    A.ehi[e] = G.bc ? G.n[e] : G.n[e] + G.g - 1;
+  }
+  for (int d = 0; d < 3; ++d)
+    for (int e = 0; e < 3; ++e) {
+      if (G.bc) {
+        A.flo[d][e] = 0;
+        A.fhi[d][e] = G.n[e] + (d == e ? 1 : 0);
+      } else {
+        A.flo[d][e] = -G.g + (d == e ? 1 : 0);
+        A.fhi[d][e] = G.n[e] + G.g - 1;
+      }
+    }
+  for (int e = 0; e < 3; ++e) {
+    A.lo[e] = min(A.elo[e], min(A.flo[0][e], min(A.flo[1][e], A.flo[2][e])));
+    A.hi[e] = max(A.ehi[e], max(A.fhi[0][e], max(A.fhi[1][e], A.fhi[2][e])));
+  }
+  A.rho = tp<T>(B.q[cur][0]);
+  A.e = tp<T>(B.q[cur][1]);
+  for (int d = 0; d < 3; ++d) {
+    A.v[d] = tp<T>(B.v[d]);
+    A.vn[d] = tp<T>(B.q[1 - cur][2 + d]);
+  }
+  A.dtp = dtp;
+  A.fac = fac;
+  Box ub;
+  for (int e = 0; e < 3; ++e) {
+    ub.lo[e] = A.lo[e];
+    ub.hi[e] = A.hi[e];
+  }
+  if (G.bc) DFK_LAUNCH((k_visc<T, true>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  else DFK_LAUNCH((k_visc<T, false>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  for (int d = 0; d < 3; ++d) {
+    Box fb;
+    for (int e = 0; e < 3; ++e) {
+      fb.lo[e] = A.flo[d][e];
+      fb.hi[e] = A.fhi[d][e];
+    }
+    DFK_LAUNCH((k_copy_faces<T>), grid_of(fb), dim3(BX, BY), st, G, fb, tp<T>(B.v[d]), A.vn[d]);
+  }
+}
+
+void viscosity(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac) {
+  if (!(P.visc > 0.0)) return;
+  if (P.fp32) viscosity_t<float>(st, G, P, B, cur, dtp, fac);
+  else viscosity_t<double>(st, G, P, B, cur, dtp, fac);
 }
 
 template <typename T>

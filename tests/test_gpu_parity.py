@@ -298,6 +298,57 @@ def test_wall_boundaries_parity(dfm, nl, n, steps):
     assert fe < 1e-9, (fg, fo)
 
 
+# ------------------------------------------- artificial viscosity (SubStep2)
+
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("n", [(16, 16, 16), (20, 12, 18)])
+def test_viscosity_stage_parity(dfm, n, walls):
+    from oracle.oracle import Oracle
+
+    _say(f"[viscosity parity] stage n={n} walls={walls}")
+    if walls:
+        o0, g = _wall_pair(dfm, n, seed=37)
+    else:
+        o0, g = _random_pair(dfm, n, seed=37)
+    nx, ny, nz = n
+    o = Oracle(nx, ny, nz, dx0=0.05, GM=0.01, eps=0.05, L=2e-3, mach=0.5, chi=0.1, noise_amp=0.0,
+               bcmode=1 if walls else 0, visc=2.0)
+    for name in FIELD_NAMES:
+        o.set_full_field(0, name, g.field(0, name))
+    g.set_viscosity(2.0)
+    # velocity departures of 1e-3 over 0.05 cells: dt large enough for q to show
+    o.stage("viscosity", 0.5)
+    g.stage("viscosity", 0.5)
+    errs = _field_errors(o, g, 1)
+    assert max(errs.values()) < 1e-13, {k: v for k, v in errs.items() if v > 1e-14}
+    ref = o0.full_field(0, "e")
+    assert np.max(np.abs(o.full_field(0, "e") - ref)) > 1e-9  # the stage did act
+
+
+@pytest.mark.parametrize("nl,n,steps,walls", [(1, 32, 40, False), (2, 16, 6, False), (1, 24, 20, True)])
+def test_viscosity_run_parity(dfm, nl, n, steps, walls):
+    # supersonic (Mach 2) runs with the viscosity on, whole steps
+    from oracle.oracle import Oracle
+
+    c = inputs.job(n, nl, 2.0, 0.01, 0.1, 1e-3, seed=19)
+    _say(f"[viscosity parity] {nl} levels of {n}^3 x {steps} walls={walls}")
+    o = Oracle(n, n, n, nlevels=nl, dx0=c["dx0"], gamma=c["gamma"], cfl=c["cfl"], seed=c["seed"],
+               noise_amp=c["noise_amp"], GM=c["GM"], eps=c["eps"], L=c["L"], mach=c["mach"], chi=c["chi"],
+               bcmode=1 if walls else 0, visc=2.0)
+    g = dfm.Run(n, n, n, nlevels=nl, dx0=c["dx0"], gamma=c["gamma"], cfl=c["cfl"], seed=c["seed"],
+                noise_amp=c["noise_amp"])
+    g.set_viscosity(2.0)
+    if walls:
+        g.set_boundaries(1)
+    g.set_perturber(c["GM"], c["eps"], c["L"], c["mach"], c["chi"])
+    o.step(steps)
+    g.step(steps)
+    errs = _field_errors(o, g, nl)
+    assert max(errs.values()) < 1e-11, {k: v for k, v in errs.items() if v > 1e-13}
+    fe, fg, fo = _force_err(o, g)
+    assert fe < 1e-9, (fg, fo)
+
+
 def test_nested_wider_ghosts_parity(dfm):
     cfg = inputs.job(16, 2, 0.6, 5e-3, 0.1, 1e-3, seed=8)
     _say("[parity] nested ghost width 12")
