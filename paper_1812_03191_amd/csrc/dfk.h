@@ -66,7 +66,7 @@ struct LevBufs {
   double *hw;         // heat weights on a box of hw_n[0] x hw_n[1] x hw_n[2] cells
                       // centred on the perturber vertex (x fastest)
   int hw_n[3];        // box extent (0: no heat table)
-  double *part;       // reduction partials: 3 per block, then 1 signal speed per block
+  double *part;       // reduction partials: three planes of one value per block, then the signal speeds
 };
 
 // ---- launchers (all asynchronous on `st`) ---------------------------------

@@ -118,15 +118,15 @@ __device__ __forceinline__ int mirror_idx(int idx, int n) {
   return idx < 0 ? -1 - idx : (idx >= n ? 2 * n - 1 - idx : idx);
 }
 
-// Level-0 read of a centred departure with the outer boundary conditions.
-// bc 1: zero departure (the inflow state) beyond x_max, the nearest active
+// Level-0 read of a centred departure with the outer boundary conditions
+// (M: the level's bc).  bc 1: zero departure (the inflow state) beyond x_max, the nearest active
 // cell elsewhere (zero-gradient outflow).  bc 2: zero departure (the
 // background) beyond both flow ends, mirror images across the walls.  (For
 // momenta only the ones normal to x read ghosts here, which hold the
 // background at the flow ends in both modes.)
-template <typename T>
+template <int M, typename T>
 __device__ __forceinline__ T cread(const T *q, const Geo &G, int i, int j, int k) {
-  if (G.bc == 2) {
+  if (M == 2) {
     if (i < 0 || i >= G.n[0]) return T(0);
     return q[lin(G, i, mirror_idx(j, G.n[1]), mirror_idx(k, G.n[2]))];
   }
@@ -138,13 +138,13 @@ __device__ __forceinline__ T cread(const T *q, const Geo &G, int i, int j, int k
 }
 
 // Level-0 read of the velocity departure normal to faces of dimension d
-// (active faces 0..n along d).  bc 1: zero beyond x_max, copies elsewhere.
+// (active faces 0..n along d; M: the level's bc).  bc 1: zero beyond x_max, copies elsewhere.
 // bc 2: zero (the wind) beyond both flow ends for x faces, mirror images
 // across the flow ends for the tangential ones; across a wall the normal
 // velocity is reversed (zero on the wall) and the tangential ones mirrored.
-template <typename T>
+template <int M, typename T>
 __device__ __forceinline__ T fread_bc(const T *v, const Geo &G, int d, int i, int j, int k) {
-  if (G.bc == 2) {
+  if (M == 2) {
     T sgn = T(1);
     if (d == 0) {
       if (i < 0 || i > G.n[0]) return T(0);
@@ -244,7 +244,7 @@ struct KickArgs {
 // (Phi_c - Phi_m)/dx = GM (x_c + x_m) / (d_c d_m (d_c + d_m)).
 // REBUILD first sets the face velocity from the transported momenta,
 // (P+_m + P-_c) / (rho_m + rho_c).  KICK = false skips the source.
-template <typename T, bool BC, bool REBUILD, bool KICK>
+template <typename T, bool REBUILD, bool KICK>
 __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) {
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
@@ -258,14 +258,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
   const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
   const T *rho = A.q[0], *e = A.q[1];
   const idx_t c = lin(G, i, j, k);
-  T drc, dec;
-  if (BC) {
-    drc = cread(rho, G, i, j, k);
-    dec = cread(e, G, i, j, k);
-  } else {
-    drc = rho[c];
-    dec = e[c];
-  }
+  const T drc = rho[c], dec = e[c];
   const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
   const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
   const T dcen = sqrt(r2c);
@@ -276,25 +269,11 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
     if (!in) continue;
     const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
     const idx_t m = c - dstride(G, d);
-    T drm, dem;
-    if (BC) {
-      drm = cread(rho, G, im, jm, km);
-      dem = cread(e, G, im, jm, km);
-    } else {
-      drm = rho[m];
-      dem = e[m];
-    }
+    const T drm = rho[m], dem = e[m];
     T vf;
     if (REBUILD) {
       const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
-      T ppm, pmc;
-      if (BC) {
-        ppm = cread(pp, G, im, jm, km);
-        pmc = cread(pm, G, i, j, k);
-      } else {
-        ppm = pp[m];
-        pmc = pm[c];
-      }
+      const T ppm = pp[m], pmc = pm[c];
       const T vb = (T)vback(P, d);
       vf = (ppm + pmc - vb * (drm + drc)) / (T(2) * rho0 + drm + drc);
     } else {
@@ -308,7 +287,6 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
       const T gradphi = GM * (xc[d] + xm) / (dm * dcen * (dm + dcen));
       vf = vf - h * (gradp + gradphi);
     }
-    if (BC && d == 0 && i == G.n[0]) vf = T(0);  // injection face at x_max carries the wind
     A.v[d][c] = vf;
   }
 }
@@ -335,15 +313,15 @@ struct ViscArgs {
 // (dx rho_face).  All from the values before the stage: the new velocities go
 // to vn.  On level 0 the boundary faces (the injection face, walls under bc 2)
 // keep their values, and cells and faces past the boundary read its ghosts.
-template <typename T, bool BC>
+template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) {
   int id[3];
   if (!thread_cell(Box{{A.lo[0], A.lo[1], A.lo[2]}, {A.hi[0], A.hi[1], A.hi[2]}}, id[0], id[1], id[2])) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const T c2 = (T)P.visc, rho0 = (T)P.rho0, dx = (T)G.dx;
-  auto rho_at = [&](int i, int j, int k) -> T { return BC ? cread(A.rho, G, i, j, k) : A.rho[lin(G, i, j, k)]; };
+  auto rho_at = [&](int i, int j, int k) -> T { return BC ? cread<BC>(A.rho, G, i, j, k) : A.rho[lin(G, i, j, k)]; };
   auto v_at = [&](int d, int i, int j, int k) -> T {
-    return BC ? fread_bc(A.v[d], G, d, i, j, k) : A.v[d][lin(G, i, j, k)];
+    return BC ? fread_bc<BC>(A.v[d], G, d, i, j, k) : A.v[d][lin(G, i, j, k)];
   };
   // q_d and dv_d of the cell at p
   auto qd = [&](int d, const int *p, T &dv) -> T {
@@ -375,7 +353,7 @@ __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) 
     const T vold = A.v[d][c];
     T vnew = vold;
     const bool fixed = BC && ((d == 0 && id[0] == G.n[0]) ||
-                              (G.bc == 2 && d > 0 && (id[d] == 0 || id[d] == G.n[d])));
+                              (BC == 2 && d > 0 && (id[d] == 0 || id[d] == G.n[d])));
     if (!fixed) {
       int m[3] = {id[0] - (d == 0), id[1] - (d == 1), id[2] - (d == 2)};
       T dvc, dvm;
@@ -444,7 +422,7 @@ __device__ __forceinline__ T dtemp(T dr, T de, T rho0, T e0) {
 
 // Thermal diffusion (eqs. 19-22, energy flux down the gradient of e/rho with
 // coefficient chi rho0) and heat release L dt w_c / dx^3 (Sect. 3.4).
-template <typename T, bool BC>
+template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArgs<T> A) {
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
@@ -462,8 +440,8 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
       if (BC) {
         const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
         const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
-        Tm = dtemp(cread(A.rho, G, im, jm, km), cread(A.e, G, im, jm, km), rho0, e0);
-        Tp = dtemp(cread(A.rho, G, ip, jp, kp), cread(A.e, G, ip, jp, kp), rho0, e0);
+        Tm = dtemp(cread<BC>(A.rho, G, im, jm, km), cread<BC>(A.e, G, im, jm, km), rho0, e0);
+        Tp = dtemp(cread<BC>(A.rho, G, ip, jp, kp), cread<BC>(A.e, G, ip, jp, kp), rho0, e0);
       } else {
         const idx_t s = dstride(G, d);
         Tm = dtemp(A.rho[c - s], A.e[c - s], rho0, e0);
@@ -511,10 +489,10 @@ struct PassArgs {
 // Cell of the x pass at row (j, k) and x: false where level 0's boundary
 // holds the background (beyond x_max; under bc 2 beyond both flow ends), else
 // the cell to read (the nearest active one under bc 1).
-template <bool BC>
+template <int BC>
 __device__ __forceinline__ bool xcell_at(const Geo &G, int x, int j, int k, idx_t &c) {
   if (BC) {
-    if (x >= G.n[0] || (G.bc == 2 && x < 0)) return false;
+    if (x >= G.n[0] || (BC == 2 && x < 0)) return false;
     x = x < 0 ? 0 : x;
   }
   c = lin(G, x, j, k);
@@ -565,7 +543,7 @@ __host__ __device__ inline Box xtile_box(const Box &b) {
   return v;
 }
 
-template <typename T, bool BC>
+template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A) {
   int iv, j, k;
   if (!thread_cell(xtile_box(A.b), iv, j, k)) return;
@@ -584,7 +562,7 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   // momenta tangential to x beyond a flow end under bc 2: the mirror cell's
   idx_t ct = c;
   bool int_ = in;
-  if (BC && G.bc == 2 && !in) {
+  if (BC == 2 && !in) {
     ct = lin(G, mirror_idx(xl, G.n[0]), j, k);
     int_ = true;
   }
@@ -868,7 +846,7 @@ struct MarchArgs {
 
 // One column segment [c0, c1) of the quantity group GRP (0: rho, e, P-x, P+x;
 // 1: P-y, P+y, P-z, P+z) at in-plane position (i, t).
-template <typename T, int DIR, bool BC, int GRP>
+template <typename T, int DIR, int BC, int GRP>
 __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
                                              int i, int t, int c0, int c1) {
   constexpr int TD = (DIR == 1) ? 2 : 1;
@@ -941,7 +919,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   // ahead of their use
   // bc 2: across a wall (DIR is y or z) every quantity takes its mirror
   // image, and the two momenta normal to the wall swap and change sign
-  const bool walls = BC && G.bc == 2;
+  constexpr bool walls = BC == 2;
   constexpr int pa = (DIR == 1) ? 0 : 2;  // P-, P+ normal to DIR in group 1
   auto ld = [&](int u, int c) -> T {      // u < 0: the density
     const T *q = u < 0 ? A.qi[0] : qin[u];
@@ -1044,7 +1022,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   }
 }
 
-template <typename T, int DIR, bool BC>
+template <typename T, int DIR, int BC>
 __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   constexpr int TD = (DIR == 1) ? 2 : 1;
   constexpr int T1 = (DIR == 0) ? 1 : 0;
@@ -1099,7 +1077,7 @@ __device__ __forceinline__ int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i
 // CommUp (Sect. 3.2.1, Fig. 2): every fine entry outside the fine active set
 // from the 27 coarse entries around its host, interpolating along z, then y,
 // then x.  The background is uniform, so departures interpolate like values.
-template <typename T, bool CBC>
+template <typename T, int CBC>
 __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A) {
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
@@ -1120,8 +1098,8 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A)
   auto C = [&](int a, int b, int cc) -> T {
     const int ci = H[0] + a, cj = H[1] + b, ck = H[2] + cc;
     if (CBC) {
-      if (A.stag < 0) return cread(A.Q, Gc, ci, cj, ck);
-      return fread_bc(A.Q, Gc, A.stag, ci, cj, ck);
+      if (A.stag < 0) return cread<CBC>(A.Q, Gc, ci, cj, ck);
+      return fread_bc<CBC>(A.Q, Gc, A.stag, ci, cj, ck);
     }
     return A.Q[lin(Gc, ci, cj, ck)];
   };
@@ -1196,7 +1174,7 @@ __device__ __forceinline__ bool is_covered(const RedArgs<T> &A, int i, int j, in
          k < A.cov_hi[2];
 }
 
-// block sum of three values into part[3*block]; fixed order for a fixed grid
+// block sum of three values into part[q * blocks + block]; fixed order for a fixed grid
 __device__ void block_sum3(double a, double b, double c, double *part) {
   __shared__ double sh[3][BX * BY / 64];
   a = wave_sum(a);
@@ -1218,9 +1196,11 @@ __device__ void block_sum3(double a, double b, double c, double *part) {
       s1 += sh[1][q];
       s2 += sh[2][q];
     }
-    part[3 * blk + 0] = s0;
-    part[3 * blk + 1] = s1;
-    part[3 * blk + 2] = s2;
+    // three planes of one value per block (coalesced for the final sum)
+    const long nb = gridDim.x;
+    part[blk] = s0;
+    part[nb + blk] = s1;
+    part[2 * nb + blk] = s2;
   }
 }
 
@@ -1296,7 +1276,7 @@ __device__ void final3_body(const FinalArgs &A) {
 #pragma unroll
       for (int u = 0; u < 8; ++u)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) x[u][q] = p[3 * (size_t)(b + u * FT) + q];
+        for (int q = 0; q < 3; ++q) x[u][q] = p[(size_t)q * n + b + u * FT];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         s0 += x[u][0];
@@ -1305,9 +1285,9 @@ __device__ void final3_body(const FinalArgs &A) {
       }
     }
     for (; b < n; b += FT) {
-      s0 += p[3 * (size_t)b + 0];
-      s1 += p[3 * (size_t)b + 1];
-      s2 += p[3 * (size_t)b + 2];
+      s0 += p[b];
+      s1 += p[(size_t)n + b];
+      s2 += p[2 * (size_t)n + b];
     }
   }
   s0 = wave_sum(s0);
@@ -1425,7 +1405,7 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
 // an active cell and one of its faces, taken at the face's owner (the cell on
 // its high side, or the last cell for face n), which holds both adjacent cells'
 // densities and energies.
-template <typename T, bool REBUILD, bool KICK, bool POST>
+template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
 __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
   int i, j, k;
   const bool ok = thread_cell(A.b, i, j, k);
@@ -1459,25 +1439,25 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
         if (POST) sig = fmax(sig, fabs(vback(P, 0)) + cs_own);
         return;
       }
-      if (d > 0 && G.bc == 2 && (last || id[d] == 0)) {
+      if (d > 0 && BCM == 2 && (last || id[d] == 0)) {
         A.v[d][cf] = T(0);  // a wall: no normal velocity
         if (POST) sig = fmax(sig, cs_own);
         return;
       }
       T dcr = drc, der = dec, xr = xc[d], r2r = r2c, dr_ = dcen;
       if (last) {
-        dcr = cread(rho, G, pi, pj, pk);
-        der = cread(e, G, pi, pj, pk);
+        dcr = cread<BCM>(rho, G, pi, pj, pk);
+        der = cread<BCM>(e, G, pi, pj, pk);
         xr = xcen<T>(G, d, id[d] + 1);
         r2r = r2c - xc[d] * xc[d] + xr * xr;
         dr_ = sqrt(r2r);
       }
       const int im = pi - (d == 0), jm = pj - (d == 1), km = pk - (d == 2);
-      const T drm = cread(rho, G, im, jm, km), dem = cread(e, G, im, jm, km);
+      const T drm = cread<BCM>(rho, G, im, jm, km), dem = cread<BCM>(e, G, im, jm, km);
       T vf;
       if (REBUILD) {
         const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
-        const T ppm = cread(pp, G, im, jm, km), pmc = cread(pm, G, pi, pj, pk);
+        const T ppm = cread<BCM>(pp, G, im, jm, km), pmc = cread<BCM>(pm, G, pi, pj, pk);
         const T vb = (T)vback(P, d);
         vf = (ppm + pmc - vb * (drm + dcr)) / (T(2) * rho0 + drm + dcr);
       } else {
@@ -1691,17 +1671,24 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
     const dim3 gr = grid_of(A.b);
     RedArgs<T> R{};
     if (post) R = red_args<T>(G, *post, 0, S);
-    if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, true, true, true>), gr, bl, st, G, P, A, R);
-    else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, true, true, false>), gr, bl, st, G, P, A, R);
-    else if (rebuild) DFK_LAUNCH((k_kick0<T, true, false, false>), gr, bl, st, G, P, A, R);
-    else DFK_LAUNCH((k_kick0<T, false, true, false>), gr, bl, st, G, P, A, R);
+    if (G.bc == 2) {
+      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
+      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
+      else if (rebuild) DFK_LAUNCH((k_kick0<T, 2, true, false, false>), gr, bl, st, G, P, A, R);
+      else DFK_LAUNCH((k_kick0<T, 2, false, true, false>), gr, bl, st, G, P, A, R);
+    } else {
+      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, 1, true, true, true>), gr, bl, st, G, P, A, R);
+      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, 1, true, true, false>), gr, bl, st, G, P, A, R);
+      else if (rebuild) DFK_LAUNCH((k_kick0<T, 1, true, false, false>), gr, bl, st, G, P, A, R);
+      else DFK_LAUNCH((k_kick0<T, 1, false, true, false>), gr, bl, st, G, P, A, R);
+    }
     return;
   }
   const dim3 gr = grid_of(A.b);
   {
-    if (rebuild && do_kick) DFK_LAUNCH((k_kick<T, false, true, true>), gr, bl, st, G, P, A);
-    else if (rebuild) DFK_LAUNCH((k_kick<T, false, true, false>), gr, bl, st, G, P, A);
-    else DFK_LAUNCH((k_kick<T, false, false, true>), gr, bl, st, G, P, A);
+    if (rebuild && do_kick) DFK_LAUNCH((k_kick<T, true, true>), gr, bl, st, G, P, A);
+    else if (rebuild) DFK_LAUNCH((k_kick<T, true, false>), gr, bl, st, G, P, A);
+    else DFK_LAUNCH((k_kick<T, false, true>), gr, bl, st, G, P, A);
   }
 }
 
@@ -1768,8 +1755,9 @@ static void viscosity_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B,
     ub.lo[e] = A.lo[e];
     ub.hi[e] = A.hi[e];
   }
-  if (G.bc) DFK_LAUNCH((k_visc<T, true>), grid_of(ub), dim3(BX, BY), st, G, P, A);
-  else DFK_LAUNCH((k_visc<T, false>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  if (G.bc == 2) DFK_LAUNCH((k_visc<T, 2>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  else if (G.bc) DFK_LAUNCH((k_visc<T, 1>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  else DFK_LAUNCH((k_visc<T, 0>), grid_of(ub), dim3(BX, BY), st, G, P, A);
   for (int d = 0; d < 3; ++d) {
     Box fb;
     for (int e = 0; e < 3; ++e) {
@@ -1803,8 +1791,9 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.fac = fac;
   A.do_diff = do_diff && P.chi > 0.0;
   A.do_heat = do_heat && P.L != 0.0;
-  if (G.bc) DFK_LAUNCH((k_diffuse_heat<T, true>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
-  else DFK_LAUNCH((k_diffuse_heat<T, false>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  else if (G.bc) DFK_LAUNCH((k_diffuse_heat<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  else DFK_LAUNCH((k_diffuse_heat<T, 0>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
 }
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
                   double fac, bool do_diff, bool do_heat) {
@@ -1843,12 +1832,12 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   if (dir == 0) {
     const dim3 bl(BX, BY);
     const int n = G.n[0];
-    if (G.bc == 2) DFK_LAUNCH((k_xpass<T, true>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    if (G.bc == 2) DFK_LAUNCH((k_xpass<T, 2>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= BX) DFK_LAUNCH((k_xrow<T, 1>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= 2 * BX && n % 2 == 0) DFK_LAUNCH((k_xrow<T, 2>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= 4 * BX && n % 4 == 0) DFK_LAUNCH((k_xrow<T, 4>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
-    else if (G.bc) DFK_LAUNCH((k_xpass<T, true>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
-    else DFK_LAUNCH((k_xpass<T, false>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    else if (G.bc) DFK_LAUNCH((k_xpass<T, 1>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    else DFK_LAUNCH((k_xpass<T, 0>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
     return;
   }
   MarchArgs<T> M;
@@ -1874,12 +1863,15 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   const long ntb = (M.hi[td] - M.lo[td] + 1) / 2;
   const long nch = (ext + M.chunk - 1) / M.chunk;
   const dim3 gr((unsigned)(nbx * ntb * nch)), bl(64, 4);
-  if (G.bc) {
-    if (dir == 1) DFK_LAUNCH((k_march<T, 1, true>), gr, bl, st, G, P, M);
-    else DFK_LAUNCH((k_march<T, 2, true>), gr, bl, st, G, P, M);
+  if (G.bc == 2) {
+    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 2>), gr, bl, st, G, P, M);
+    else DFK_LAUNCH((k_march<T, 2, 2>), gr, bl, st, G, P, M);
+  } else if (G.bc) {
+    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 1>), gr, bl, st, G, P, M);
+    else DFK_LAUNCH((k_march<T, 2, 1>), gr, bl, st, G, P, M);
   } else {
-    if (dir == 1) DFK_LAUNCH((k_march<T, 1, false>), gr, bl, st, G, P, M);
-    else DFK_LAUNCH((k_march<T, 2, false>), gr, bl, st, G, P, M);
+    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 0>), gr, bl, st, G, P, M);
+    else DFK_LAUNCH((k_march<T, 2, 0>), gr, bl, st, G, P, M);
   }
 }
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
@@ -1924,8 +1916,9 @@ static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const
     A.Q = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
     A.out = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
     A.b = full_box(Gf);
-    if (Gc.bc) DFK_LAUNCH((k_commup<T, true>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
-    else DFK_LAUNCH((k_commup<T, false>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
+    if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
+    else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
+    else DFK_LAUNCH((k_commup<T, 0>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
   }
 }
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf, LevBufs &Bf,
