@@ -273,7 +273,7 @@ PMC_KINDS = ((("k_kick0<", ", false, true, false>"), "kick"), (("k_kick<", ", fa
              (("k_step_final",), "force"), (("k_post<",), "post"))
 
 
-def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
+def summarize_pmc(fetch_csv: str, write_csv: str, precision: str = "fp64") -> None:
     """HBM bytes per launch of each kernel kind from a FETCH_SIZE and a
     WRITE_SIZE pass of rocprofv3 over `bench.py ... --copy-probe`.  Both
     counters read in KiB per dispatch; each is scaled by what it reads for the
@@ -308,14 +308,16 @@ def summarize_pmc(fetch_csv: str, write_csv: str) -> None:
            "workload": "128^3 single level FP64 (the bench workload)",
            "kernels": {k: {"fetch_bytes": int(f), "write_bytes": int(w), "bytes_per_launch": int(f + w)}
                        for k, (f, w) in sorted(kinds.items())}}
-    with open(os.path.join(ROOT, "profiles", "pmc_traffic_config2.json"), "w") as fh:
-        json.dump(out, fh, indent=1)
+    if precision == "fp64":  # the bench line reads the FP64 figures
+        with open(os.path.join(ROOT, "profiles", "pmc_traffic_config2.json"), "w") as fh:
+            json.dump(out, fh, indent=1)
+    esz = 4 if precision == "fp32" else 8
     cells = workload()[0]["nx"] * workload()[0]["ny"] * workload()[0]["nz"]
     print(f"scale factors: FETCH_SIZE x{kf:.3f}, WRITE_SIZE x{kw:.3f} (1 GiB copy probe)\n")
     print("| kind | fetch MiB | write MiB | total MiB | algorithmic MiB |")
     print("|---|---:|---:|---:|---:|")
     for k, (f, w) in sorted(kinds.items()):
-        alg = (POST_BYTES if k == "post" else ALG_BYTES.get(k, 0)) * cells / 2**20
+        alg = (POST_BYTES if k == "post" else ALG_BYTES.get(k, 0)) * cells / 2**20 * esz / 8
         print(f"| {k} | {f / 2**20:.1f} | {w / 2**20:.1f} | {(f + w) / 2**20:.1f} | {alg:.1f} |")
 
 
@@ -338,7 +340,7 @@ def main():
                     help="write profiles/pmc_traffic_config2.json from two counter passes and exit")
     args = ap.parse_args()
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc)
+        summarize_pmc(*args.summarize_pmc, precision=args.precision)
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "

@@ -1421,11 +1421,13 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
     const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
     const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
     const T dcen = sqrt(r2c);
-    // signal speed of a cell from its density and energy departures (FP64)
+    // sound speed of a cell from its density and energy departures, in the
+    // storage type (the maximum over the grid is taken in FP64)
+    const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
     auto sound = [&](T dr, T de) -> double {
-      const double r = P.rho0 + (double)dr, en = P.e0 + (double)de;
-      if (!(r > 0.0) || !(en > 0.0) || !isfinite(r) || !isfinite(en)) bad = 1;
-      return sqrt(P.gamma * P.gm1 * en / r);
+      const T r = rho0 + dr, en = e0 + de;
+      if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
+      return (double)sqrt(gg * en / r);
     };
     double cs_own = 0.0;
     if (POST) cs_own = sound(drc, dec);
