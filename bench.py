@@ -343,8 +343,8 @@ def main():
         summarize_pmc(*args.summarize_pmc, precision=args.precision)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(each run is independent; see DESIGN.md for how the update would shard)",
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent runs of a sweep go to separate GPUs as separate processes)",
               file=sys.stderr)
         sys.exit(2)
 

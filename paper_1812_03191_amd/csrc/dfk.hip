@@ -102,12 +102,23 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
   return (T)(((double)i - 0.5 * (double)G.n[d] + 0.5) * G.dx);
 }
 
+// Quotient and square root in the storage type: IEEE-rounded in FP64; in
+// FP32 the hardware reciprocal and square root (about 1 ulp each, normal
+// operands), a few instructions instead of the correctly rounded expansions.
+// Every FP32 use has a positive normal operand (densities and energies near
+// their background, distances of at least the Plummer length, sums of two
+// slopes of one sign).
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // van Leer's harmonic limited difference; evaluated without a branch (the
 // quotient of the discarded side is selected away)
 template <typename T>
 __device__ __forceinline__ T vleer(T a, T b) {
   const T p = a * b;
-  const T r = (T(2) * p) / (a + b);
+  const T r = qdiv(T(2) * p, a + b);
   return p > T(0) ? r : T(0);
 }
 
@@ -261,7 +272,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
   const T drc = rho[c], dec = e[c];
   const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
   const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
-  const T dcen = sqrt(r2c);
+  const T dcen = qsqrt(r2c);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     bool in = i >= A.flo[d][0] && i < A.fhi[d][0] && j >= A.flo[d][1] && j < A.fhi[d][1] &&
@@ -281,10 +292,10 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
     }
     if (KICK) {
       const T rface = rho0 + T(0.5) * (drm + drc);
-      const T gradp = gm1 * (dec - dem) / (dx * rface);
+      const T gradp = qdiv(gm1 * (dec - dem), dx * rface);
       const T xm = xc[d] - dx;
-      const T dm = sqrt(r2c - xc[d] * xc[d] + xm * xm);
-      const T gradphi = GM * (xc[d] + xm) / (dm * dcen * (dm + dcen));
+      const T dm = qsqrt(r2c - xc[d] * xc[d] + xm * xm);
+      const T gradphi = qdiv(GM * (xc[d] + xm), dm * dcen * (dm + dcen));
       vf = vf - h * (gradp + gradphi);
     }
     A.v[d][c] = vf;
@@ -342,7 +353,7 @@ __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) 
       const T q = qd(d, id, dv);
       de += q * dv;
     }
-    A.e[c] = A.e[c] - dt * de / dx;
+    A.e[c] = A.e[c] - qdiv(dt * de, dx);
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -359,7 +370,7 @@ __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) 
       T dvc, dvm;
       const T qc = qd(d, id, dvc), qm = qd(d, m, dvm);
       const T rface = rho0 + T(0.5) * (rho_at(m[0], m[1], m[2]) + rho_at(id[0], id[1], id[2]));
-      vnew = vold - dt * (qc - qm) / (dx * rface);
+      vnew = vold - qdiv(dt * (qc - qm), dx * rface);
     }
     A.vn[d][c] = vnew;
   }
@@ -393,11 +404,12 @@ __global__ void __launch_bounds__(BX * BY) k_compress(Geo G, Phys P, CellArgs<T>
   if (!thread_cell(A.b, i, j, k)) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const idx_t c = lin(G, i, j, k);
-  const T divv = ((A.v[0][c + 1] - A.v[0][c]) + (A.v[1][c + G.sy] - A.v[1][c]) +
-                  (A.v[2][c + G.sz] - A.v[2][c])) / (T)G.dx;
+  const T divv = qdiv((A.v[0][c + 1] - A.v[0][c]) + (A.v[1][c + G.sy] - A.v[1][c]) +
+                           (A.v[2][c + G.sz] - A.v[2][c]),
+                       (T)G.dx);
   const T a = T(0.5) * (T)P.gm1 * dt * divv;
   const T de = A.e[c];
-  A.e[c] = (de * (T(1) - a) - T(2) * a * (T)P.e0) / (T(1) + a);
+  A.e[c] = qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a);
 }
 
 // ---------------------------------------------------- diffusion + heat
@@ -417,7 +429,7 @@ struct DiffArgs {
 // departure of e/rho from e0/rho0
 template <typename T>
 __device__ __forceinline__ T dtemp(T dr, T de, T rho0, T e0) {
-  return (rho0 * de - e0 * dr) / (rho0 * (rho0 + dr));
+  return qdiv(rho0 * de - e0 * dr, rho0 * (rho0 + dr));
 }
 
 // Thermal diffusion (eqs. 19-22, energy flux down the gradient of e/rho with
@@ -438,10 +450,15 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
     for (int d = 0; d < 3; ++d) {
       T Tm, Tp;
       if (BC) {
-        const int im = i - (d == 0), jm = j - (d == 1), km = k - (d == 2);
-        const int ip = i + (d == 0), jp = j + (d == 1), kp = k + (d == 2);
-        Tm = dtemp(cread<BC>(A.rho, G, im, jm, km), cread<BC>(A.e, G, im, jm, km), rho0, e0);
-        Tp = dtemp(cread<BC>(A.rho, G, ip, jp, kp), cread<BC>(A.e, G, ip, jp, kp), rho0, e0);
+        // level 0 (as cread): past x_max, and past x_min under bc 2, the
+        // background (zero departures); elsewhere past the boundary the last
+        // cell again (outflow copies and wall mirrors agree one cell out)
+        const int id = d == 0 ? i : (d == 1 ? j : k);
+        const idx_t s = dstride(G, d);
+        const bool bm = BC == 2 && d == 0 && id == 0, bp = d == 0 && id == G.n[0] - 1;
+        const idx_t cm = id > 0 ? c - s : c, cp = id < G.n[d] - 1 ? c + s : c;
+        Tm = bm ? T(0) : dtemp(A.rho[cm], A.e[cm], rho0, e0);
+        Tp = bp ? T(0) : dtemp(A.rho[cp], A.e[cp], rho0, e0);
       } else {
         const idx_t s = dstride(G, d);
         Tm = dtemp(A.rho[c - s], A.e[c - s], rho0, e0);
@@ -449,7 +466,7 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
       }
       lap += (Tp - Tc) - (Tc - Tm);
     }
-    en = dec + dt * (T)(P.chi * P.rho0) * lap / (T)(G.dx * G.dx);
+    en = dec + qdiv(dt * (T)(P.chi * P.rho0) * lap, (T)(G.dx * G.dx));
   }
   if (A.do_heat && A.hw_n[0] > 0) {
     const int a = i - A.hw_lo[0], b = j - A.hw_lo[1], d = k - A.hw_lo[2];
@@ -567,10 +584,10 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
     int_ = true;
   }
   const T dr = in ? gld(A.qi[0], c) : T(0);
-  const T irr = T(1) / (rho0 * (rho0 + dr));
+  const T irr = qdiv(T(1), rho0 * (rho0 + dr));
   // velocity departure on the left face (faces lo..hi are the ones used)
   const T da = gld(A.v[0], lin(G, clampi(x, A.b.lo[0], A.b.hi[0]), j, k));
-  const T a = vb + da, nu = a * dt / dx;
+  const T a = vb + da, nu = qdiv(a * dt, dx);
   const T M0 = rho0 * vb * mfac;
   auto left_face = [&](T sv) -> T {
     const T sm = from_left(sv), sp = from_right(sv);
@@ -730,9 +747,9 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
   }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    irr[r] = T(1) / (rho0 * (rho0 + dr[r]));
+    irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
     a[r] = vb + da[r];
-    nu[r] = a[r] * dt / dx;
+    nu[r] = qdiv(a[r] * dt, dx);
   }
   // left-face value of the upwind van Leer reconstruction of s, per cell
   auto left_faces = [&](const T (&sv)[R], T (&fv)[R]) {
@@ -938,8 +955,8 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     const T r_m2 = ld(-1, c0 - 2), r_m1 = ld(-1, c0 - 1);
     w0[0] = ld(-1, c0);
     w1[0] = ld(-1, c0 + 1);
-    const T ir_m2 = T(1) / (rho0 * (rho0 + r_m2)), ir_m1 = T(1) / (rho0 * (rho0 + r_m1));
-    const T ir_0 = T(1) / (rho0 * (rho0 + w0[0])), ir_p1 = T(1) / (rho0 * (rho0 + w1[0]));
+    const T ir_m2 = qdiv(T(1), rho0 * (rho0 + r_m2)), ir_m1 = qdiv(T(1), rho0 * (rho0 + r_m1));
+    const T ir_0 = qdiv(T(1), rho0 * (rho0 + w0[0])), ir_p1 = qdiv(T(1), rho0 * (rho0 + w1[0]));
     sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = w0[0]; s1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -983,7 +1000,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     for (int u = 0; u < 4; ++u)
       if (u < nq) nn[u + 1] = ld(u, c + 3);
     const T vn = gld(A.v, base + min(c + 2, c1) * st);
-    const T ir2 = T(1) / (rho0 * (rho0 + w2[0]));
+    const T ir2 = qdiv(T(1), rho0 * (rho0 + w2[0]));
     T s2[5];
     s2[0] = w2[0];
 #pragma unroll
@@ -1409,7 +1426,8 @@ template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
 __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
   int i, j, k;
   const bool ok = thread_cell(A.b, i, j, k);
-  double fx = 0.0, fy = 0.0, fz = 0.0, sig = 0.0;
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  T sig = T(0);
   int bad = 0;
   if (ok) {
     const T h = (T)(A.fac * A.dtp[0]);
@@ -1420,25 +1438,25 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
     const T drc = rho[c], dec = e[c];
     const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
     const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
-    const T dcen = sqrt(r2c);
-    // sound speed of a cell from its density and energy departures, in the
-    // storage type (the maximum over the grid is taken in FP64)
+    const T dcen = qsqrt(r2c);
+    // sound speed of a cell from its density and energy departures, and the
+    // signal speeds, in the storage type (their maximum is exact in any type)
     const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
-    auto sound = [&](T dr, T de) -> double {
+    auto sound = [&](T dr, T de) -> T {
       const T r = rho0 + dr, en = e0 + de;
       if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
-      return (double)sqrt(gg * en / r);
+      return qsqrt(qdiv(gg * en, r));
     };
-    double cs_own = 0.0;
+    T cs_own = T(0);
     if (POST) cs_own = sound(drc, dec);
     // face on the low side of cell p (p = own cell, or the virtual cell n past
     // the last one along d), with the own cell's values when p is the own cell
     auto face = [&](int d, bool last) {
-      const int pi = i + (last && d == 0), pj = j + (last && d == 1), pk = k + (last && d == 2);
-      const idx_t cf = last ? lin(G, pi, pj, pk) : c;
+      const idx_t sd = dstride(G, d);
+      const idx_t cf = last ? c + sd : c;
       if (last && d == 0) {
         A.v[0][cf] = T(0);  // injection face at x_max carries the wind
-        if (POST) sig = fmax(sig, fabs(vback(P, 0)) + cs_own);
+        if (POST) sig = fmax(sig, fabs((T)vback(P, 0)) + cs_own);
         return;
       }
       if (d > 0 && BCM == 2 && (last || id[d] == 0)) {
@@ -1446,36 +1464,45 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
         if (POST) sig = fmax(sig, cs_own);
         return;
       }
-      T dcr = drc, der = dec, xr = xc[d], r2r = r2c, dr_ = dcen;
+      // the cells on the two sides of the face, through the boundary
+      // conditions: for face n (reached here only along y and z under bc 1)
+      // both sides read the last cell (zero-gradient outflow); below face 0
+      // lies the own cell again (outflow) or, along x under bc 2, the
+      // background (zero departures)
+      T xr = xc[d], r2r = r2c, dr_ = dcen;
+      idx_t cm = c;
+      bool bgm = false;
       if (last) {
-        dcr = cread<BCM>(rho, G, pi, pj, pk);
-        der = cread<BCM>(e, G, pi, pj, pk);
         xr = xcen<T>(G, d, id[d] + 1);
         r2r = r2c - xc[d] * xc[d] + xr * xr;
-        dr_ = sqrt(r2r);
+        dr_ = qsqrt(r2r);
+      } else if (id[d] > 0) {
+        cm = c - sd;
+      } else {
+        bgm = BCM == 2 && d == 0;
       }
-      const int im = pi - (d == 0), jm = pj - (d == 1), km = pk - (d == 2);
-      const T drm = cread<BCM>(rho, G, im, jm, km), dem = cread<BCM>(e, G, im, jm, km);
+      const T dcr = drc, der = dec;
+      const T drm = bgm ? T(0) : rho[cm], dem = bgm ? T(0) : e[cm];
       T vf;
       if (REBUILD) {
         const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
-        const T ppm = cread<BCM>(pp, G, im, jm, km), pmc = cread<BCM>(pm, G, pi, pj, pk);
+        const T ppm = bgm ? T(0) : pp[cm], pmc = pm[c];
         const T vb = (T)vback(P, d);
-        vf = (ppm + pmc - vb * (drm + dcr)) / (T(2) * rho0 + drm + dcr);
+        vf = qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
       } else {
         vf = A.v[d][cf];
       }
       if (KICK) {
         const T rface = rho0 + T(0.5) * (drm + dcr);
-        const T gradp = gm1 * (der - dem) / (dx * rface);
+        const T gradp = qdiv(gm1 * (der - dem), dx * rface);
         const T xm = xr - dx;
-        const T dm = sqrt(r2r - xr * xr + xm * xm);
-        const T gradphi = GM * (xr + xm) / (dm * dr_ * (dm + dr_));
+        const T dm = qsqrt(r2r - xr * xr + xm * xm);
+        const T gradphi = qdiv(GM * (xr + xm), dm * dr_ * (dm + dr_));
         vf = vf - h * (gradp + gradphi);
       }
       A.v[d][cf] = vf;
       if (POST) {
-        const double a = fabs(vback(P, d) + (double)vf);
+        const T a = fabs((T)vback(P, d) + vf);
         // the active cells beside the face: the one below (own cell for the
         // boundary face, cell id-1 otherwise) and the own cell for a low face
         if (last) {
@@ -1492,20 +1519,18 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
       if (id[d] == G.n[d] - 1) face(d, true);
     }
     if (POST) {
-      // force of the gas in this cell on the perturber, eq. 18 (FP64)
-      const double x = xcen<double>(G, 0, i), y = xcen<double>(G, 1, j), z = xcen<double>(G, 2, k);
-      const double d2 = x * x + y * y + z * z + P.eps2;
-      const double vol = G.dx * G.dx * G.dx;
-      const double w = P.GM * (double)drc * vol / (d2 * sqrt(d2));
-      fx = w * x;
-      fy = w * y;
-      fz = w * z;
+      // force of the gas in this cell on the perturber, eq. 18: the cell's
+      // term in the storage type, the sum in FP64
+      const T w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
+      fx = (double)(w * xc[0]);
+      fy = (double)(w * xc[1]);
+      fz = (double)(w * xc[2]);
       if (!isfinite(sig)) bad = 1;
     }
   }
   if (POST) {
     block_sum3(fx, fy, fz, R.part);
-    block_signal(sig, bad, R.spart, R.S);
+    block_signal((double)sig, bad, R.spart, R.S);
   }
 }
 
