@@ -1281,6 +1281,22 @@ struct FinalArgs {
 constexpr int FT = 1024;
 constexpr int FW = FT / 64;
 
+// thread 0: the wave sums sh (in wave order) into out, then the log entry
+__device__ void final3_finish(const FinalArgs &A, const double (*sh)[FW]) {
+  for (int q = 0; q < 3; ++q) {
+    double t = 0.0;
+    for (int v = 0; v < FW; ++v) t += sh[q][v];
+    A.out[q] = t;
+  }
+  if (A.flog) {
+    const unsigned int n = A.S->nlog;
+    double *e = A.flog + 4 * (size_t)(n % FLOG);
+    for (int q = 0; q < 3; ++q) e[q] = A.out[q];
+    e[3] = A.S->t;
+    A.S->nlog = n + 1;
+  }
+}
+
 __device__ void final3_body(const FinalArgs &A) {
   __shared__ double sh[3][FW];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -1317,20 +1333,7 @@ __device__ void final3_body(const FinalArgs &A) {
     sh[2][w] = s2;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int q = 0; q < 3; ++q) {
-      double t = 0.0;
-      for (int v = 0; v < FW; ++v) t += sh[q][v];
-      A.out[q] = t;
-    }
-    if (A.flog) {
-      const unsigned int n = A.S->nlog;
-      double *e = A.flog + 4 * (size_t)(n % FLOG);
-      for (int q = 0; q < 3; ++q) e[q] = A.out[q];
-      e[3] = A.S->t;
-      A.S->nlog = n + 1;
-    }
-  }
+  if (threadIdx.x == 0) final3_finish(A, sh);
   __syncthreads();
 }
 
@@ -1544,6 +1547,22 @@ struct DtArgs {
 };
 
 // coarse step cfl * min_l 2^l min(dx_l / smax_l, dx_l^2 / (6 chi)) (eq. 55, xi = 2)
+// thread 0: the step lengths from each level's largest signal speed smax
+__device__ void dt_finish(const Phys &P, const DtArgs &A, Scal *S, const double *smax) {
+  double best = INFINITY;
+  for (int l = 0; l < A.nl; ++l) {
+    double dtl = A.dx[l] / smax[l];
+    if (P.chi > 0.0) dtl = fmin(dtl, A.dx[l] * A.dx[l] / (6.0 * P.chi));
+    S->dtl[l] = P.cfl * dtl;  // the level's own limit (for the sub-cycling criterion)
+    dtl = ldexp(dtl, l);
+    best = fmin(best, dtl);
+  }
+  if (A.advance == 2) return;  // limits only: the host sets the schedule
+  const double dt0 = P.cfl * best;
+  for (int l = 0; l < A.nl; ++l) S->dt[l] = ldexp(dt0, -l);
+  if (A.advance) S->t += dt0;
+}
+
 __device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
   __shared__ double sh[FW];
   __shared__ double smax[MAXLEV];
@@ -1570,29 +1589,77 @@ __device__ void dt_body(const Phys &P, const DtArgs &A, Scal *S) {
     }
     __syncthreads();
   }
-  if (threadIdx.x != 0) return;
-  double best = INFINITY;
-  for (int l = 0; l < A.nl; ++l) {
-    double dtl = A.dx[l] / smax[l];
-    if (P.chi > 0.0) dtl = fmin(dtl, A.dx[l] * A.dx[l] / (6.0 * P.chi));
-    S->dtl[l] = P.cfl * dtl;  // the level's own limit (for the sub-cycling criterion)
-    dtl = ldexp(dtl, l);
-    best = fmin(best, dtl);
-  }
-  if (A.advance == 2) return;  // limits only: the host sets the schedule
-  const double dt0 = P.cfl * best;
-  for (int l = 0; l < A.nl; ++l) S->dt[l] = ldexp(dt0, -l);
-  if (A.advance) S->t += dt0;
+  if (threadIdx.x == 0) dt_finish(P, A, S, smax);
 }
 
 __global__ void __launch_bounds__(FT) k_dt_final(Phys P, DtArgs A, Scal *S) { dt_body(P, A, S); }
 
-// between two steps: the force of the state just reached (logged at its
-// time), then the next step's time step from the same state's signal speeds
-__global__ void __launch_bounds__(FT) k_step_final(Phys P, FinalArgs F, DtArgs D, Scal *S, int do_force,
-                                                     int do_dt) {
-  if (do_force) final3_body(F);
-  if (do_dt) dt_body(P, D, S);
+// Between two steps: the force of the state just reached (logged at its
+// time), then the next step's time step from the same state's signal speeds.
+// One pass reads the partials of both (the force planes and the signal
+// speeds of a block side by side, all in flight together); the sums keep the
+// order of final3_body and the maxima are those of dt_body.
+template <bool do_force, bool do_dt>
+__global__ void __launch_bounds__(FT) k_step_final(Phys P, FinalArgs F, DtArgs D, Scal *S) {
+  __shared__ double sh[3][FW];
+  __shared__ double shm[MAXLEV][FW];
+  __shared__ double smax[MAXLEV];
+  const int t = threadIdx.x, w = t / 64;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int l = 0; l < D.nl; ++l) {
+    const double *p = F.part[l], *q = D.part[l];
+    const int n = D.npart[l];
+    double m = 0.0;
+    int b = t;
+    for (; b + 7 * FT < n; b += 8 * FT) {
+      double x[8][3], y[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (do_force)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) x[u][c] = p[(size_t)c * n + b + u * FT];
+        if (do_dt) y[u] = q[b + u * FT];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (do_force) {
+          s0 += x[u][0];
+          s1 += x[u][1];
+          s2 += x[u][2];
+        }
+        if (do_dt) m = fmax(m, y[u]);
+      }
+    }
+    for (; b < n; b += FT) {
+      if (do_force) {
+        s0 += p[b];
+        s1 += p[(size_t)n + b];
+        s2 += p[2 * (size_t)n + b];
+      }
+      if (do_dt) m = fmax(m, q[b]);
+    }
+    m = wave_max(m);
+    if (t % 64 == 0) shm[l][w] = m;
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (t % 64 == 0) {
+    sh[0][w] = s0;
+    sh[1][w] = s1;
+    sh[2][w] = s2;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  if (do_force) final3_finish(F, sh);
+  if (do_dt) {
+    for (int l = 0; l < D.nl; ++l) {
+      double v = shm[l][0];
+      for (int u = 1; u < FW; ++u) v = fmax(v, shm[l][u]);
+      smax[l] = v;
+    }
+    dt_finish(P, D, S, smax);
+  }
 }
 
 __global__ void k_zero(unsigned int *p, size_t n) {
@@ -2054,8 +2121,11 @@ void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P,
     parts[l] = B[l].part;
     np[l] = (int)part_count(G[l]);
   }
-  hipLaunchKernelGGL(k_step_final, dim3(1), dim3(FT), 0, st, P, final_args(parts, np, nl, S, 2, flog),
-                     dt_args(G, B, nl, do_dt == 2 ? 2 : 1), S, do_force, do_dt);
+  const FinalArgs F = final_args(parts, np, nl, S, 2, flog);
+  const DtArgs D = dt_args(G, B, nl, do_dt == 2 ? 2 : 1);
+  if (do_force && do_dt) hipLaunchKernelGGL((k_step_final<true, true>), dim3(1), dim3(FT), 0, st, P, F, D, S);
+  else if (do_force) hipLaunchKernelGGL((k_step_final<true, false>), dim3(1), dim3(FT), 0, st, P, F, D, S);
+  else if (do_dt) hipLaunchKernelGGL((k_step_final<false, true>), dim3(1), dim3(FT), 0, st, P, F, D, S);
 }
 
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {
