@@ -102,13 +102,21 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
   return (T)(((double)i - 0.5 * (double)G.n[d] + 0.5) * G.dx);
 }
 
-// Quotient and square root in the storage type: IEEE-rounded in FP64; in
-// FP32 the hardware reciprocal and square root (about 1 ulp each, normal
-// operands), a few instructions instead of the correctly rounded expansions.
-// Every FP32 use has a positive normal operand (densities and energies near
-// their background, distances of at least the Plummer length, sums of two
-// slopes of one sign).
-__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+// Quotient and square root in the storage type, from the hardware reciprocal
+// and square root instead of the correctly rounded expansions: in FP64 the
+// reciprocal takes two Newton steps and the quotient one residual correction
+// (within an ulp of the rounded quotient), the square root is IEEE-rounded; in
+// FP32 both are the single hardware instructions (about 1 ulp each).  Every
+// use has a normal nonzero divisor (densities and energies near their
+// background, distances of at least the Plummer length, sums of two slopes of
+// one sign; a van Leer quotient of slopes of opposite signs is selected away).
+__device__ __forceinline__ double qdiv(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  r = fma(r, fma(-b, r, 1.0), r);
+  const double q = a * r;
+  return fma(r, fma(-b, q, a), q);
+}
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
