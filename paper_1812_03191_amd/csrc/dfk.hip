@@ -96,6 +96,31 @@ __device__ __forceinline__ void gst(T *p, idx_t i, T v) {
   *reinterpret_cast<T *>(reinterpret_cast<char *>(p) + (unsigned)i * (unsigned)sizeof(T)) = v;
 }
 
+// W adjacent cells of a row in one lane: T itself, or a two-element vector
+// whose loads and stores are single 8- or 16-byte accesses (the first cell's
+// index is even and rows start 128-byte aligned)
+template <typename T, int W>
+struct lanes_of {
+  using type = T;
+};
+template <>
+struct lanes_of<double, 2> {
+  using type = double __attribute__((ext_vector_type(2)));
+};
+template <>
+struct lanes_of<float, 2> {
+  using type = float __attribute__((ext_vector_type(2)));
+};
+
+template <typename V, typename T>
+__device__ __forceinline__ V gldv(const T *p, idx_t i) {
+  return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(p) + (unsigned)i * (unsigned)sizeof(T));
+}
+template <typename V, typename T>
+__device__ __forceinline__ void gstv(T *p, idx_t i, V v) {
+  *reinterpret_cast<V *>(reinterpret_cast<char *>(p) + (unsigned)i * (unsigned)sizeof(T)) = v;
+}
+
 // cell-centre coordinate: the perturber is the central vertex of the level
 template <typename T>
 __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
@@ -118,6 +143,10 @@ __device__ __forceinline__ double qdiv(double a, double b) {
   return fma(r, fma(-b, q, a), q);
 }
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+template <typename V>
+__device__ __forceinline__ V qdiv(V a, V b) {
+  return V{qdiv(a.x, b.x), qdiv(a.y, b.y)};  // two-element vectors, per element
+}
 __device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
@@ -854,7 +883,8 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
 // difference and each face transfer is computed once, and the cell is written
 // as soon as its right face is known.  The eight quantities are split over two
 // waves of the block: one moves rho, e, P-x, P+x, the other P-y, P+y, P-z, P+z
-// (both compute the mass transfers they scale).
+// (both compute the mass transfers they scale).  A lane may own W = 2 adjacent
+// columns, whose cells then move as one 8- or 16-byte access.
 template <typename T>
 struct MarchArgs {
   int lo[3], hi[3];   // cells to update; DIR is the walked dimension
@@ -871,9 +901,13 @@ struct MarchArgs {
 
 // One column segment [c0, c1) of the quantity group GRP (0: rho, e, P-x, P+x;
 // 1: P-y, P+y, P-z, P+z) at in-plane position (i, t).
-template <typename T, int DIR, int BC, int GRP>
+// FRONT: the level has frontier transfers (a finer level's sums to take, or
+// its own to accumulate); without them the solver's transfers stand.
+template <typename T, int DIR, int BC, int GRP, bool FRONT, int W>
 __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
                                              int i, int t, int c0, int c1) {
+  static_assert(W == 1 || !FRONT, "frontier transfers are per column");
+  using V = typename lanes_of<T, W>::type;  // the W adjacent columns of a lane
   constexpr int TD = (DIR == 1) ? 2 : 1;
   constexpr int T1 = (DIR == 0) ? 1 : 0;
   constexpr int T2 = (DIR == 2) ? 1 : 2;
@@ -894,7 +928,11 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     return base + c * st;
   };
   constexpr int mq[4] = {GRP ? 4 : 1, GRP ? 5 : 2, GRP ? 6 : 3, GRP ? 7 : 1};
-  constexpr int nq = GRP ? 4 : 3;
+  constexpr int nq_n = GRP ? 4 : 3;
+  // the momenta across the wind (P-y .. P+z) have a zero background, and
+  // only x carries a background velocity: those terms are dropped outright
+  constexpr bool zq[4] = {mq[0] >= 4, mq[1] >= 4, mq[2] >= 4, mq[3] >= 4};
+  constexpr bool wind = DIR == 0;
   T q0[4], sb[4];
   const T *qin[4];
   T *qout[4];
@@ -910,7 +948,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   bool ov = false;
   long fbase = 0, fnt = 0;
   int flo = 0, fhi = 0;
-  if (A.facc) {
+  if (FRONT && A.facc) {
     const int a1 = tv1 - G.n[T1] / 4, a2 = tv2 - G.n[T2] / 4;
     if (a1 >= 0 && a2 >= 0 && a1 < G.n[T1] / 2 && a2 < G.n[T2] / 2) {
       ov = true;
@@ -920,22 +958,28 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       fhi = (3 * G.n[DIR]) / 4;
     }
   }
-  const bool acc_col = A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
+  const bool acc_col = FRONT && A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
   const long acc_nt = (long)G.n[T1] * G.n[T2];
   const long acc_i = (long)tv2 * G.n[T1] + tv1;
   // final transfer of quantity m through face f, given the solver's value
-  auto fix = [&](int f, int m, T F) -> T {
-    if (ov && (f == flo || f == fhi)) {
-      const T *a = A.facc + ((long)(DIR * 2 + (f == fhi)) * NQ + m) * fnt + fbase;
-      F = (a[0] + a[1]) + (a[A.fn[T1]] + a[A.fn[T1] + 1]);
+  auto fix = [&](int f, int m, V F) -> V {
+    if constexpr (!FRONT) {
+      return F;
+    } else {
+      if (ov && (f == flo || f == fhi)) {
+        const T *a = A.facc + ((long)(DIR * 2 + (f == fhi)) * NQ + m) * fnt + fbase;
+        F = (a[0] + a[1]) + (a[A.fn[T1]] + a[A.fn[T1] + 1]);
+      }
+      if (acc_col && f >= c0 && f < c1 && (f == 0 || f == G.n[DIR]))
+        A.acc[((long)(DIR * 2 + (f != 0)) * NQ + m) * acc_nt + acc_i] += F;
+      return F;
     }
-    if (acc_col && f >= c0 && f < c1 && (f == 0 || f == G.n[DIR]))
-      A.acc[((long)(DIR * 2 + (f != 0)) * NQ + m) * acc_nt + acc_i] += F;
-    return F;
   };
-  auto upwind = [&](T sl, T dl, T sr, T dr, T a, T nu) -> T {
+  auto upwind = [&](V sl, V dl, V sr, V dr, V a, V nu) -> V {
     return (a > T(0)) ? sl + T(0.5) * dl * (T(1) - nu) : sr - T(0.5) * dr * (T(1) + nu);
   };
+  // departure of the specific value of quantity u from raw departures (q, rho)
+  auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
 
   // window: departures of the specific values at c, c+1 (s0, s1; index 0 is
   // the density departure), limited difference at c (d0), transfer through
@@ -946,92 +990,92 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   // image, and the two momenta normal to the wall swap and change sign
   constexpr bool walls = BC == 2;
   constexpr int pa = (DIR == 1) ? 0 : 2;  // P-, P+ normal to DIR in group 1
-  auto ld = [&](int u, int c) -> T {      // u < 0: the density
+  auto ld = [&](int u, int c) -> V {      // u < 0: the density
     const T *q = u < 0 ? A.qi[0] : qin[u];
     if (walls && (c < 0 || c >= G.n[DIR])) {
       const idx_t m = base + mirror_idx(c, G.n[DIR]) * st;
-      if (GRP == 1 && (u == pa || u == pa + 1)) return -gld(qin[u ^ 1], m);
-      return gld(q, m);
+      if (GRP == 1 && (u == pa || u == pa + 1)) return -gldv<V>(qin[u ^ 1], m);
+      return gldv<V>(q, m);
     }
-    return gld(q, cidx(c));
+    return gldv<V>(q, cidx(c));
   };
 
-  T s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
-  T va;
+  V s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
+  V va;
   {
-    T sm2[5], sm1[5];
-    const T r_m2 = ld(-1, c0 - 2), r_m1 = ld(-1, c0 - 1);
+    V sm2[5], sm1[5];
+    const V r_m2 = ld(-1, c0 - 2), r_m1 = ld(-1, c0 - 1);
     w0[0] = ld(-1, c0);
     w1[0] = ld(-1, c0 + 1);
-    const T ir_m2 = qdiv(T(1), rho0 * (rho0 + r_m2)), ir_m1 = qdiv(T(1), rho0 * (rho0 + r_m1));
-    const T ir_0 = qdiv(T(1), rho0 * (rho0 + w0[0])), ir_p1 = qdiv(T(1), rho0 * (rho0 + w1[0]));
+    const V ir_m2 = qdiv(V(1), rho0 * (rho0 + r_m2)), ir_m1 = qdiv(V(1), rho0 * (rho0 + r_m1));
+    const V ir_0 = qdiv(V(1), rho0 * (rho0 + w0[0])), ir_p1 = qdiv(V(1), rho0 * (rho0 + w1[0]));
     sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = w0[0]; s1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (u >= nq) break;
+      if (u >= nq_n) break;
       w0[u + 1] = ld(u, c0);
       w1[u + 1] = ld(u, c0 + 1);
-      sm2[u + 1] = (rho0 * ld(u, c0 - 2) - q0[u] * r_m2) * ir_m2;
-      sm1[u + 1] = (rho0 * ld(u, c0 - 1) - q0[u] * r_m1) * ir_m1;
-      s0[u + 1] = (rho0 * w0[u + 1] - q0[u] * w0[0]) * ir_0;
-      s1[u + 1] = (rho0 * w1[u + 1] - q0[u] * w1[0]) * ir_p1;
+      sm2[u + 1] = spec(u, ld(u, c0 - 2), r_m2, ir_m2);
+      sm1[u + 1] = spec(u, ld(u, c0 - 1), r_m1, ir_m1);
+      s0[u + 1] = spec(u, w0[u + 1], w0[0], ir_0);
+      s1[u + 1] = spec(u, w1[u + 1], w1[0], ir_p1);
     }
-    const T da = gld(A.v, base + c0 * st);
-    const T a = vb + da, nu = a * cour;
-    T dM = T(0), M = T(0);
+    const V da = gldv<V>(A.v, base + c0 * st);
+    const V a = wind ? vb + da : da, nu = a * cour;
+    V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      if (u > nq) break;
-      const T dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
+      if (u > nq_n) break;
+      const V dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
       d0[u] = vleer(s1[u] - s0[u], s0[u] - sm1[u]);
-      const T fv = upwind(sm1[u], dm1, s0[u], d0[u], a, nu);
+      const V fv = upwind(sm1[u], dm1, s0[u], d0[u], a, nu);
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
-        M = M0 + dM;
+        M = wind ? M0 + dM : dM;
         F0[0] = GRP ? dM : fix(c0, 0, dM);  // the density belongs to the first wave
       } else {
-        F0[u] = fix(c0, mq[u - 1], sb[u - 1] * dM + fv * M);
+        F0[u] = fix(c0, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
       }
     }
     w2[0] = ld(-1, c0 + 2);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) w2[u + 1] = ld(u, c0 + 2);
-    va = gld(A.v, base + (c0 + 1) * st);
+      if (u < nq_n) w2[u + 1] = ld(u, c0 + 2);
+    va = gldv<V>(A.v, base + (c0 + 1) * st);
   }
   for (int c = c0; c < c1; ++c) {
     const idx_t ic = cidx(c);
     // next iteration's loads: cell c+3 and face c+2
-    T nn[5];
+    V nn[5];
     nn[0] = ld(-1, c + 3);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) nn[u + 1] = ld(u, c + 3);
-    const T vn = gld(A.v, base + min(c + 2, c1) * st);
-    const T ir2 = qdiv(T(1), rho0 * (rho0 + w2[0]));
-    T s2[5];
+      if (u < nq_n) nn[u + 1] = ld(u, c + 3);
+    const V vn = gldv<V>(A.v, base + min(c + 2, c1) * st);
+    const V ir2 = qdiv(V(1), rho0 * (rho0 + w2[0]));
+    V s2[5];
     s2[0] = w2[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq) s2[u + 1] = (rho0 * w2[u + 1] - q0[u] * w2[0]) * ir2;
-    const T da = va;
-    const T a = vb + da, nu = a * cour;
-    T dM = T(0), M = T(0);
+      if (u < nq_n) s2[u + 1] = spec(u, w2[u + 1], w2[0], ir2);
+    const V da = va;
+    const V a = wind ? vb + da : da, nu = a * cour;
+    V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      if (u > nq) break;
-      const T d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
-      const T fv = upwind(s0[u], d0[u], s1[u], d1, a, nu);
-      T F1;
+      if (u > nq_n) break;
+      const V d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
+      const V fv = upwind(s0[u], d0[u], s1[u], d1, a, nu);
+      V F1;
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
-        M = M0 + dM;
+        M = wind ? M0 + dM : dM;
         F1 = GRP ? dM : fix(c + 1, 0, dM);
       } else {
-        F1 = fix(c + 1, mq[u - 1], sb[u - 1] * dM + fv * M);
+        F1 = fix(c + 1, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
       }
       T *qo = (u == 0) ? A.qo[0] : qout[u - 1];
-      if (u > 0 || GRP == 0) gst(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
+      if (u > 0 || GRP == 0) gstv<V>(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
       F0[u] = F1;
       d0[u] = d1;
       s0[u] = s1[u];
@@ -1047,7 +1091,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   }
 }
 
-template <typename T, int DIR, int BC>
+template <typename T, int DIR, int BC, bool FRONT, int W>
 __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   constexpr int TD = (DIR == 1) ? 2 : 1;
   constexpr int T1 = (DIR == 0) ? 1 : 0;
@@ -1057,23 +1101,23 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   // from the first lane makes the quantity group, and so every field pointer,
   // a scalar
   const int grp = __builtin_amdgcn_readfirstlane(ty) & 1;
-  const int nbx = (A.hi[0] - A.lo[0] + 63) / 64;
+  const int nbx = (A.hi[0] - A.lo[0] + 64 * W - 1) / (64 * W);
   const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
   const unsigned h = blockIdx.x;
   const int bx = (int)(h % (unsigned)nbx);
   const unsigned r1 = h / (unsigned)nbx;
   const int tb = (int)(r1 % (unsigned)ntb);
   const int ch = (int)(r1 / (unsigned)ntb);
-  const int i = A.lo[0] + bx * 64 + lane;
+  const int i = A.lo[0] + (bx * 64 + lane) * W;  // the lane's first column (W divides the extent)
   const int t = A.lo[TD] + tb * 2 + (ty >> 1);
   if (i >= A.hi[0] || t >= A.hi[TD]) return;
   const int c0 = A.lo[DIR] + ch * A.chunk;
   const int c1 = min(c0 + A.chunk, A.hi[DIR]);
   if (c0 >= c1) return;
   if (grp)
-    march_column<T, DIR, BC, 1>(G, P, A, i, t, c0, c1);
+    march_column<T, DIR, BC, 1, FRONT, W>(G, P, A, i, t, c0, c1);
   else
-    march_column<T, DIR, BC, 0>(G, P, A, i, t, c0, c1);
+    march_column<T, DIR, BC, 0, FRONT, W>(G, P, A, i, t, c0, c1);
 }
 
 // ------------------------------------------------------------ CommUp
@@ -1903,6 +1947,13 @@ void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
   else diffuse_heat_t<double>(st, G, P, B, cur, dtp, fac, do_diff, do_heat);
 }
 
+template <typename T, int BC, bool FRONT, int W>
+static void march_launch(hipStream_t st, int dir, const Geo &G, const Phys &P, const MarchArgs<T> &M, dim3 gr,
+                         dim3 bl) {
+  if (dir == 1) DFK_LAUNCH((k_march<T, 1, BC, FRONT, W>), gr, bl, st, G, P, M);
+  else DFK_LAUNCH((k_march<T, 2, BC, FRONT, W>), gr, bl, st, G, P, M);
+}
+
 template <typename T>
 static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src,
                              const double *dtp, double fac, const Geo *Gf, const void *fine_acc, int chunk) {
@@ -1961,19 +2012,25 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   M.acc = A.acc;
   M.facc = A.facc;
   const int td = (dir == 1) ? 2 : 1;
-  const long nbx = (M.hi[0] - M.lo[0] + 63) / 64;
   const long ntb = (M.hi[td] - M.lo[td] + 1) / 2;
   const long nch = (ext + M.chunk - 1) / M.chunk;
+  const bool front = M.acc || M.facc;
+  // FP32 level 0 without frontier transfers: two adjacent columns per lane
+  // (its rows start 128-byte aligned and the x extent is even); FP64 keeps one
+  // (the two-column form holds twice the registers and was not faster)
+  const int w = (sizeof(T) == 4 && G.bc && !front && (M.hi[0] - M.lo[0]) % 2 == 0 && M.lo[0] % 2 == 0) ? 2 : 1;
+  const long nbx = (M.hi[0] - M.lo[0] + 64 * w - 1) / (64 * w);
   const dim3 gr((unsigned)(nbx * ntb * nch)), bl(64, 4);
-  if (G.bc == 2) {
-    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 2>), gr, bl, st, G, P, M);
-    else DFK_LAUNCH((k_march<T, 2, 2>), gr, bl, st, G, P, M);
-  } else if (G.bc) {
-    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 1>), gr, bl, st, G, P, M);
-    else DFK_LAUNCH((k_march<T, 2, 1>), gr, bl, st, G, P, M);
+  if (!G.bc) {
+    march_launch<T, 0, true, 1>(st, dir, G, P, M, gr, bl);  // finer levels always carry frontier transfers
+  } else if (G.bc == 2) {
+    if (front) march_launch<T, 2, true, 1>(st, dir, G, P, M, gr, bl);
+    else if (w == 2) march_launch<T, 2, false, 2>(st, dir, G, P, M, gr, bl);
+    else march_launch<T, 2, false, 1>(st, dir, G, P, M, gr, bl);
   } else {
-    if (dir == 1) DFK_LAUNCH((k_march<T, 1, 0>), gr, bl, st, G, P, M);
-    else DFK_LAUNCH((k_march<T, 2, 0>), gr, bl, st, G, P, M);
+    if (front) march_launch<T, 1, true, 1>(st, dir, G, P, M, gr, bl);
+    else if (w == 2) march_launch<T, 1, false, 2>(st, dir, G, P, M, gr, bl);
+    else march_launch<T, 1, false, 1>(st, dir, G, P, M, gr, bl);
   }
 }
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
