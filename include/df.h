@@ -161,6 +161,17 @@ int df_set_subcycling(df_run *run, int32_t mode);
  * (the default) switches it off; DF_EINVAL for negative or non-finite c2. */
 int df_set_viscosity(df_run *run, double c2);
 
+/* Launch shape of the transport step (the x, y, z passes of T in eq. 15,
+ * Sect. 3.2.3 and 3.3): on (1, default) the x and y passes of level 0 run
+ * as one launch when level 0 has no finer level, uses the default boundaries
+ * and has at most 128 cells along x (an even count above 64): each row's x
+ * pass is taken in registers and fed to the y pass, so the x pass's results
+ * never reach device memory.  off (0): every pass is a launch of its own.  The
+ * results agree to rounding either way (the same operations in the same order;
+ * the compiler may pair a product and a sum into one fused multiply-add
+ * differently); DF_EINVAL for other values. */
+int df_set_transport_fusion(df_run *run, int32_t on);
+
 /* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
  * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
  * every other boundary is zero-gradient outflow.  mode 1: the paper's list,

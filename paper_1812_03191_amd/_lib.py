@@ -72,6 +72,7 @@ def _load():
         "df_stream_copy": [vp, vp, ctypes.c_size_t, vp],
         "df_set_subcycling": [vp, i32],
         "df_set_boundaries": [vp, i32],
+        "df_set_transport_fusion": [vp, i32],
         "df_set_viscosity": [vp, ctypes.c_double],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
     }
@@ -266,6 +267,10 @@ class Run:
     def set_boundaries(self, mode: int) -> None:
         """0: inflow at x_max, outflow elsewhere; 1: the boundary list of Sect. 3.4"""
         _ck(_load().df_set_boundaries(self._h, int(mode)))
+
+    def set_transport_fusion(self, on: bool) -> None:
+        """fuse level 0's x and y transport passes where they qualify (default on)"""
+        _ck(_load().df_set_transport_fusion(self._h, int(bool(on))))
 
     def schedule(self) -> list:
         """sub-steps of level l+1 per step of level l in the last coarse step"""

@@ -67,6 +67,7 @@ struct df_run {
   bool bound = false;
   bool ready = false;
   bool sig_valid = false;  // the signal-speed partials are those of the current state
+  bool fuse_xy = true;     // fuse the x and y passes where transport_xy applies
   int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
   double visc = 0.0;       // artificial-viscosity coefficient (kept across df_set_perturber)
   int xi[MAXLEV];          // sub-steps of level l+1 per step of level l (last coarse step)
@@ -182,13 +183,24 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   // keeps its role, so the launches of two consecutive steps repeat exactly
   LevBufs Bx = B;
   Bx.q[c][1] = B.etmp;
-  { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
-  { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
-  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, c, dtp, scale, Gf, facc, R->chunk); }
+  bool fused = false;
+  if (R->fuse_xy) {
+    // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
+    TScope t(R, K_PASSX);
+    fused = dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
+  }
+  if (!fused) {
+    { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
+  }
+  // the z pass and the rebuild take the set the y pass wrote (q[c] after
+  // separate passes, q[1-c] after the fused ones)
+  const int cy = fused ? 1 - c : c;
+  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, cy, dtp, scale, Gf, facc, R->chunk); }
   // a single-level step ends here: the same launch forms the force and the
   // next step's signal-speed partials
-  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - c, dtp, 0.5 * scale, true, R->nl == 1 ? R->scal : nullptr); }
-  R->cur[l] = 1 - c;
+  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, R->nl == 1 ? R->scal : nullptr); }
+  R->cur[l] = 1 - cy;
 }
 
 void cycle(df_run *R, int l) {
@@ -523,6 +535,14 @@ int df_set_viscosity(df_run *R, double c2) {
   if (!std::isfinite(c2) || c2 < 0.0) return fail(DF_EINVAL, "viscosity coefficient must be finite and >= 0");
   R->visc = c2;
   R->phys.visc = c2;
+  return DF_OK;
+}
+
+int df_set_transport_fusion(df_run *R, int32_t on) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (on != 0 && on != 1) return fail(DF_EINVAL, "transport fusion must be 0 or 1");
+  R->fuse_xy = on == 1;
   return DF_OK;
 }
 

@@ -95,6 +95,11 @@ void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
 // chunk: cells per column segment of the streaming y and z passes
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src,
                     const double *dtp, double fac, const Geo *Gf, const void *fine_acc, int chunk);
+// fused x and y passes q[src] -> q[1-src] of level 0 without a finer level
+// (bc 1, at most 128 cells along x, an even count above 64); false, launching
+// nothing, when the level does not qualify
+bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
+                  double fac, int chunk);
 void zero(hipStream_t st, void *p, size_t bytes);
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf,
             LevBufs &Bf, int curf);

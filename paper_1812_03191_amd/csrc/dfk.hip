@@ -121,6 +121,19 @@ __device__ __forceinline__ void gstv(T *p, idx_t i, V v) {
   *reinterpret_cast<V *>(reinterpret_cast<char *>(p) + (unsigned)i * (unsigned)sizeof(T)) = v;
 }
 
+// W per-cell values of a lane as its lanes_of vector
+template <typename V, typename T, int W>
+__device__ __forceinline__ V to_lanes(const T (&a)[W]) {
+  if constexpr (W == 1) {
+    return a[0];
+  } else {
+    V v;
+    v.x = a[0];
+    v.y = a[1];
+    return v;
+  }
+}
+
 // cell-centre coordinate: the perturber is the central vertex of the level
 template <typename T>
 __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
@@ -758,38 +771,40 @@ __device__ __forceinline__ void row_store(T *p, idx_t c, const T (&v)[R]) {
   *reinterpret_cast<vec *>(reinterpret_cast<char *>(p) + (unsigned)c * (unsigned)sizeof(T)) = w;
 }
 
+// x pass of one level-0 row held by one wave, R cells per lane (lane l owns
+// cells R l .. R l + R - 1; lanes past the row end hold zero departures, the
+// inflow state beyond x_max): from the row's density and left-face velocity
+// departures (dr, da, set by the caller) the mass transfers through every left
+// face, then per quantity its transfers and updated departures.
 template <typename T, int R>
-__global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) {
-  int lane, j, k;
-  if (!thread_cell(xrow_box(A.b), lane, j, k)) return;
-  const int n = G.n[0];
-  const int x0 = R * lane;
-  const bool live = x0 < n;  // the lane's cells are active (R divides n)
-  const T dt = (T)(A.fac * A.dtp[0]);
-  const T dx = (T)G.dx;
-  const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx);
-  const T rho0 = (T)P.rho0;
-  const T vb = (T)vback(P, 0);
-  const T M0 = rho0 * vb * mfac;
-  const idx_t c = lin(G, x0, j, k);
-  T dr[R], irr[R], da[R], a[R], nu[R], dM[R], M[R];
+struct XRow {
+  T dr[R], da[R];
+  T dt, dx, rho0, ivol, irr[R], a[R], nu[R], dM[R], M[R];
+
+  __device__ __forceinline__ void begin(const Geo &G, const Phys &P, T dt_) {
+    dt = dt_;
+    dx = (T)G.dx;
+    const T mfac = dt * dx * dx;
+    ivol = T(1) / (dx * dx * dx);
+    rho0 = (T)P.rho0;
+    const T vb = (T)vback(P, 0);
+    const T M0 = rho0 * vb * mfac;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    dr[r] = T(0);
-    da[r] = T(0);
-  }
-  if (live) {
-    row_load<T, R>(A.qi[0], c, dr);
-    row_load<T, R>(A.v[0], c, da);  // left faces x0 .. x0+R-1 (all <= n - 1)
-  }
+    for (int r = 0; r < R; ++r) {
+      irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
+      a[r] = vb + da[r];
+      nu[r] = qdiv(a[r] * dt, dx);
+    }
+    T fv[R];
+    left_faces(dr, fv);
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
-    a[r] = vb + da[r];
-    nu[r] = qdiv(a[r] * dt, dx);
+    for (int r = 0; r < R; ++r) {
+      dM[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
+      M[r] = M0 + dM[r];
+    }
   }
   // left-face value of the upwind van Leer reconstruction of s, per cell
-  auto left_faces = [&](const T (&sv)[R], T (&fv)[R]) {
+  __device__ __forceinline__ void left_faces(const T (&sv)[R], T (&fv)[R]) const {
     T sl[R], sr[R], d[R], dl[R];
     row_left<T, R>(sv, sl, sv[0]);
     row_right<T, R>(sv, sr, T(0));
@@ -799,16 +814,90 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
 #pragma unroll
     for (int r = 0; r < R; ++r)
       fv[r] = (a[r] > T(0)) ? sl[r] + T(0.5) * dl[r] * (T(1) - nu[r]) : sv[r] - T(0.5) * d[r] * (T(1) + nu[r]);
-  };
-  {
-    T fv[R];
-    left_faces(dr, fv);
+  }
+  // specific value and own departure of quantity m >= 1 from its input: the
+  // energy departure (m = 1) or the face velocity whose momentum it is
+  __device__ __forceinline__ void quantity(const Phys &P, int m, const T (&in)[R], T (&sv)[R],
+                                           T (&own)[R]) const {
+    if (m >= 2) {
+      // momentum P = rho v of a face velocity: its specific value is v itself
+      const T vbd = (T)vback(P, (m - 2) >> 1);
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      dM[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
-      M[r] = M0 + dM[r];
+      for (int r = 0; r < R; ++r) {
+        sv[r] = in[r];
+        own[r] = rho0 * sv[r] + dr[r] * (vbd + sv[r]);
+      }
+    } else {
+      const T q0 = (T)qback(P, m);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sv[r] = (rho0 * in[r] - q0 * dr[r]) * irr[r];
+        own[r] = in[r];
+      }
     }
   }
+  // transfers of quantity m through the left faces
+  __device__ __forceinline__ void transfers(const Phys &P, int m, const T (&sv)[R], T (&F)[R]) const {
+    T fv[R];
+    left_faces(sv, fv);
+    const T s0 = (T)sback(P, m);
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] = s0 * dM[r] + fv[r] * M[r];
+  }
+  // updated departures from the left-face transfers (none through x_max)
+  __device__ __forceinline__ void update(const T (&own)[R], const T (&FL)[R], T (&out)[R]) const {
+    T FR[R];
+    row_right<T, R>(FL, FR, T(0));
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = own[r] - (FR[r] - FL[r]) * ivol;
+  }
+};
+
+// input of quantity m >= 1 of the row of level 0 at index c (first cell of the
+// lane): the energy departure, or the face velocity whose momentum it is (the
+// right x face from the next lane's left face, zero past x_max)
+template <typename T, int R>
+__device__ __forceinline__ void xrow_input(const Geo &G, const PassArgs<T> &A, int m, idx_t c, bool live,
+                                           const T (&da)[R], T (&in)[R]) {
+  if (m == 3) {
+    row_right<T, R>(da, in, T(0));
+    return;
+  }
+  if (m == 2) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) in[r] = da[r];
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) in[r] = T(0);
+  if (!live) return;
+  if (m == 1) {
+    row_load<T, R>(A.qi[1], c, in);
+  } else {
+    const int d = (m - 2) >> 1;
+    row_load<T, R>(A.v[d], c + ((m & 1) ? dstride(G, d) : 0), in);
+  }
+}
+
+template <typename T, int R>
+__global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) {
+  int lane, j, k;
+  if (!thread_cell(xrow_box(A.b), lane, j, k)) return;
+  const int n = G.n[0];
+  const int x0 = R * lane;
+  const bool live = x0 < n;  // the lane's cells are active (R divides n)
+  const idx_t c = lin(G, x0, j, k);
+  XRow<T, R> X;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    X.dr[r] = T(0);
+    X.da[r] = T(0);
+  }
+  if (live) {
+    row_load<T, R>(A.qi[0], c, X.dr);
+    row_load<T, R>(A.v[0], c, X.da);  // left faces x0 .. x0+R-1 (all <= n - 1)
+  }
+  X.begin(G, P, (T)(A.fac * A.dtp[0]));
   // flux matching on the frontier of the finer level
   const bool ov = A.facc && j - G.n[1] / 4 >= 0 && k - G.n[2] / 4 >= 0 && j - G.n[1] / 4 < G.n[1] / 2 &&
                   k - G.n[2] / 4 < G.n[2] / 2;
@@ -826,53 +915,23 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
         }
       }
     }
-    T FR[R], out[R];
-    row_right<T, R>(FL, FR, T(0));
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = own[r] - (FR[r] - FL[r]) * ivol;
+    T out[R];
+    X.update(own, FL, out);
     if (live) row_store<T, R>(A.qo[m], c, out);
   };
   {
     T F[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] = dM[r];
-    finish(0, dr, F);
+    for (int r = 0; r < R; ++r) F[r] = X.dM[r];
+    finish(0, X.dr, F);
   }
 
 #pragma unroll 1
   for (int m = 1; m < NQ; ++m) {
-    T sv[R], own[R];
-    if (m >= 2) {
-      // momentum P = rho v of a face velocity: its specific value is v itself
-      const int d = (m - 2) >> 1;
-      if (d == 0 && (m & 1)) {
-        // right faces x0+1 .. x0+R: the next cell's left face (zero at x_max)
-        row_right<T, R>(da, sv, T(0));
-      } else {
-#pragma unroll
-        for (int r = 0; r < R; ++r) sv[r] = T(0);
-        if (live) row_load<T, R>(A.v[d], c + ((m & 1) ? dstride(G, d) : 0), sv);
-      }
-      const T vbd = (T)vback(P, d);
-#pragma unroll
-      for (int r = 0; r < R; ++r) own[r] = rho0 * sv[r] + dr[r] * (vbd + sv[r]);
-    } else {
-      T dq[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) dq[r] = T(0);
-      if (live) row_load<T, R>(A.qi[m], c, dq);
-      const T q0 = (T)qback(P, m);
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        sv[r] = (rho0 * dq[r] - q0 * dr[r]) * irr[r];
-        own[r] = dq[r];
-      }
-    }
-    T fv[R], F[R];
-    left_faces(sv, fv);
-    const T s0 = (T)sback(P, m);
-#pragma unroll
-    for (int r = 0; r < R; ++r) F[r] = s0 * dM[r] + fv[r] * M[r];
+    T in[R], sv[R], own[R], F[R];
+    xrow_input<T, R>(G, A, m, c, live, X.da, in);
+    X.quantity(P, m, in, sv, own);
+    X.transfers(P, m, sv, F);
     finish(m, own, F);
   }
 }
@@ -899,13 +958,58 @@ struct MarchArgs {
   int fn[3];
 };
 
-// One column segment [c0, c1) of the quantity group GRP (0: rho, e, P-x, P+x;
-// 1: P-y, P+y, P-z, P+z) at in-plane position (i, t).
+// Transported quantities of group GRP of NG (u = 0.. of the group; entries
+// past the group's count are unused): two groups {e, P-x, P+x} and {P-y, P+y,
+// P-z, P+z}, or four groups {e}, {P-x, P+x}, {P-y, P+y}, {P-z, P+z}.  Every
+// group also transports the density (its mass transfers carry the others);
+// the first one stores it.
+constexpr int group_q(int NG, int GRP, int u) {
+  return NG == 2 ? (GRP ? 4 + u : (u < 3 ? 1 + u : 1)) : (GRP == 0 ? 1 : (u < 2 ? 2 * GRP + u : 1));
+}
+constexpr int group_n(int NG, int GRP) { return NG == 2 ? (GRP ? 4 : 3) : (GRP ? 2 : 1); }
+
+// Rows of a column read from the transported set (the y and z passes): the
+// raw departures of row c (w[0] the density, w[1..] the group's quantities)
+// through level 0's boundary rules.  bc 1 clamps c to the active range; bc 2:
+// across a wall (DIR is y or z) every quantity takes its mirror image, and the
+// two momenta normal to the wall swap and change sign.
+template <typename T, typename V, int DIR, int BC, int GRP, int NG>
+struct ColSrc {
+  const T *rho;
+  const T *qin[4];
+  idx_t base, st;
+  int n;
+  __device__ __forceinline__ V ld(int u, int c) const {  // u < 0: the density
+    constexpr bool walls = BC == 2;
+    // group wg holds P-, P+ normal to DIR at u = pa, pa + 1
+    constexpr int wg = NG == 2 ? 1 : (DIR == 1 ? 2 : 3);
+    constexpr int pa = NG == 2 ? ((DIR == 1) ? 0 : 2) : 0;
+    const T *q = u < 0 ? rho : qin[u];
+    if (walls && (c < 0 || c >= n)) {
+      const idx_t m = base + mirror_idx(c, n) * st;
+      if (GRP == wg && (u == pa || u == pa + 1)) return -gldv<V>(qin[u ^ 1], m);
+      return gldv<V>(q, m);
+    }
+    if (BC) c = clampi(c, 0, n - 1);
+    return gldv<V>(q, base + c * st);
+  }
+  __device__ __forceinline__ void get(int c, V (&w)[5]) {
+    w[0] = ld(-1, c);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (u < group_n(NG, GRP)) w[u + 1] = ld(u, c);
+  }
+};
+
+// One column segment [c0, c1) of the quantity group GRP of NG at in-plane
+// position (i, t), W adjacent columns per lane.  The rows come from src, in
+// increasing order c0-2, c0-1, ..., each requested one iteration ahead of its
+// use; lanes that are not live (past the row end) neither read nor write.
 // FRONT: the level has frontier transfers (a finer level's sums to take, or
 // its own to accumulate); without them the solver's transfers stand.
-template <typename T, int DIR, int BC, int GRP, bool FRONT, int W>
+template <typename T, int DIR, int BC, int GRP, bool FRONT, int W, int NG, typename Src>
 __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
-                                             int i, int t, int c0, int c1) {
+                                             int i, int t, int c0, int c1, Src &src, bool live) {
   static_assert(W == 1 || !FRONT, "frontier transfers are per column");
   using V = typename lanes_of<T, W>::type;  // the W adjacent columns of a lane
   constexpr int TD = (DIR == 1) ? 2 : 1;
@@ -927,20 +1031,18 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     if (BC) c = clampi(c, 0, G.n[DIR] - 1);
     return base + c * st;
   };
-  constexpr int mq[4] = {GRP ? 4 : 1, GRP ? 5 : 2, GRP ? 6 : 3, GRP ? 7 : 1};
-  constexpr int nq_n = GRP ? 4 : 3;
+  constexpr int mq[4] = {group_q(NG, GRP, 0), group_q(NG, GRP, 1), group_q(NG, GRP, 2), group_q(NG, GRP, 3)};
+  constexpr int nq = group_n(NG, GRP);
   // the momenta across the wind (P-y .. P+z) have a zero background, and
   // only x carries a background velocity: those terms are dropped outright
   constexpr bool zq[4] = {mq[0] >= 4, mq[1] >= 4, mq[2] >= 4, mq[3] >= 4};
   constexpr bool wind = DIR == 0;
   T q0[4], sb[4];
-  const T *qin[4];
   T *qout[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     q0[u] = (T)qback(P, mq[u]);
     sb[u] = (T)sback(P, mq[u]);
-    qin[u] = A.qi[mq[u]];
     qout[u] = A.qo[mq[u]];
   }
 
@@ -980,90 +1082,71 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   };
   // departure of the specific value of quantity u from raw departures (q, rho)
   auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
+  // velocity departure on face c (normal to DIR)
+  auto face = [&](int c) -> V { return live ? gldv<V>(A.v, base + c * st) : V(0); };
 
   // window: departures of the specific values at c, c+1 (s0, s1; index 0 is
   // the density departure), limited difference at c (d0), transfer through
   // face c (F0); raw departures of cells c, c+1, c+2 (w0, w1, w2) and the
-  // velocity departure on face c+1 (va), all loaded at least one iteration
+  // velocity departure on face c+1 (va), all fetched at least one iteration
   // ahead of their use
-  // bc 2: across a wall (DIR is y or z) every quantity takes its mirror
-  // image, and the two momenta normal to the wall swap and change sign
-  constexpr bool walls = BC == 2;
-  constexpr int pa = (DIR == 1) ? 0 : 2;  // P-, P+ normal to DIR in group 1
-  auto ld = [&](int u, int c) -> V {      // u < 0: the density
-    const T *q = u < 0 ? A.qi[0] : qin[u];
-    if (walls && (c < 0 || c >= G.n[DIR])) {
-      const idx_t m = base + mirror_idx(c, G.n[DIR]) * st;
-      if (GRP == 1 && (u == pa || u == pa + 1)) return -gldv<V>(qin[u ^ 1], m);
-      return gldv<V>(q, m);
-    }
-    return gldv<V>(q, cidx(c));
-  };
-
   V s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
   V va;
   {
-    V sm2[5], sm1[5];
-    const V r_m2 = ld(-1, c0 - 2), r_m1 = ld(-1, c0 - 1);
-    w0[0] = ld(-1, c0);
-    w1[0] = ld(-1, c0 + 1);
-    const V ir_m2 = qdiv(V(1), rho0 * (rho0 + r_m2)), ir_m1 = qdiv(V(1), rho0 * (rho0 + r_m1));
+    V rm2[5], rm1[5], sm2[5], sm1[5];
+    src.get(c0 - 2, rm2);
+    src.get(c0 - 1, rm1);
+    src.get(c0, w0);
+    src.get(c0 + 1, w1);
+    const V ir_m2 = qdiv(V(1), rho0 * (rho0 + rm2[0])), ir_m1 = qdiv(V(1), rho0 * (rho0 + rm1[0]));
     const V ir_0 = qdiv(V(1), rho0 * (rho0 + w0[0])), ir_p1 = qdiv(V(1), rho0 * (rho0 + w1[0]));
-    sm2[0] = r_m2; sm1[0] = r_m1; s0[0] = w0[0]; s1[0] = w1[0];
+    sm2[0] = rm2[0]; sm1[0] = rm1[0]; s0[0] = w0[0]; s1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      if (u >= nq_n) break;
-      w0[u + 1] = ld(u, c0);
-      w1[u + 1] = ld(u, c0 + 1);
-      sm2[u + 1] = spec(u, ld(u, c0 - 2), r_m2, ir_m2);
-      sm1[u + 1] = spec(u, ld(u, c0 - 1), r_m1, ir_m1);
+      if (u >= nq) break;
+      sm2[u + 1] = spec(u, rm2[u + 1], rm2[0], ir_m2);
+      sm1[u + 1] = spec(u, rm1[u + 1], rm1[0], ir_m1);
       s0[u + 1] = spec(u, w0[u + 1], w0[0], ir_0);
       s1[u + 1] = spec(u, w1[u + 1], w1[0], ir_p1);
     }
-    const V da = gldv<V>(A.v, base + c0 * st);
+    const V da = face(c0);
     const V a = wind ? vb + da : da, nu = a * cour;
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      if (u > nq_n) break;
+      if (u > nq) break;
       const V dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
       d0[u] = vleer(s1[u] - s0[u], s0[u] - sm1[u]);
       const V fv = upwind(sm1[u], dm1, s0[u], d0[u], a, nu);
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
         M = wind ? M0 + dM : dM;
-        F0[0] = GRP ? dM : fix(c0, 0, dM);  // the density belongs to the first wave
+        F0[0] = GRP ? dM : fix(c0, 0, dM);  // the density belongs to the first group
       } else {
         F0[u] = fix(c0, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
       }
     }
-    w2[0] = ld(-1, c0 + 2);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < nq_n) w2[u + 1] = ld(u, c0 + 2);
-    va = gldv<V>(A.v, base + (c0 + 1) * st);
+    src.get(c0 + 2, w2);
+    va = face(c0 + 1);
   }
   for (int c = c0; c < c1; ++c) {
     const idx_t ic = cidx(c);
-    // next iteration's loads: cell c+3 and face c+2
+    // next iteration's rows: cell c+3 (the last one needed is c1+1) and face c+2
     V nn[5];
-    nn[0] = ld(-1, c + 3);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < nq_n) nn[u + 1] = ld(u, c + 3);
-    const V vn = gldv<V>(A.v, base + min(c + 2, c1) * st);
+    if (c + 3 <= c1 + 1) src.get(c + 3, nn);
+    const V vn = face(min(c + 2, c1));
     const V ir2 = qdiv(V(1), rho0 * (rho0 + w2[0]));
     V s2[5];
     s2[0] = w2[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (u < nq_n) s2[u + 1] = spec(u, w2[u + 1], w2[0], ir2);
+      if (u < nq) s2[u + 1] = spec(u, w2[u + 1], w2[0], ir2);
     const V da = va;
     const V a = wind ? vb + da : da, nu = a * cour;
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
-      if (u > nq_n) break;
+      if (u > nq) break;
       const V d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
       const V fv = upwind(s0[u], d0[u], s1[u], d1, a, nu);
       V F1;
@@ -1075,7 +1158,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
         F1 = fix(c + 1, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
       }
       T *qo = (u == 0) ? A.qo[0] : qout[u - 1];
-      if (u > 0 || GRP == 0) gstv<V>(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
+      if ((u > 0 || GRP == 0) && live) gstv<V>(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
       F0[u] = F1;
       d0[u] = d1;
       s0[u] = s1[u];
@@ -1094,8 +1177,6 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
 template <typename T, int DIR, int BC, bool FRONT, int W>
 __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   constexpr int TD = (DIR == 1) ? 2 : 1;
-  constexpr int T1 = (DIR == 0) ? 1 : 0;
-  constexpr int T2 = (DIR == 2) ? 1 : 2;
   const int lane = threadIdx.x, ty = threadIdx.y;
   // threadIdx.y is the same across a wave (blockDim.x is one wave): reading it
   // from the first lane makes the quantity group, and so every field pointer,
@@ -1114,10 +1195,122 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   const int c0 = A.lo[DIR] + ch * A.chunk;
   const int c1 = min(c0 + A.chunk, A.hi[DIR]);
   if (c0 >= c1) return;
-  if (grp)
-    march_column<T, DIR, BC, 1, FRONT, W>(G, P, A, i, t, c0, c1);
-  else
-    march_column<T, DIR, BC, 0, FRONT, W>(G, P, A, i, t, c0, c1);
+  using V = typename lanes_of<T, W>::type;
+  int id3[3];
+  id3[0] = i;
+  id3[TD] = t;
+  id3[DIR] = 0;
+  const idx_t base = lin(G, id3[0], id3[1], id3[2]);
+  if (grp) {
+    ColSrc<T, V, DIR, BC, 1, 2> src{A.qi[0], {A.qi[4], A.qi[5], A.qi[6], A.qi[7]}, base, dstride(G, DIR), G.n[DIR]};
+    march_column<T, DIR, BC, 1, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, true);
+  } else {
+    ColSrc<T, V, DIR, BC, 0, 2> src{A.qi[0], {A.qi[1], A.qi[2], A.qi[3], A.qi[1]}, base, dstride(G, DIR), G.n[DIR]};
+    march_column<T, DIR, BC, 0, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, true);
+  }
+}
+
+// Rows of a column that are the x pass of whole level-0 rows (the fused x and
+// y passes): for row r (clamped to the active range, as the y pass reads its
+// ghosts under bc 1) the x-updated departures of the density and the group's
+// quantities, computed from the row's inputs exactly as k_xrow does; the
+// inputs of the next row are loaded while the y pass uses this one.
+template <typename T, int W, int GRP, int NG>
+struct XSrc {
+  using V = typename lanes_of<T, W>::type;
+  const Geo *G;
+  const Phys *P;
+  const PassArgs<T> *A;
+  T dt;
+  int t, x0;
+  bool live;
+  T dr[W], da[W], in[4][W];  // inputs of the next row
+
+  __device__ __forceinline__ void load(int r) {
+    const int j = clampi(r, 0, G->n[1] - 1);
+    const idx_t c = lin(*G, x0, j, t);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      dr[q] = T(0);
+      da[q] = T(0);
+    }
+    if (live) {
+      row_load<T, W>(A->qi[0], c, dr);
+      row_load<T, W>(A->v[0], c, da);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < group_n(NG, GRP)) {
+        const int m = group_q(NG, GRP, u);
+        if (m != 2 && m != 3) xrow_input<T, W>(*G, *A, m, c, live, da, in[u]);
+      }
+    }
+  }
+  __device__ __forceinline__ void get(int r, V (&w)[5]) {
+    XRow<T, W> X;
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      X.dr[q] = dr[q];
+      X.da[q] = da[q];
+    }
+    X.begin(*G, *P, dt);
+    T out[W];
+    X.update(X.dr, X.dM, out);
+    w[0] = to_lanes<V, T, W>(out);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < group_n(NG, GRP)) {
+        const int m = group_q(NG, GRP, u);
+        T inq[W], sv[W], own[W], F[W];
+        if (m == 2 || m == 3) xrow_input<T, W>(*G, *A, m, 0, live, X.da, inq);
+        else
+#pragma unroll
+          for (int q = 0; q < W; ++q) inq[q] = in[u][q];
+        X.quantity(*P, m, inq, sv, own);
+        X.transfers(*P, m, sv, F);
+        X.update(own, F, out);
+        w[u + 1] = to_lanes<V, T, W>(out);
+      }
+    }
+    load(r + 1);
+  }
+};
+
+template <typename T, int W, int GRP, int NG>
+__device__ __forceinline__ void xy_group(const Geo &G, const Phys &P, const PassArgs<T> &A, const MarchArgs<T> &M,
+                                         T dt, int t, int x0, bool live, int c0, int c1) {
+  XSrc<T, W, GRP, NG> src{&G, &P, &A, dt, t, x0, live};
+  src.load(c0 - 2);
+  march_column<T, 1, 1, GRP, false, W, NG>(G, P, M, x0, t, c0, c1, src, live);
+}
+
+// Fused x and y passes of level 0 without a finer level (bc 1, rows of at most
+// 64 W cells): one wave per (plane t, quantity group, y segment) holds whole
+// rows, W cells per lane, takes the x pass of each row it needs in registers
+// and walks the y pass on it; only the y pass's results reach HBM.  Results
+// are those of the separate passes up to the pairing of products and sums
+// into fused multiply-adds.
+template <typename T, int W, int NG>
+__global__ void __launch_bounds__(256) k_xymarch(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
+  constexpr int RB = 4 / NG;  // planes per block
+  const int lane = threadIdx.x, ty = threadIdx.y;
+  const int grp = __builtin_amdgcn_readfirstlane(ty) % NG;
+  const int ntb = (G.n[2] + RB - 1) / RB;
+  const int tb = (int)(blockIdx.x % (unsigned)ntb), ch = (int)(blockIdx.x / (unsigned)ntb);
+  const int t = tb * RB + ty / NG;
+  if (t >= G.n[2]) return;
+  const int c0 = ch * M.chunk;
+  const int c1 = min(c0 + M.chunk, G.n[1]);
+  if (c0 >= c1) return;
+  const int x0 = W * lane;
+  const bool live = x0 < G.n[0];
+  const T dt = (T)(A.fac * A.dtp[0]);
+  if (grp == 0) xy_group<T, W, 0, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
+  else if (grp == 1) xy_group<T, W, 1, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
+  if constexpr (NG == 4) {
+    if (grp == 2) xy_group<T, W, 2, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
+    else if (grp == 3) xy_group<T, W, 3, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
+  }
 }
 
 // ------------------------------------------------------------ CommUp
@@ -2033,6 +2226,54 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
     else march_launch<T, 1, false, 1>(st, dir, G, P, M, gr, bl);
   }
 }
+template <typename T>
+static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
+                           double fac, int chunk) {
+  const int n = G.n[0];
+  if (G.bc != 1 || G.has_fine || n > 2 * BX || (n > BX && n % 2 != 0)) return false;
+  PassArgs<T> A;
+  A.b = active_box(G);
+  for (int m = 0; m < NQ; ++m) {
+    A.qi[m] = tp<T>(B.q[src][m]);
+    A.qo[m] = tp<T>(B.q[1 - src][m]);
+  }
+  for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
+  A.dtp = dtp;
+  A.fac = fac;
+  A.acc = nullptr;
+  A.facc = nullptr;
+  for (int d = 0; d < 3; ++d) A.fn[d] = 0;
+  MarchArgs<T> M;
+  for (int d = 0; d < 3; ++d) {
+    M.lo[d] = A.b.lo[d];
+    M.hi[d] = A.b.hi[d];
+    M.fn[d] = 0;
+  }
+  M.chunk = G.n[1] <= chunk ? G.n[1] : chunk;
+  for (int m = 0; m < NQ; ++m) {
+    M.qi[m] = A.qo[m];
+    M.qo[m] = A.qo[m];
+  }
+  M.v = A.v[1];
+  M.dtp = dtp;
+  M.fac = fac;
+  M.acc = nullptr;
+  M.facc = nullptr;
+  // FP64 splits the quantities over four waves (the two-group form holds too
+  // many registers next to the x pass), FP32 over two
+  constexpr int NG = sizeof(T) == 8 ? 4 : 2;
+  const long ntb = (G.n[2] + 4 / NG - 1) / (4 / NG), nch = (G.n[1] + M.chunk - 1) / M.chunk;
+  const dim3 gr((unsigned)(ntb * nch)), bl(64, 4);
+  if (n <= BX) DFK_LAUNCH((k_xymarch<T, 1, NG>), gr, bl, st, G, P, A, M);
+  else DFK_LAUNCH((k_xymarch<T, 2, NG>), gr, bl, st, G, P, A, M);
+  return true;
+}
+bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp, double fac,
+                  int chunk) {
+  if (P.fp32) return transport_xy_t<float>(st, G, P, B, src, dtp, fac, chunk);
+  return transport_xy_t<double>(st, G, P, B, src, dtp, fac, chunk);
+}
+
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
                     double fac, const Geo *Gf, const void *fine_acc, int chunk) {
   if (P.fp32) transport_pass_t<float>(st, dir, G, P, B, src, dtp, fac, Gf, fine_acc, chunk);

@@ -124,6 +124,36 @@ def test_x_pass_launch_forms(dfm, stage, dt, n):
     assert max(errs.values()) < 1e-13, {k: v for k, v in errs.items() if v > 1e-14}
 
 
+# Fused x and y passes against separate ones: one wave per row (32, 64 cells),
+# two cells per lane with every lane live (128) or some lanes past the row end
+# (96), y extents of one segment and of several with a ragged last one (40).
+FUSED_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 6), (128, 40, 6)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", FUSED_SHAPES)
+def test_fused_xy_equals_separate_passes(dfm, n, prec):
+    _say(f"[fused xy] n={n} {prec}")
+    nx, ny, nz = n
+    p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
+    runs = []
+    for fuse in (False, True):
+        g = dfm.Run(nx, ny, nz, dx0=0.05, seed=31, noise_amp=1e-3, precision=p)
+        g.set_perturber(0.01, 0.05, 2e-3, 1.3, 0.1)
+        g.set_transport_fusion(fuse)
+        g.step(6)
+        runs.append(g)
+    # the same operations in the same order; only the pairing of a product
+    # and a sum into one fused multiply-add may differ between the kernels
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    for name in FIELD_NAMES:
+        a, b = runs[0].field(0, name), runs[1].field(0, name)
+        assert np.max(np.abs(a - b)) <= tol * SCALE[name], (name, float(np.max(np.abs(a - b))))
+    fa, fb = runs[0].force(), runs[1].force()
+    assert np.max(np.abs(fa[:3] - fb[:3])) <= 1e2 * tol * np.linalg.norm(fa[:3]), (fa, fb)
+    assert fa[3] == fb[3]
+
+
 # ------------------------------------------------------- full single level
 
 def test_config1_parity_100_steps(dfm):
