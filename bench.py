@@ -39,6 +39,7 @@ ALG_BYTES = {
     "pass_x": 8 * (5 + 8),        # read rho, e, vx, vy, vz; write the 8 transported
     "pass_y": 8 * (9 + 8),        # read 8 transported + vy; write 8
     "pass_z": 8 * (9 + 8),        # read 8 transported + vz; write 8
+    "pass_xy": 8 * (5 + 8),       # fused x and y: read rho, e, vx, vy, vz; write the 8 transported
     "rebuild_kick": 8 * (8 + 3),  # read 8 transported; write vx, vy, vz
     # single level: the one-block kernel that sums the partials (the rebuild
     # kick forms them from the fields it already reads)
@@ -269,7 +270,9 @@ PMC_KINDS = ((("k_kick0<", ", false, true, false>"), "kick"), (("k_kick<", ", fa
              (("k_kick0<", ", true, true, "), "rebuild_kick"), (("k_kick<", ", true, true>"), "rebuild_kick"),
              (("k_compress<",), "compress"), (("k_diffuse_heat<",), "diffuse_heat"),
              (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
-             (("k_march<", ", 1, "), "pass_y"), (("k_march<", ", 2, "), "pass_z"),
+             (("k_march<double, 1,",), "pass_y"), (("k_march<float, 1,",), "pass_y"),
+             (("k_march<double, 2,",), "pass_z"), (("k_march<float, 2,",), "pass_z"),
+             (("k_xymarch<",), "pass_xy"),
              (("k_step_final",), "force"), (("k_post<",), "post"))
 
 
@@ -405,9 +408,13 @@ def main():
         if roof["traffic"]:
             # measured DRAM bytes of the same kernel over its duration
             roof["traffic_frac"] = round(roof["traffic"] / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        # every kind's algorithmic bandwidth and its fraction of the HBM peak
         kern = {k: {"ms_total": round(v[0], 3), "launches": v[1],
-                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None} for k, v in kern.items()
-                if v[1]}
+                    "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
+                    "alg_GBs": round(ALG_BYTES[k] * cells * esz // 8 / (v[0] / v[1] / 1e3) / 1e9, 1)
+                    if ALG_BYTES.get(k) else None,
+                    "hbm_frac": round(ALG_BYTES[k] * cells * esz // 8 / (v[0] / v[1] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                    if ALG_BYTES.get(k) else None} for k, v in kern.items() if v[1]}
 
     extra = {}
     legs = set() if args.no_batched else set(x.strip() for x in args.legs.split(",") if x.strip())

@@ -205,10 +205,11 @@ int df_debug_stage(df_run *run, int32_t stage, double dt);
  * pass after each step that forms both the force partials and the next step's
  * signal speeds, with the one-block kernel that logs the force and sets the
  * next time step; DF_K_DT is the time step before the first step of a df_step
- * call (with a signal pass if the state was changed by other calls). */
+ * call (with a signal pass if the state was changed by other calls);
+ * DF_K_PASSXY the fused x and y transport passes (df_set_transport_fusion). */
 enum {
   DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
-  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_NKINDS
+  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_PASSXY, DF_K_NKINDS
 };
 int df_timing_enable(df_run *run, int32_t max_launches);
 int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);

@@ -179,7 +179,7 @@ def force_log(h, cap: int = 4096) -> np.ndarray:
 
 
 KERNEL_KINDS = ("kick", "compress", "diffuse_heat", "pass_x", "pass_y", "pass_z", "rebuild_kick",
-                "commup", "commmean", "dt", "force", "zero", "viscosity")
+                "commup", "commmean", "dt", "force", "zero", "viscosity", "pass_xy")
 
 
 def timing_enable(h, max_launches: int) -> None:

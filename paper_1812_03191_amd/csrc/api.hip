@@ -147,7 +147,7 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
 // ---------------------------------------------------------------- timing
 // Kernel kinds timed by df_timing_read (the order of the DF_K_* list in df.h).
 enum { K_KICK = 0, K_COMPRESS, K_DIFFUSE, K_PASSX, K_PASSY, K_PASSZ, K_REBUILD, K_COMMUP, K_COMMMEAN,
-       K_DT, K_FORCE, K_ZERO, K_VISC, K_NKINDS };
+       K_DT, K_FORCE, K_ZERO, K_VISC, K_PASSXY, K_NKINDS };
 
 struct TScope {
   df_run *R;
@@ -183,13 +183,12 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   // keeps its role, so the launches of two consecutive steps repeat exactly
   LevBufs Bx = B;
   Bx.q[c][1] = B.etmp;
-  bool fused = false;
-  if (R->fuse_xy) {
-    // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
-    TScope t(R, K_PASSX);
-    fused = dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
-  }
-  if (!fused) {
+  // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
+  const bool fused = R->fuse_xy && dfk::transport_xy_fits(G);
+  if (fused) {
+    TScope t(R, K_PASSXY);
+    dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
+  } else {
     { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
     { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
   }

@@ -100,6 +100,7 @@ void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBuf
 // nothing, when the level does not qualify
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
                   double fac, int chunk);
+bool transport_xy_fits(const Geo &G);
 void zero(hipStream_t st, void *p, size_t bytes);
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf,
             LevBufs &Bf, int curf);

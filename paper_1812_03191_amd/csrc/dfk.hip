@@ -141,13 +141,14 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
 }
 
 // Quotient and square root in the storage type, from the hardware reciprocal
-// and square root instead of the correctly rounded expansions: in FP64 the
-// reciprocal takes two Newton steps and the quotient one residual correction
-// (within an ulp of the rounded quotient), the square root is IEEE-rounded; in
-// FP32 both are the single hardware instructions (about 1 ulp each).  Every
-// use has a normal nonzero divisor (densities and energies near their
-// background, distances of at least the Plummer length, sums of two slopes of
-// one sign; a van Leer quotient of slopes of opposite signs is selected away).
+// and reciprocal square root instead of the correctly rounded expansions: in
+// FP64 the reciprocal takes two Newton steps and the quotient one residual
+// correction, the square root two Goldschmidt steps and one residual
+// correction (each within an ulp of the rounded result); in FP32 both are the
+// single hardware instructions (about 1 ulp each).  Every use has a normal
+// positive operand or divisor (densities and energies near their background,
+// squared distances of at least a quarter cell, sums of two slopes of one
+// sign; a van Leer quotient of slopes of opposite signs is selected away).
 __device__ __forceinline__ double qdiv(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(r, fma(-b, r, 1.0), r);
@@ -160,7 +161,19 @@ template <typename V>
 __device__ __forceinline__ V qdiv(V a, V b) {
   return V{qdiv(a.x, b.x), qdiv(a.y, b.y)};  // two-element vectors, per element
 }
-__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ double qsqrt(double x) {
+  // hardware reciprocal square root, two of Goldschmidt's steps towards
+  // g = sqrt(x), h = 1/(2 sqrt(x)), one residual correction
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  return fma(fma(-g, g, x), h, g);
+}
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // van Leer's harmonic limited difference; evaluated without a branch (the
@@ -1131,9 +1144,10 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   }
   for (int c = c0; c < c1; ++c) {
     const idx_t ic = cidx(c);
-    // next iteration's rows: cell c+3 (the last one needed is c1+1) and face c+2
+    // next iteration's rows: cell c+3 and face c+2 (one row past the last
+    // needed one, c1+1, is fetched and not used: no branch splits the body)
     V nn[5];
-    if (c + 3 <= c1 + 1) src.get(c + 3, nn);
+    src.get(c + 3, nn);
     const V vn = face(min(c + 2, c1));
     const V ir2 = qdiv(V(1), rho0 * (rho0 + w2[0]));
     V s2[5];
@@ -1291,7 +1305,7 @@ __device__ __forceinline__ void xy_group(const Geo &G, const Phys &P, const Pass
 // are those of the separate passes up to the pairing of products and sums
 // into fused multiply-adds.
 template <typename T, int W, int NG>
-__global__ void __launch_bounds__(256) k_xymarch(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_xymarch(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
   constexpr int RB = 4 / NG;  // planes per block
   const int lane = threadIdx.x, ty = threadIdx.y;
   const int grp = __builtin_amdgcn_readfirstlane(ty) % NG;
@@ -2226,11 +2240,16 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
     else march_launch<T, 1, false, 1>(st, dir, G, P, M, gr, bl);
   }
 }
+bool transport_xy_fits(const Geo &G) {
+  const int n = G.n[0];
+  return G.bc == 1 && !G.has_fine && n <= 2 * BX && (n <= BX || n % 2 == 0);
+}
+
 template <typename T>
 static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
                            double fac, int chunk) {
   const int n = G.n[0];
-  if (G.bc != 1 || G.has_fine || n > 2 * BX || (n > BX && n % 2 != 0)) return false;
+  if (!transport_xy_fits(G)) return false;
   PassArgs<T> A;
   A.b = active_box(G);
   for (int m = 0; m < NQ; ++m) {
