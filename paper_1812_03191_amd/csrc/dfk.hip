@@ -475,6 +475,27 @@ __global__ void __launch_bounds__(BX * BY) k_compress(Geo G, Phys P, CellArgs<T>
   A.e[c] = qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a);
 }
 
+// The same on level 0 with two adjacent cells per lane (even row length; the
+// box's x range counts pairs): every field moves as one 8- or 16-byte access.
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_compress2(Geo G, Phys P, CellArgs<T> A) {
+  using V = typename lanes_of<T, 2>::type;
+  int p, j, k;
+  if (!thread_cell(A.b, p, j, k)) return;
+  const T dt = (T)(A.fac * A.dtp[0]);
+  const idx_t c = lin(G, 2 * p, j, k);
+  const V vx0 = gldv<V>(A.v[0], c);
+  V vx1;
+  vx1.x = vx0.y;
+  vx1.y = gld(A.v[0], c + 2);
+  const V divv = qdiv((vx1 - vx0) + (gldv<V>(A.v[1], c + (idx_t)G.sy) - gldv<V>(A.v[1], c)) +
+                          (gldv<V>(A.v[2], c + (idx_t)G.sz) - gldv<V>(A.v[2], c)),
+                      V((T)G.dx));
+  const V a = T(0.5) * (T)P.gm1 * dt * divv;
+  const V de = gldv<V>(A.e, c);
+  gstv<V>(A.e, c, qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a));
+}
+
 // ---------------------------------------------------- diffusion + heat
 
 template <typename T>
@@ -540,6 +561,62 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
     }
   }
   A.eo[c] = en;
+}
+
+// The same on level 0 with two adjacent cells per lane (even row length; the
+// box's x range counts pairs): the pair's own fields and its y and z
+// neighbours move as 8- or 16-byte accesses, the x neighbours of the pair are
+// the other cell of the pair and one cell on each side.
+template <typename T, int BC>
+__global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffArgs<T> A) {
+  using V = typename lanes_of<T, 2>::type;
+  int p, j, k;
+  if (!thread_cell(A.b, p, j, k)) return;
+  const int i = 2 * p;
+  const T dt = (T)(A.fac * A.dtp[0]);
+  const T rho0 = (T)P.rho0, e0 = (T)P.e0;
+  const idx_t c = lin(G, i, j, k);
+  const V de = gldv<V>(A.e, c);
+  V en = de;
+  if (A.do_diff) {
+    auto tv = [&](V r, V e) -> V { return qdiv(rho0 * e - e0 * r, rho0 * (rho0 + r)); };
+    const V Tc = tv(gldv<V>(A.rho, c), de);
+    // x: past x_max (and past x_min under bc 2) the background, else the
+    // nearest active cell (as k_diffuse_heat)
+    V Tl, Tr;
+    Tl.y = Tc.x;
+    Tr.x = Tc.y;
+    if (BC == 2 && i == 0) {
+      Tl.x = T(0);
+    } else {
+      const idx_t cm = i > 0 ? c - 1 : c;
+      Tl.x = dtemp(gld(A.rho, cm), gld(A.e, cm), rho0, e0);
+    }
+    Tr.y = i + 1 == G.n[0] - 1 ? T(0) : dtemp(gld(A.rho, c + 2), gld(A.e, c + 2), rho0, e0);
+    V lap = V(0);
+    lap += (Tr - Tc) - (Tc - Tl);
+#pragma unroll
+    for (int d = 1; d < 3; ++d) {
+      const int id = d == 1 ? j : k;
+      const idx_t s = dstride(G, d);
+      const idx_t cm = id > 0 ? c - s : c, cp = id < G.n[d] - 1 ? c + s : c;
+      const V Tm = tv(gldv<V>(A.rho, cm), gldv<V>(A.e, cm)), Tp = tv(gldv<V>(A.rho, cp), gldv<V>(A.e, cp));
+      lap += (Tp - Tc) - (Tc - Tm);
+    }
+    en = de + qdiv(dt * (T)(P.chi * P.rho0) * lap, V((T)(G.dx * G.dx)));
+  }
+  if (A.do_heat && A.hw_n[0] > 0) {
+    const int b = j - A.hw_lo[1], d = k - A.hw_lo[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int a = i + q - A.hw_lo[0];
+      if (a >= 0 && b >= 0 && d >= 0 && a < A.hw_n[0] && b < A.hw_n[1] && d < A.hw_n[2]) {
+        const double w = A.hw[((long)d * A.hw_n[1] + b) * A.hw_n[0] + a];
+        if (w != 0.0) en[q] += (T)(P.L * (A.fac * A.dtp[0]) * w / (G.dx * G.dx * G.dx));
+      }
+    }
+  }
+  gstv<V>(A.eo, c, en);
 }
 
 // -------------------------------------------------------------- transport
@@ -2066,6 +2143,11 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.dtp = dtp;
   A.fac = fac;
+  if (G.bc && G.n[0] % 2 == 0) {
+    A.b.hi[0] = G.n[0] / 2;  // cell pairs
+    DFK_LAUNCH(k_compress2<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+    return;
+  }
   DFK_LAUNCH(k_compress<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
 }
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac) {
@@ -2144,7 +2226,11 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.fac = fac;
   A.do_diff = do_diff && P.chi > 0.0;
   A.do_heat = do_heat && P.L != 0.0;
-  if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  if (G.bc && G.n[0] % 2 == 0) {
+    A.b.hi[0] = G.n[0] / 2;  // cell pairs
+    if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+    else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  } else if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
   else if (G.bc) DFK_LAUNCH((k_diffuse_heat<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
   else DFK_LAUNCH((k_diffuse_heat<T, 0>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
 }
