@@ -175,6 +175,13 @@ __device__ __forceinline__ double qsqrt(double x) {
   return fma(fma(-g, g, x), h, g);
 }
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <typename V>
+__device__ __forceinline__ V qsqrtv(V x) {
+  V r;
+  r.x = qsqrt(x.x);  // two-element vectors, per element
+  r.y = qsqrt(x.y);
+  return r;
+}
 
 // van Leer's harmonic limited difference; evaluated without a branch (the
 // quotient of the discarded side is selected away)
@@ -1515,8 +1522,9 @@ template <typename T>
 struct RedArgs {
   Box b;
   const T *rho, *e, *v[3];
-  double *part;              // per-block partials (3 per block)
+  double *part;              // per-block partials: three planes of npart values
   double *spart;             // per-block maximum signal speeds
+  int npart;                 // partial slots per plane (the blocks of the one-cell-per-thread grid)
   Scal *S;
   int cov_lo[3], cov_hi[3];  // covered cells (empty if no finer level)
 };
@@ -1528,7 +1536,7 @@ __device__ __forceinline__ bool is_covered(const RedArgs<T> &A, int i, int j, in
 }
 
 // block sum of three values into part[q * blocks + block]; fixed order for a fixed grid
-__device__ void block_sum3(double a, double b, double c, double *part) {
+__device__ void block_sum3(double a, double b, double c, double *part, int npart) {
   __shared__ double sh[3][BX * BY / 64];
   a = wave_sum(a);
   b = wave_sum(b);
@@ -1550,7 +1558,7 @@ __device__ void block_sum3(double a, double b, double c, double *part) {
       s2 += sh[2][q];
     }
     // three planes of one value per block (coalesced for the final sum)
-    const long nb = gridDim.x;
+    const long nb = npart;
     part[blk] = s0;
     part[nb + blk] = s1;
     part[2 * nb + blk] = s2;
@@ -1574,7 +1582,7 @@ __global__ void __launch_bounds__(BX * BY) k_force(Geo G, Phys P, RedArgs<T> A) 
     fy = w * y;
     fz = w * z;
   }
-  block_sum3(fx, fy, fz, A.part);
+  block_sum3(fx, fy, fz, A.part, A.npart);
 }
 
 // mass, internal energy and kinetic energy (face velocities averaged to
@@ -1598,7 +1606,7 @@ __global__ void __launch_bounds__(BX * BY) k_totals(Geo G, Phys P, RedArgs<T> A)
     ei = (P.e0 + (double)A.e[c]) * vol;
     ek = 0.5 * r * v2 * vol;
   }
-  block_sum3(m, ei, ek, A.part);
+  block_sum3(m, ei, ek, A.part, A.npart);
 }
 
 // fixed-order sum of the partials of all levels (one block)
@@ -1748,7 +1756,7 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
       fz = w * z;
     }
   }
-  block_sum3(fx, fy, fz, A.part);
+  block_sum3(fx, fy, fz, A.part, A.npart);
   block_signal(sig, bad, A.spart, A.S);
 }
 
@@ -1868,8 +1876,176 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
     }
   }
   if (POST) {
-    block_sum3(fx, fy, fz, R.part);
+    block_sum3(fx, fy, fz, R.part, R.npart);
     block_signal((double)sig, bad, R.spart, R.S);
+  }
+}
+
+// k_kick0 with two adjacent cells per lane (level 0, even row length; the
+// box's x range counts pairs): the pair's own fields and its y and z
+// neighbours move as 8- or 16-byte accesses, the two low x faces of the pair
+// take the cell before the pair and the pair itself.  Arithmetic per face is
+// that of k_kick0.  With POST a block covers the cells of up to two blocks of
+// k_kick0's grid: it writes its partials to slot blockIdx.x and zeros to
+// slot gridDim.x + blockIdx.x (when that is below npart), so the final sums
+// read every slot of the one-cell-per-thread layout.
+template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
+__global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
+  using V = typename lanes_of<T, 2>::type;
+  int p, j, k;
+  const bool ok = thread_cell(A.b, p, j, k);
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  T sig = T(0);
+  int bad = 0;
+  if (ok) {
+    const int i = 2 * p;
+    const T h = (T)(A.fac * A.dtp[0]);
+    const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
+    const T *rho = A.q[0], *e = A.q[1];
+    const int id[3] = {i, j, k};
+    const idx_t c = lin(G, i, j, k);
+    const V drc = gldv<V>(rho, c), dec = gldv<V>(e, c);
+    V xcx;
+    xcx.x = xcen<T>(G, 0, i);
+    xcx.y = xcen<T>(G, 0, i + 1);
+    const T yc = xcen<T>(G, 1, j), zc = xcen<T>(G, 2, k);
+    const V r2c = xcx * xcx + yc * yc + zc * zc + eps2;
+    const V dcen = qsqrtv(r2c);
+    const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
+    auto sound1 = [&](T dr, T de) -> T {
+      const T r = rho0 + dr, en = e0 + de;
+      if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
+      return qsqrt(qdiv(gg * en, r));
+    };
+    auto sound = [&](V dr, V de) -> V {
+      V s;
+      s.x = sound1(dr.x, de.x);
+      s.y = sound1(dr.y, de.y);
+      return s;
+    };
+    auto vmax = [&](V a) { sig = fmax(sig, fmax(a.x, a.y)); };
+    auto vabs = [&](V a) -> V {
+      V r;
+      r.x = fabs(a.x);
+      r.y = fabs(a.y);
+      return r;
+    };
+    V cs_own = V(0);
+    if (POST) cs_own = sound(drc, dec);
+    // the kick of a face pair: cells below (drm, dem) and above (dcr, der) the
+    // faces, the position of the cell above (xr, r2r, dr_)
+    auto kickv = [&](int d, V vf, V drm, V dem, V dcr, V der, V xr, V r2r, V dr_) -> V {
+      if (KICK) {
+        const V rface = rho0 + T(0.5) * (drm + dcr);
+        const V gradp = qdiv(gm1 * (der - dem), dx * rface);
+        const V xm = xr - dx;
+        const V dm = qsqrtv(r2r - xr * xr + xm * xm);
+        const V gradphi = qdiv(GM * (xr + xm), dm * dr_ * (dm + dr_));
+        vf = vf - h * (gradp + gradphi);
+      }
+      return vf;
+    };
+    auto rebuild = [&](int d, V ppm, V pmc, V drm, V dcr) -> V {
+      const T vb = (T)vback(P, d);
+      return qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
+    };
+    // x: faces i and i+1; below them cell i-1 (the own cell i again at x = 0,
+    // the background under bc 2) and cell i
+    {
+      V drm, dem, ppm;
+      drm.y = drc.x;
+      dem.y = dec.x;
+      const T *pm = A.q[2], *pp = A.q[3];
+      if (i > 0) {
+        drm.x = gld(rho, c - 1);
+        dem.x = gld(e, c - 1);
+      } else if (BCM == 2) {
+        drm.x = T(0);
+        dem.x = T(0);
+      } else {
+        drm.x = drc.x;
+        dem.x = dec.x;
+      }
+      V vf;
+      if (REBUILD) {
+        const V ppc = gldv<V>(pp, c);
+        ppm.y = ppc.x;
+        ppm.x = i > 0 ? gld(pp, c - 1) : (BCM == 2 ? T(0) : ppc.x);
+        vf = rebuild(0, ppm, gldv<V>(pm, c), drm, drc);
+      } else {
+        vf = gldv<V>(A.v[0], c);
+      }
+      vf = kickv(0, vf, drm, dem, drc, dec, xcx, r2c, dcen);
+      gstv<V>(A.v[0], c, vf);
+      if (POST) {
+        const V a = vabs((T)vback(P, 0) + vf);
+        vmax(a + cs_own);
+        if (i > 0) sig = fmax(sig, a.x + sound1(drm.x, dem.x));
+        sig = fmax(sig, a.y + cs_own.x);
+      }
+      if (i + 1 == G.n[0] - 1) {
+        A.v[0][c + 2] = T(0);  // injection face at x_max carries the wind
+        if (POST) sig = fmax(sig, fabs((T)vback(P, 0)) + cs_own.y);
+      }
+    }
+    // y and z: the low faces of both cells, then face n after the last ones
+#pragma unroll
+    for (int d = 1; d < 3; ++d) {
+      const idx_t sd = dstride(G, d);
+      const T xd = d == 1 ? yc : zc;
+      const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
+      if (BCM == 2 && id[d] == 0) {
+        gstv<V>(A.v[d], c, V(0));  // a wall: no normal velocity
+        if (POST) vmax(cs_own);
+      } else {
+        const idx_t cm = id[d] > 0 ? c - sd : c;
+        const V drm = gldv<V>(rho, cm), dem = gldv<V>(e, cm);
+        V vf = REBUILD ? rebuild(d, gldv<V>(pp, cm), gldv<V>(pm, c), drm, drc) : gldv<V>(A.v[d], c);
+        vf = kickv(d, vf, drm, dem, drc, dec, V(xd), r2c, dcen);
+        gstv<V>(A.v[d], c, vf);
+        if (POST) {
+          const V a = vabs((T)vback(P, d) + vf);
+          vmax(a + cs_own);
+          if (id[d] > 0) vmax(a + sound(drm, dem));
+        }
+      }
+      if (id[d] == G.n[d] - 1) {
+        const idx_t cf = c + sd;
+        if (BCM == 2) {
+          gstv<V>(A.v[d], cf, V(0));  // a wall
+          if (POST) vmax(cs_own);
+        } else {
+          // both sides read the last cells (zero-gradient outflow)
+          const T xr = xcen<T>(G, d, id[d] + 1);
+          const V r2r = r2c - xd * xd + xr * xr;
+          const V dr_ = qsqrtv(r2r);
+          V vf = REBUILD ? rebuild(d, gldv<V>(pp, c), gldv<V>(pm, c), drc, drc) : gldv<V>(A.v[d], cf);
+          vf = kickv(d, vf, drc, dec, drc, dec, V(xr), r2r, dr_);
+          gstv<V>(A.v[d], cf, vf);
+          if (POST) vmax(vabs((T)vback(P, d) + vf) + cs_own);
+        }
+      }
+    }
+    if (POST) {
+      // force of the gas in these cells on the perturber, eq. 18: each cell's
+      // term in the storage type, the sum in FP64
+      const V w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
+      fx = (double)(w.x * xcx.x) + (double)(w.y * xcx.y);
+      fy = (double)(w.x * yc) + (double)(w.y * yc);
+      fz = (double)(w.x * zc) + (double)(w.y * zc);
+      if (!isfinite(sig)) bad = 1;
+    }
+  }
+  if (POST) {
+    block_sum3(fx, fy, fz, R.part, R.npart);
+    block_signal((double)sig, bad, R.spart, R.S);
+    const unsigned z = gridDim.x + blockIdx.x;
+    if (threadIdx.x == 0 && threadIdx.y == 0 && z < (unsigned)R.npart) {
+      R.part[z] = 0.0;
+      R.part[R.npart + z] = 0.0;
+      R.part[2 * (size_t)R.npart + z] = 0.0;
+      R.spart[z] = 0.0;
+    }
   }
 }
 
@@ -2096,11 +2272,28 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
   A.fac = fac;
   const dim3 bl(BX, BY);
   if (G.bc) {
-    // level 0: one thread per active cell (boundary faces by the last cells)
+    // level 0: one thread per active cell (boundary faces by the last cells),
+    // or per pair of cells when the rows have an even length
     A.b = active_box(G);
-    const dim3 gr = grid_of(A.b);
     RedArgs<T> R{};
     if (post) R = red_args<T>(G, *post, 0, S);
+    if (G.n[0] % 2 == 0) {
+      A.b.hi[0] = G.n[0] / 2;
+      const dim3 gr = grid_of(A.b);
+      if (G.bc == 2) {
+        if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
+        else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
+        else if (rebuild) DFK_LAUNCH((k_kick0p<T, 2, true, false, false>), gr, bl, st, G, P, A, R);
+        else DFK_LAUNCH((k_kick0p<T, 2, false, true, false>), gr, bl, st, G, P, A, R);
+      } else {
+        if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 1, true, true, true>), gr, bl, st, G, P, A, R);
+        else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 1, true, true, false>), gr, bl, st, G, P, A, R);
+        else if (rebuild) DFK_LAUNCH((k_kick0p<T, 1, true, false, false>), gr, bl, st, G, P, A, R);
+        else DFK_LAUNCH((k_kick0p<T, 1, false, true, false>), gr, bl, st, G, P, A, R);
+      }
+      return;
+    }
+    const dim3 gr = grid_of(A.b);
     if (G.bc == 2) {
       if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
       else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
@@ -2466,7 +2659,8 @@ static RedArgs<T> red_args(const Geo &G, LevBufs &B, int cur, Scal *S) {
   A.e = tp<T>(B.q[cur][1]);
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.part = B.part;
-  A.spart = B.part + 3 * part_count(G);
+  A.npart = (int)part_count(G);
+  A.spart = B.part + 3 * (size_t)A.npart;
   A.S = S;
   for (int d = 0; d < 3; ++d) {
     A.cov_lo[d] = G.has_fine ? G.n[d] / 4 : 0;
