@@ -68,6 +68,7 @@ struct df_run {
   bool ready = false;
   bool sig_valid = false;  // the signal-speed partials are those of the current state
   bool fuse_xy = true;     // fuse the x and y passes where transport_xy applies
+  bool slot_mode = false;  // single level: the kicks take the step length from the signal-speed slots
   int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
   double visc = 0.0;       // artificial-viscosity coefficient (kept across df_set_perturber)
   int xi[MAXLEV];          // sub-steps of level l+1 per step of level l (last coarse step)
@@ -175,9 +176,12 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   int c = R->cur[l];
   const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
   const void *facc = Gf ? R->buf[l + 1].acc : nullptr;
-  { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale); }
+  // single level: the kick sets this step's length from the last end-of-step
+  // pass's signal speeds, and the compression logs that pass's force
+  Scal *slots = R->slot_mode ? R->scal : nullptr;
+  { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale, slots); }
   if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, G, P, B, c, dtp, scale); }
-  { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale); }
+  { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale, slots, R->flog); }
   { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
   // the x pass reads the new energy from the diffusion output; every buffer
   // keeps its role, so the launches of two consecutive steps repeat exactly
@@ -265,6 +269,7 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 // n coarse steps: device time step, recursive cycle, force into the log
 // signal-speed and force partials of the current state (post_partials)
 void post_reduce(df_run *R) {
+  dfk::zero(R->stream, R->scal->smax, sizeof(R->scal->smax));  // the pass refills the signal-speed slots
   for (int l = 0; l < R->nl; ++l) dfk::post_partials(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->scal);
   R->sig_valid = true;
 }
@@ -326,6 +331,26 @@ int criterion_step(df_run *R) {
 // two steps logs the force and sets the next time step.
 void enqueue_steps(df_run *R, int n) {
   if (n <= 0) return;
+  if (R->nl == 1 && R->geo[0].bc && R->geo[0].n[0] % 2 == 0) {
+    // single level: no launch between two steps.  Each first kick takes the
+    // step length from the slots of the end-of-step pass before it (the
+    // rebuild kick, or the signal pass of a changed state), each compression
+    // logs the force of the state the step started from, and one kernel logs
+    // the last step's force.
+    if (!R->sig_valid) {
+      TScope t(R, K_DT);
+      post_reduce(R);
+    }
+    R->slot_mode = true;
+    for (int s = 0; s < n; ++s) cycle(R, 0);
+    R->slot_mode = false;
+    {
+      TScope t(R, K_FORCE);
+      dfk::log_pending(R->stream, R->geo[0], R->buf[0], R->scal, R->flog);
+    }
+    R->sig_valid = true;
+    return;
+  }
   if (!R->sig_valid) {
     TScope t(R, K_DT);
     post_reduce(R);

@@ -9,6 +9,7 @@ namespace dfk {
 constexpr int NQ = 8;       // transported set: rho, e, P-x, P+x, P-y, P+y, P-z, P+z
 constexpr int NSTATE = 5;   // rho, e, vx, vy, vz
 constexpr int MAXLEV = 12;
+constexpr int NSLOT = 512;  // signal-speed slots of a single-level run
 
 // Array geometry of one level.  Every field of a level is one 3-D array,
 // x fastest; entry (i,j,k), i in [-g, s[0]-g), is at off + i + j*sy + k*sz.
@@ -53,6 +54,12 @@ struct Scal {
   int health;                // bit 0: a non-positive or non-finite rho or e seen
   unsigned int nlog;         // force-log entries written so far
   double dtl[MAXLEV];        // per-level step limits cfl min(dx/smax, dx^2/6chi) of the last time step
+  // single-level runs: the largest signal speed of the last end-of-step pass,
+  // as the bits of a non-negative double, in NSLOT slots (block h takes slot
+  // h mod NSLOT, so a slot is only met by blocks of one XCD, h mod 8)
+  unsigned long long smax[NSLOT];
+  double tlog;               // time of the state whose force partials await the log
+  int pending;               // 1: the end-of-step force partials are not logged yet
 };
 
 constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
@@ -72,15 +79,21 @@ struct LevBufs {
 // ---- launchers (all asynchronous on `st`) ---------------------------------
 void init_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, uint64_t seed,
                 double amp);
+// with slots (single-level runs on level 0): the step length from the signal
+// speeds the last end-of-step pass left in slots->smax, written to slots->dt[0]
+// and added to slots->t by the kick itself
 void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
-          double fac);
+          double fac, Scal *slots = nullptr);
 // face velocities from the transported momenta of q[src], then an optional
 // kick; with post (level 0 with a kick) the same launch also forms the force
 // and signal-speed partials of post_partials for the new state
 void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src,
                   const double *dtp, double fac, bool do_kick, Scal *post = nullptr);
+// with log (single-level runs on level 0): the first block also clears
+// log->smax for this step's end-of-step pass and logs a pending force (the
+// partials in B.part, at log->tlog) into flog
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
-              double fac);
+              double fac, Scal *log = nullptr, double *flog = nullptr);
 // artificial viscosity over fac dt: e in place; the face velocities through
 // the three momentum arrays of q[1-cur] as scratch (they are free before the
 // x pass writes them)
@@ -130,5 +143,7 @@ int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int
 size_t part_count(const Geo &G);
 // plain copy of n 16-byte words (measurement reference)
 void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16);
+// logs a pending force of a single-level run (as compress with log does)
+void log_pending(hipStream_t st, const Geo &G, LevBufs &B, Scal *S, double *flog);
 
 }  // namespace dfk

@@ -316,6 +316,7 @@ struct KickArgs {
   T *v[3];
   const double *dtp;
   double fac;
+  Scal *slots;               // non-null: the step length from slots->smax (single-level runs)
 };
 
 // Velocity source S(h) (eq. 15): each face velocity receives
@@ -463,6 +464,10 @@ struct CellArgs {
   const T *v[3];
   const double *dtp;
   double fac;
+  Scal *log;                 // non-null: clear log->smax and log a pending force (first block)
+  const double *part;        // the force partials: three planes of npart values
+  int npart;
+  double *flog;
 };
 
 // Compressional heating (SubStep3): e <- e (1 - a) / (1 + a),
@@ -482,25 +487,35 @@ __global__ void __launch_bounds__(BX * BY) k_compress(Geo G, Phys P, CellArgs<T>
   A.e[c] = qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a);
 }
 
+template <int NT>
+__device__ void log_pending_body(const double *part, int n, Scal *S, double *flog);
+
 // The same on level 0 with two adjacent cells per lane (even row length; the
 // box's x range counts pairs): every field moves as one 8- or 16-byte access.
 template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_compress2(Geo G, Phys P, CellArgs<T> A) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  if (!thread_cell(A.b, p, j, k)) return;
-  const T dt = (T)(A.fac * A.dtp[0]);
-  const idx_t c = lin(G, 2 * p, j, k);
-  const V vx0 = gldv<V>(A.v[0], c);
-  V vx1;
-  vx1.x = vx0.y;
-  vx1.y = gld(A.v[0], c + 2);
-  const V divv = qdiv((vx1 - vx0) + (gldv<V>(A.v[1], c + (idx_t)G.sy) - gldv<V>(A.v[1], c)) +
-                          (gldv<V>(A.v[2], c + (idx_t)G.sz) - gldv<V>(A.v[2], c)),
-                      V((T)G.dx));
-  const V a = T(0.5) * (T)P.gm1 * dt * divv;
-  const V de = gldv<V>(A.e, c);
-  gstv<V>(A.e, c, qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a));
+  if (thread_cell(A.b, p, j, k)) {
+    const T dt = (T)(A.fac * A.dtp[0]);
+    const idx_t c = lin(G, 2 * p, j, k);
+    const V vx0 = gldv<V>(A.v[0], c);
+    V vx1;
+    vx1.x = vx0.y;
+    vx1.y = gld(A.v[0], c + 2);
+    const V divv = qdiv((vx1 - vx0) + (gldv<V>(A.v[1], c + (idx_t)G.sy) - gldv<V>(A.v[1], c)) +
+                            (gldv<V>(A.v[2], c + (idx_t)G.sz) - gldv<V>(A.v[2], c)),
+                        V((T)G.dx));
+    const V a = T(0.5) * (T)P.gm1 * dt * divv;
+    const V de = gldv<V>(A.e, c);
+    gstv<V>(A.e, c, qdiv(de * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a));
+  }
+  if (A.log && blockIdx.x == 0) {
+    // the kick of this step has read the slots: clear them for this step's
+    // end-of-step pass, and log the force of the last step's state
+    for (int q = threadIdx.y * BX + threadIdx.x; q < NSLOT; q += BX * BY) A.log->smax[q] = 0ull;
+    log_pending_body<BX * BY>(A.part, A.npart, A.log, A.flog);
+  }
 }
 
 // ---------------------------------------------------- diffusion + heat
@@ -734,7 +749,7 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   const T irr = qdiv(T(1), rho0 * (rho0 + dr));
   // velocity departure on the left face (faces lo..hi are the ones used)
   const T da = gld(A.v[0], lin(G, clampi(x, A.b.lo[0], A.b.hi[0]), j, k));
-  const T a = vb + da, nu = qdiv(a * dt, dx);
+  const T a = vb + da, nu = a * (dt / dx);
   const T M0 = rho0 * vb * mfac;
   auto left_face = [&](T sv) -> T {
     const T sm = from_left(sv), sp = from_right(sv);
@@ -881,7 +896,7 @@ struct XRow {
   __device__ __forceinline__ void begin(const Geo &G, const Phys &P, T dt_) {
     dt = dt_;
     dx = (T)G.dx;
-    const T mfac = dt * dx * dx;
+    const T mfac = dt * dx * dx, cour = dt / dx;
     ivol = T(1) / (dx * dx * dx);
     rho0 = (T)P.rho0;
     const T vb = (T)vback(P, 0);
@@ -890,7 +905,7 @@ struct XRow {
     for (int r = 0; r < R; ++r) {
       irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
       a[r] = vb + da[r];
-      nu[r] = qdiv(a[r] * dt, dx);
+      nu[r] = a[r] * cour;
     }
     T fv[R];
     left_faces(dr, fv);
@@ -1638,6 +1653,7 @@ __device__ void final3_finish(const FinalArgs &A, const double (*sh)[FW]) {
     for (int q = 0; q < 3; ++q) e[q] = A.out[q];
     e[3] = A.S->t;
     A.S->nlog = n + 1;
+    A.S->pending = 0;
   }
 }
 
@@ -1683,6 +1699,63 @@ __device__ void final3_body(const FinalArgs &A) {
 
 __global__ void __launch_bounds__(FT) k_final3(FinalArgs A) { final3_body(A); }
 
+// A pending end-of-step force (single-level runs): the fixed-order sum of the
+// three planes of partials by the NT threads of one block, into S->force and
+// the log at the time S->tlog of its state; every thread calls it.
+template <int NT>
+__device__ void log_pending_body(const double *part, int n, Scal *S, double *flog) {
+  constexpr int NW = NT / 64;
+  __shared__ double sh[3][NW];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  if (!S->pending) return;  // the same value for every thread of the block
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  int b = tid;
+  for (; b + 7 * NT < n; b += 8 * NT) {
+    double x[8][3];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) x[u][q] = part[(size_t)q * n + b + u * NT];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      s0 += x[u][0];
+      s1 += x[u][1];
+      s2 += x[u][2];
+    }
+  }
+  for (; b < n; b += NT) {
+    s0 += part[b];
+    s1 += part[(size_t)n + b];
+    s2 += part[2 * (size_t)n + b];
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  if (tid % 64 == 0) {
+    sh[0][tid / 64] = s0;
+    sh[1][tid / 64] = s1;
+    sh[2][tid / 64] = s2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const unsigned int k = S->nlog;
+    double *e = flog + 4 * (size_t)(k % FLOG);
+    for (int q = 0; q < 3; ++q) {
+      double t = 0.0;
+      for (int v = 0; v < NW; ++v) t += sh[q][v];
+      S->force[q] = t;
+      e[q] = t;
+    }
+    e[3] = S->tlog;
+    S->nlog = k + 1;
+    S->pending = 0;
+  }
+}
+
+__global__ void __launch_bounds__(FT) k_log_pending(const double *part, int n, Scal *S, double *flog) {
+  log_pending_body<FT>(part, n, S, flog);
+}
+
 // Signal speed c_s + |v| of an active cell, the largest over its six faces,
 // and whether its density and energy are positive and finite.
 template <typename T>
@@ -1719,6 +1792,11 @@ __device__ void block_signal(double sig, int bad, double *spart, Scal *S) {
     double m = sh[0];
     for (int q = 1; q < BX * BY / 64; ++q) m = fmax(m, sh[q]);
     spart[blockIdx.x] = m;
+    // the same maximum into this block's slot (m >= 0, so the order of the
+    // bits is that of the values)
+    if (S)
+      __hip_atomic_fetch_max(&S->smax[blockIdx.x & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -1776,6 +1854,10 @@ __global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A,
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
+  if (POST && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    R.S->tlog = R.S->t;  // the force partials of this state await the log
+    R.S->pending = 1;
+  }
   if (ok) {
     const T h = (T)(A.fac * A.dtp[0]);
     const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
@@ -1897,9 +1979,36 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
+  // the step length: as dt_body (one level), from the slots of the last
+  // end-of-step pass; the first thread records it and advances the time
+  double dtk = 0.0;
+  if (A.slots) {
+    __shared__ double shs[BX * BY / 64];
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    double m = 0.0;
+    for (int q = tid; q < NSLOT; q += BX * BY) m = fmax(m, __longlong_as_double((long long)A.slots->smax[q]));
+    m = wave_max(m);
+    if (tid % 64 == 0) shs[tid / 64] = m;
+    __syncthreads();
+    double smax = shs[0];
+#pragma unroll
+    for (int q = 1; q < BX * BY / 64; ++q) smax = fmax(smax, shs[q]);
+    double dtl = G.dx / smax;
+    if (P.chi > 0.0) dtl = fmin(dtl, G.dx * G.dx / (6.0 * P.chi));
+    dtk = P.cfl * dtl;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+      A.slots->dtl[0] = P.cfl * dtl;
+      A.slots->dt[0] = dtk;
+      A.slots->t += dtk;
+    }
+  }
+  if (POST && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    R.S->tlog = R.S->t;  // the force partials of this state await the log
+    R.S->pending = 1;
+  }
   if (ok) {
     const int i = 2 * p;
-    const T h = (T)(A.fac * A.dtp[0]);
+    const T h = (T)(A.fac * (A.slots ? dtk : A.dtp[0]));
     const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
     const T *rho = A.q[0], *e = A.q[1];
     const int id[3] = {i, j, k};
@@ -2247,8 +2356,10 @@ static RedArgs<T> red_args(const Geo &G, LevBufs &B, int cur, Scal *S);
 
 template <typename T>
 static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, void *const *v, const double *dtp,
-                   double fac, bool rebuild, bool do_kick, LevBufs *post = nullptr, Scal *S = nullptr) {
+                   double fac, bool rebuild, bool do_kick, LevBufs *post = nullptr, Scal *S = nullptr,
+                   Scal *slots = nullptr) {
   KickArgs<T> A;
+  A.slots = nullptr;
   for (int d = 0; d < 3; ++d)
     for (int e = 0; e < 3; ++e) {
       if (G.bc) {
@@ -2279,6 +2390,7 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
     if (post) R = red_args<T>(G, *post, 0, S);
     if (G.n[0] % 2 == 0) {
       A.b.hi[0] = G.n[0] / 2;
+      A.slots = slots;  // only the paired form takes the step length from the slots
       const dim3 gr = grid_of(A.b);
       if (G.bc == 2) {
         if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
@@ -2315,9 +2427,11 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
   }
 }
 
-void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac) {
-  if (P.fp32) kick_t<float>(st, G, P, B.q[cur], B.v, dtp, fac, false, true);
-  else kick_t<double>(st, G, P, B.q[cur], B.v, dtp, fac, false, true);
+void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac,
+          Scal *slots) {
+  if (slots && !(G.bc && G.n[0] % 2 == 0)) slots = nullptr;
+  if (P.fp32) kick_t<float>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
+  else kick_t<double>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
 }
 
 void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
@@ -2329,13 +2443,17 @@ void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int s
 
 template <typename T>
 static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
-                       double fac) {
+                       double fac, Scal *log, double *flog) {
   CellArgs<T> A;
   A.b = G.bc ? active_box(G) : uniform_box(G, 0, 1);
   A.e = tp<T>(B.q[cur][1]);
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.dtp = dtp;
   A.fac = fac;
+  A.log = log;
+  A.part = B.part;
+  A.npart = (int)part_count(G);
+  A.flog = flog;
   if (G.bc && G.n[0] % 2 == 0) {
     A.b.hi[0] = G.n[0] / 2;  // cell pairs
     DFK_LAUNCH(k_compress2<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
@@ -2343,9 +2461,11 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
   }
   DFK_LAUNCH(k_compress<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
 }
-void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac) {
-  if (P.fp32) compress_t<float>(st, G, P, B, cur, dtp, fac);
-  else compress_t<double>(st, G, P, B, cur, dtp, fac);
+void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac,
+              Scal *log, double *flog) {
+  if (log && !(G.bc && G.n[0] % 2 == 0)) log = nullptr;  // only the paired form logs
+  if (P.fp32) compress_t<float>(st, G, P, B, cur, dtp, fac, log, flog);
+  else compress_t<double>(st, G, P, B, cur, dtp, fac, log, flog);
 }
 
 template <typename T>
@@ -2589,6 +2709,10 @@ __global__ void __launch_bounds__(256) k_copy16(uint4 *dst, const uint4 *src, si
 #pragma unroll
   for (int u = 0; u < 4; ++u)
     if (base + 256 * u < n) dst[base + 256 * u] = w[u];
+}
+
+void log_pending(hipStream_t st, const Geo &G, LevBufs &B, Scal *S, double *flog) {
+  hipLaunchKernelGGL(k_log_pending, dim3(1), dim3(FT), 0, st, (const double *)B.part, (int)part_count(G), S, flog);
 }
 
 void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16) {
