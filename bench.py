@@ -266,9 +266,9 @@ def attainable_bandwidth(nbytes=1 << 30, reps=10):
 
 # kernel kind of each kernel name in a counter file (FP64 and FP32 alike):
 # every listed substring must occur in the demangled name
-PMC_KINDS = ((("k_kick0<", ", false, true, false>"), "kick"), (("k_kick<", ", false, true>"), "kick"),
-             (("k_kick0<", ", true, true, "), "rebuild_kick"), (("k_kick<", ", true, true>"), "rebuild_kick"),
-             (("k_compress<",), "compress"), (("k_diffuse_heat<",), "diffuse_heat"),
+PMC_KINDS = ((("k_kick0p<", ", false, true, false>"), "kick"), (("k_kick<", ", false, true>"), "kick"),
+             (("k_kick0p<", ", true, true, "), "rebuild_kick"), (("k_kick<", ", true, true>"), "rebuild_kick"),
+             (("k_compress",), "compress"), (("k_diffuse_heat",), "diffuse_heat"),
              (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
              (("k_march<double, 1,",), "pass_y"), (("k_march<float, 1,",), "pass_y"),
              (("k_march<double, 2,",), "pass_z"), (("k_march<float, 2,",), "pass_z"),

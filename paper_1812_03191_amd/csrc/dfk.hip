@@ -539,8 +539,9 @@ __device__ __forceinline__ T dtemp(T dr, T de, T rho0, T e0) {
 }
 
 // Thermal diffusion (eqs. 19-22, energy flux down the gradient of e/rho with
-// coefficient chi rho0) and heat release L dt w_c / dx^3 (Sect. 3.4).
-template <typename T, int BC>
+// coefficient chi rho0) and heat release L dt w_c / dx^3 (Sect. 3.4), on a
+// finer level (its ghost shell holds every neighbour).
+template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArgs<T> A) {
   int i, j, k;
   if (!thread_cell(A.b, i, j, k)) return;
@@ -554,22 +555,9 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
     T lap = T(0);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      T Tm, Tp;
-      if (BC) {
-        // level 0 (as cread): past x_max, and past x_min under bc 2, the
-        // background (zero departures); elsewhere past the boundary the last
-        // cell again (outflow copies and wall mirrors agree one cell out)
-        const int id = d == 0 ? i : (d == 1 ? j : k);
-        const idx_t s = dstride(G, d);
-        const bool bm = BC == 2 && d == 0 && id == 0, bp = d == 0 && id == G.n[0] - 1;
-        const idx_t cm = id > 0 ? c - s : c, cp = id < G.n[d] - 1 ? c + s : c;
-        Tm = bm ? T(0) : dtemp(A.rho[cm], A.e[cm], rho0, e0);
-        Tp = bp ? T(0) : dtemp(A.rho[cp], A.e[cp], rho0, e0);
-      } else {
-        const idx_t s = dstride(G, d);
-        Tm = dtemp(A.rho[c - s], A.e[c - s], rho0, e0);
-        Tp = dtemp(A.rho[c + s], A.e[c + s], rho0, e0);
-      }
+      const idx_t s = dstride(G, d);
+      const T Tm = dtemp(A.rho[c - s], A.e[c - s], rho0, e0);
+      const T Tp = dtemp(A.rho[c + s], A.e[c + s], rho0, e0);
       lap += (Tp - Tc) - (Tc - Tm);
     }
     en = dec + qdiv(dt * (T)(P.chi * P.rho0) * lap, (T)(G.dx * G.dx));
@@ -585,10 +573,11 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
   A.eo[c] = en;
 }
 
-// The same on level 0 with two adjacent cells per lane (even row length; the
-// box's x range counts pairs): the pair's own fields and its y and z
-// neighbours move as 8- or 16-byte accesses, the x neighbours of the pair are
-// the other cell of the pair and one cell on each side.
+// The same on level 0, whose boundary conditions it applies on read, with two
+// adjacent cells per lane (level-0 rows have an even length; the box's x
+// range counts pairs): the pair's own fields and its y and z neighbours move
+// as 8- or 16-byte accesses, the x neighbours of the pair are the other cell
+// of the pair and one cell on each side.
 template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffArgs<T> A) {
   using V = typename lanes_of<T, 2>::type;
@@ -1838,139 +1827,22 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
   block_signal(sig, bad, A.spart, A.S);
 }
 
-// Level-0 form of the kick: one thread per active cell computes the faces on
-// the low side of its cell and, for the last cell along a dimension, also the
-// boundary face n there (the injection face at x_max carries the wind), so the
-// grid is exactly the active box.  With POST (the last kernel of a
-// single-level step) it also forms the end-of-step reductions of k_post: the
-// force partials of its cell, and the signal speed c_s + |v| of every pair of
-// an active cell and one of its faces, taken at the face's owner (the cell on
-// its high side, or the last cell for face n), which holds both adjacent cells'
-// densities and energies.
-template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
-__global__ void __launch_bounds__(BX * BY) k_kick0(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
-  int i, j, k;
-  const bool ok = thread_cell(A.b, i, j, k);
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  T sig = T(0);
-  int bad = 0;
-  if (POST && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
-    R.S->tlog = R.S->t;  // the force partials of this state await the log
-    R.S->pending = 1;
-  }
-  if (ok) {
-    const T h = (T)(A.fac * A.dtp[0]);
-    const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
-    const T *rho = A.q[0], *e = A.q[1];
-    const int id[3] = {i, j, k};
-    const idx_t c = lin(G, i, j, k);
-    const T drc = rho[c], dec = e[c];
-    const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
-    const T r2c = xc[0] * xc[0] + xc[1] * xc[1] + xc[2] * xc[2] + eps2;
-    const T dcen = qsqrt(r2c);
-    // sound speed of a cell from its density and energy departures, and the
-    // signal speeds, in the storage type (their maximum is exact in any type)
-    const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
-    auto sound = [&](T dr, T de) -> T {
-      const T r = rho0 + dr, en = e0 + de;
-      if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
-      return qsqrt(qdiv(gg * en, r));
-    };
-    T cs_own = T(0);
-    if (POST) cs_own = sound(drc, dec);
-    // face on the low side of cell p (p = own cell, or the virtual cell n past
-    // the last one along d), with the own cell's values when p is the own cell
-    auto face = [&](int d, bool last) {
-      const idx_t sd = dstride(G, d);
-      const idx_t cf = last ? c + sd : c;
-      if (last && d == 0) {
-        A.v[0][cf] = T(0);  // injection face at x_max carries the wind
-        if (POST) sig = fmax(sig, fabs((T)vback(P, 0)) + cs_own);
-        return;
-      }
-      if (d > 0 && BCM == 2 && (last || id[d] == 0)) {
-        A.v[d][cf] = T(0);  // a wall: no normal velocity
-        if (POST) sig = fmax(sig, cs_own);
-        return;
-      }
-      // the cells on the two sides of the face, through the boundary
-      // conditions: for face n (reached here only along y and z under bc 1)
-      // both sides read the last cell (zero-gradient outflow); below face 0
-      // lies the own cell again (outflow) or, along x under bc 2, the
-      // background (zero departures)
-      T xr = xc[d], r2r = r2c, dr_ = dcen;
-      idx_t cm = c;
-      bool bgm = false;
-      if (last) {
-        xr = xcen<T>(G, d, id[d] + 1);
-        r2r = r2c - xc[d] * xc[d] + xr * xr;
-        dr_ = qsqrt(r2r);
-      } else if (id[d] > 0) {
-        cm = c - sd;
-      } else {
-        bgm = BCM == 2 && d == 0;
-      }
-      const T dcr = drc, der = dec;
-      const T drm = bgm ? T(0) : rho[cm], dem = bgm ? T(0) : e[cm];
-      T vf;
-      if (REBUILD) {
-        const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
-        const T ppm = bgm ? T(0) : pp[cm], pmc = pm[c];
-        const T vb = (T)vback(P, d);
-        vf = qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
-      } else {
-        vf = A.v[d][cf];
-      }
-      if (KICK) {
-        const T rface = rho0 + T(0.5) * (drm + dcr);
-        const T gradp = qdiv(gm1 * (der - dem), dx * rface);
-        const T xm = xr - dx;
-        const T dm = qsqrt(r2r - xr * xr + xm * xm);
-        const T gradphi = qdiv(GM * (xr + xm), dm * dr_ * (dm + dr_));
-        vf = vf - h * (gradp + gradphi);
-      }
-      A.v[d][cf] = vf;
-      if (POST) {
-        const T a = fabs((T)vback(P, d) + vf);
-        // the active cells beside the face: the one below (own cell for the
-        // boundary face, cell id-1 otherwise) and the own cell for a low face
-        if (last) {
-          sig = fmax(sig, a + cs_own);
-        } else {
-          sig = fmax(sig, a + cs_own);
-          if (id[d] > 0) sig = fmax(sig, a + sound(drm, dem));
-        }
-      }
-    };
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      face(d, false);
-      if (id[d] == G.n[d] - 1) face(d, true);
-    }
-    if (POST) {
-      // force of the gas in this cell on the perturber, eq. 18: the cell's
-      // term in the storage type, the sum in FP64
-      const T w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
-      fx = (double)(w * xc[0]);
-      fy = (double)(w * xc[1]);
-      fz = (double)(w * xc[2]);
-      if (!isfinite(sig)) bad = 1;
-    }
-  }
-  if (POST) {
-    block_sum3(fx, fy, fz, R.part, R.npart);
-    block_signal((double)sig, bad, R.spart, R.S);
-  }
-}
-
-// k_kick0 with two adjacent cells per lane (level 0, even row length; the
-// box's x range counts pairs): the pair's own fields and its y and z
-// neighbours move as 8- or 16-byte accesses, the two low x faces of the pair
-// take the cell before the pair and the pair itself.  Arithmetic per face is
-// that of k_kick0.  With POST a block covers the cells of up to two blocks of
-// k_kick0's grid: it writes its partials to slot blockIdx.x and zeros to
-// slot gridDim.x + blockIdx.x (when that is below npart), so the final sums
-// read every slot of the one-cell-per-thread layout.
+// Level-0 form of the kick (rows of even length, as every level-0 mesh has):
+// one thread per pair of adjacent active cells (the box's x range counts
+// pairs) computes the faces on the low side of both cells and, for the last
+// cells along a dimension, also the boundary face n there (the injection face
+// at x_max carries the wind), so the grid is exactly the active box.  The
+// pair's own fields and its y and z neighbours move as 8- or 16-byte
+// accesses; the two low x faces take the cell before the pair and the pair
+// itself.  With POST (the last kernel of a single-level step) it also forms
+// the end-of-step reductions of k_post: the force partials of its cells, and
+// the signal speed c_s + |v| of every pair of an active cell and one of its
+// faces, taken at the face's owner (the cell on its high side, or the last
+// cell for face n), which holds both adjacent cells' densities and energies.
+// A block then covers the cells of up to two blocks of the one-cell-per-thread
+// grid whose blocks k_post and the final sums count: it writes its partials to
+// slot blockIdx.x and zeros to slot gridDim.x + blockIdx.x (when that is below
+// npart).
 template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
 __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
   using V = typename lanes_of<T, 2>::type;
@@ -2383,39 +2255,24 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
   A.fac = fac;
   const dim3 bl(BX, BY);
   if (G.bc) {
-    // level 0: one thread per active cell (boundary faces by the last cells),
-    // or per pair of cells when the rows have an even length
+    // level 0: one thread per pair of active cells (boundary faces by the
+    // last cells)
     A.b = active_box(G);
     RedArgs<T> R{};
     if (post) R = red_args<T>(G, *post, 0, S);
-    if (G.n[0] % 2 == 0) {
-      A.b.hi[0] = G.n[0] / 2;
-      A.slots = slots;  // only the paired form takes the step length from the slots
-      const dim3 gr = grid_of(A.b);
-      if (G.bc == 2) {
-        if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
-        else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
-        else if (rebuild) DFK_LAUNCH((k_kick0p<T, 2, true, false, false>), gr, bl, st, G, P, A, R);
-        else DFK_LAUNCH((k_kick0p<T, 2, false, true, false>), gr, bl, st, G, P, A, R);
-      } else {
-        if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 1, true, true, true>), gr, bl, st, G, P, A, R);
-        else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 1, true, true, false>), gr, bl, st, G, P, A, R);
-        else if (rebuild) DFK_LAUNCH((k_kick0p<T, 1, true, false, false>), gr, bl, st, G, P, A, R);
-        else DFK_LAUNCH((k_kick0p<T, 1, false, true, false>), gr, bl, st, G, P, A, R);
-      }
-      return;
-    }
+    A.b.hi[0] = G.n[0] / 2;  // level-0 rows have an even length
+    A.slots = slots;
     const dim3 gr = grid_of(A.b);
     if (G.bc == 2) {
-      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
-      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
-      else if (rebuild) DFK_LAUNCH((k_kick0<T, 2, true, false, false>), gr, bl, st, G, P, A, R);
-      else DFK_LAUNCH((k_kick0<T, 2, false, true, false>), gr, bl, st, G, P, A, R);
+      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
+      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
+      else if (rebuild) DFK_LAUNCH((k_kick0p<T, 2, true, false, false>), gr, bl, st, G, P, A, R);
+      else DFK_LAUNCH((k_kick0p<T, 2, false, true, false>), gr, bl, st, G, P, A, R);
     } else {
-      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0<T, 1, true, true, true>), gr, bl, st, G, P, A, R);
-      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0<T, 1, true, true, false>), gr, bl, st, G, P, A, R);
-      else if (rebuild) DFK_LAUNCH((k_kick0<T, 1, true, false, false>), gr, bl, st, G, P, A, R);
-      else DFK_LAUNCH((k_kick0<T, 1, false, true, false>), gr, bl, st, G, P, A, R);
+      if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 1, true, true, true>), gr, bl, st, G, P, A, R);
+      else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 1, true, true, false>), gr, bl, st, G, P, A, R);
+      else if (rebuild) DFK_LAUNCH((k_kick0p<T, 1, true, false, false>), gr, bl, st, G, P, A, R);
+      else DFK_LAUNCH((k_kick0p<T, 1, false, true, false>), gr, bl, st, G, P, A, R);
     }
     return;
   }
@@ -2429,7 +2286,7 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
 
 void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac,
           Scal *slots) {
-  if (slots && !(G.bc && G.n[0] % 2 == 0)) slots = nullptr;
+  if (!G.bc) slots = nullptr;  // the slots belong to level 0
   if (P.fp32) kick_t<float>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
   else kick_t<double>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
 }
@@ -2454,8 +2311,8 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
   A.part = B.part;
   A.npart = (int)part_count(G);
   A.flog = flog;
-  if (G.bc && G.n[0] % 2 == 0) {
-    A.b.hi[0] = G.n[0] / 2;  // cell pairs
+  if (G.bc) {
+    A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
     DFK_LAUNCH(k_compress2<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
     return;
   }
@@ -2463,7 +2320,7 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
 }
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac,
               Scal *log, double *flog) {
-  if (log && !(G.bc && G.n[0] % 2 == 0)) log = nullptr;  // only the paired form logs
+  if (!G.bc) log = nullptr;  // the slots and the log belong to level 0
   if (P.fp32) compress_t<float>(st, G, P, B, cur, dtp, fac, log, flog);
   else compress_t<double>(st, G, P, B, cur, dtp, fac, log, flog);
 }
@@ -2539,13 +2396,13 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.fac = fac;
   A.do_diff = do_diff && P.chi > 0.0;
   A.do_heat = do_heat && P.L != 0.0;
-  if (G.bc && G.n[0] % 2 == 0) {
-    A.b.hi[0] = G.n[0] / 2;  // cell pairs
+  if (G.bc) {
+    A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
     if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
     else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
-  } else if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
-  else if (G.bc) DFK_LAUNCH((k_diffuse_heat<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
-  else DFK_LAUNCH((k_diffuse_heat<T, 0>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  } else {
+    DFK_LAUNCH(k_diffuse_heat<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  }
 }
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
                   double fac, bool do_diff, bool do_heat) {
