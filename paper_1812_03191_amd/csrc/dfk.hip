@@ -744,7 +744,8 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
     const T sm = from_left(sv), sp = from_right(sv);
     const T d = vleer(sp - sv, sv - sm);
     const T dm = from_left(d);
-    return (a > T(0)) ? sm + T(0.5) * dm * (T(1) - nu) : sv - T(0.5) * d * (T(1) + nu);
+    const T lo = sm + T(0.5) * dm * (T(1) - nu), hi = sv - T(0.5) * d * (T(1) + nu);
+    return a > T(0) ? lo : hi;
   };
   const T dM = (rho0 * da + left_face(dr) * a) * mfac;
   const T M = M0 + dM;
@@ -913,8 +914,11 @@ struct XRow {
     for (int r = 0; r < R; ++r) d[r] = vleer(sr[r] - sv[r], sv[r] - sl[r]);
     row_left<T, R>(d, dl, T(0));
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      fv[r] = (a[r] > T(0)) ? sl[r] + T(0.5) * dl[r] * (T(1) - nu[r]) : sv[r] - T(0.5) * d[r] * (T(1) + nu[r]);
+    for (int r = 0; r < R; ++r) {
+      // both upwind values, then a select (a branch per face costs more)
+      const T lo = sl[r] + T(0.5) * dl[r] * (T(1) - nu[r]), hi = sv[r] - T(0.5) * d[r] * (T(1) + nu[r]);
+      fv[r] = a[r] > T(0) ? lo : hi;
+    }
   }
   // specific value and own departure of quantity m >= 1 from its input: the
   // energy departure (m = 1) or the face velocity whose momentum it is
@@ -1179,7 +1183,8 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     }
   };
   auto upwind = [&](V sl, V dl, V sr, V dr, V a, V nu) -> V {
-    return (a > T(0)) ? sl + T(0.5) * dl * (T(1) - nu) : sr - T(0.5) * dr * (T(1) + nu);
+    const V lo = sl + T(0.5) * dl * (T(1) - nu), hi = sr - T(0.5) * dr * (T(1) + nu);
+    return a > T(0) ? lo : hi;
   };
   // departure of the specific value of quantity u from raw departures (q, rho)
   auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
@@ -1392,7 +1397,7 @@ __device__ __forceinline__ void xy_group(const Geo &G, const Phys &P, const Pass
 // and walks the y pass on it; only the y pass's results reach HBM.  Results
 // are those of the separate passes up to the pairing of products and sums
 // into fused multiply-adds.
-template <typename T, int W, int NG>
+template <typename T, int W, int NG, bool FULL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_xymarch(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
   constexpr int RB = 4 / NG;  // planes per block
   const int lane = threadIdx.x, ty = threadIdx.y;
@@ -1405,7 +1410,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   const int c1 = min(c0 + M.chunk, G.n[1]);
   if (c0 >= c1) return;
   const int x0 = W * lane;
-  const bool live = x0 < G.n[0];
+  const bool live = FULL || x0 < G.n[0];  // FULL: the rows fill the wave exactly
   const T dt = (T)(A.fac * A.dtp[0]);
   if (grp == 0) xy_group<T, W, 0, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
   else if (grp == 1) xy_group<T, W, 1, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
@@ -2539,8 +2544,10 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   constexpr int NG = sizeof(T) == 8 ? 4 : 2;
   const long ntb = (G.n[2] + 4 / NG - 1) / (4 / NG), nch = (G.n[1] + M.chunk - 1) / M.chunk;
   const dim3 gr((unsigned)(ntb * nch)), bl(64, 4);
-  if (n <= BX) DFK_LAUNCH((k_xymarch<T, 1, NG>), gr, bl, st, G, P, A, M);
-  else DFK_LAUNCH((k_xymarch<T, 2, NG>), gr, bl, st, G, P, A, M);
+  if (n == BX) DFK_LAUNCH((k_xymarch<T, 1, NG, true>), gr, bl, st, G, P, A, M);
+  else if (n < BX) DFK_LAUNCH((k_xymarch<T, 1, NG, false>), gr, bl, st, G, P, A, M);
+  else if (n == 2 * BX) DFK_LAUNCH((k_xymarch<T, 2, NG, true>), gr, bl, st, G, P, A, M);
+  else DFK_LAUNCH((k_xymarch<T, 2, NG, false>), gr, bl, st, G, P, A, M);
   return true;
 }
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp, double fac,
