@@ -272,7 +272,7 @@ PMC_KINDS = ((("k_kick0p<", ", false, true, false>"), "kick"), (("k_kick<", ", f
              (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
              (("k_march<double, 1,",), "pass_y"), (("k_march<float, 1,",), "pass_y"),
              (("k_march<double, 2,",), "pass_z"), (("k_march<float, 2,",), "pass_z"),
-             (("k_xymarch<",), "pass_xy"),
+             (("k_xyshared<",), "pass_xy"),
              (("k_step_final",), "force"), (("k_post<",), "post"))
 
 

@@ -134,6 +134,16 @@ __device__ __forceinline__ V to_lanes(const T (&a)[W]) {
   }
 }
 
+template <typename V, typename T, int W>
+__device__ __forceinline__ void from_lanes(V v, T (&a)[W]) {
+  if constexpr (W == 1) {
+    a[0] = v;
+  } else {
+    a[0] = v.x;
+    a[1] = v.y;
+  }
+}
+
 // cell-centre coordinate: the perturber is the central vertex of the level
 template <typename T>
 __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
@@ -634,11 +644,13 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffAr
 
 // upwind van Leer face value from the values of the cells -2..+1 around the
 // face: a > 0 takes the low-side cell, else the high-side cell, each with its
-// limited difference and the Courant-number correction
+// limited difference and the Courant-number correction (the weights
+// (1 - nu)/2 and (1 + nu)/2 are exact halvings, so that each side is one
+// rounding of s + d w)
 template <typename T>
 __device__ __forceinline__ T face_value(T sm2, T sm1, T s0, T sp1, T a, T nu) {
-  if (a > T(0)) return sm1 + T(0.5) * vleer(s0 - sm1, sm1 - sm2) * (T(1) - nu);
-  return s0 - T(0.5) * vleer(sp1 - s0, s0 - sm1) * (T(1) + nu);
+  if (a > T(0)) return sm1 + vleer(s0 - sm1, sm1 - sm2) * (T(0.5) * (T(1) - nu));
+  return s0 - vleer(sp1 - s0, s0 - sm1) * (T(0.5) * (T(1) + nu));
 }
 
 template <typename T>
@@ -739,12 +751,13 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   // velocity departure on the left face (faces lo..hi are the ones used)
   const T da = gld(A.v[0], lin(G, clampi(x, A.b.lo[0], A.b.hi[0]), j, k));
   const T a = vb + da, nu = a * (dt / dx);
+  const T hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
   const T M0 = rho0 * vb * mfac;
   auto left_face = [&](T sv) -> T {
     const T sm = from_left(sv), sp = from_right(sv);
     const T d = vleer(sp - sv, sv - sm);
     const T dm = from_left(d);
-    const T lo = sm + T(0.5) * dm * (T(1) - nu), hi = sv - T(0.5) * d * (T(1) + nu);
+    const T lo = sm + dm * hl, hi = sv - d * hh;
     return a > T(0) ? lo : hi;
   };
   const T dM = (rho0 * da + left_face(dr) * a) * mfac;
@@ -881,29 +894,49 @@ __device__ __forceinline__ void row_store(T *p, idx_t c, const T (&v)[R]) {
 template <typename T, int R>
 struct XRow {
   T dr[R], da[R];
-  T dt, dx, rho0, ivol, irr[R], a[R], nu[R], dM[R], M[R];
+  T dt, dx, rho0, ivol, mfac, M0, irr[R], a[R], hl[R], hh[R], dM[R], M[R];
 
-  __device__ __forceinline__ void begin(const Geo &G, const Phys &P, T dt_) {
+  // face velocities and Courant numbers of the row
+  __device__ __forceinline__ void flow(const Geo &G, const Phys &P, T dt_) {
     dt = dt_;
     dx = (T)G.dx;
-    const T mfac = dt * dx * dx, cour = dt / dx;
+    mfac = dt * dx * dx;
+    const T cour = dt / dx;
     ivol = T(1) / (dx * dx * dx);
     rho0 = (T)P.rho0;
     const T vb = (T)vback(P, 0);
-    const T M0 = rho0 * vb * mfac;
+    M0 = rho0 * vb * mfac;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
       a[r] = vb + da[r];
-      nu[r] = a[r] * cour;
+      const T nu = a[r] * cour;
+      hl[r] = T(0.5) * (T(1) - nu);
+      hh[r] = T(0.5) * (T(1) + nu);
     }
-    T fv[R];
-    left_faces(dr, fv);
+  }
+  // the mass transfers through the left faces (departures dm_)
+  __device__ __forceinline__ void take_mass(const T (&dm_)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      dM[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
+      dM[r] = dm_[r];
       M[r] = M0 + dM[r];
     }
+  }
+  __device__ __forceinline__ void mass() {
+    T fv[R], dm_[R];
+    left_faces(dr, fv);
+#pragma unroll
+    for (int r = 0; r < R; ++r) dm_[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
+    take_mass(dm_);
+  }
+  __device__ __forceinline__ void recip() {
+#pragma unroll
+    for (int r = 0; r < R; ++r) irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
+  }
+  __device__ __forceinline__ void begin(const Geo &G, const Phys &P, T dt_) {
+    flow(G, P, dt_);
+    recip();
+    mass();
   }
   // left-face value of the upwind van Leer reconstruction of s, per cell
   __device__ __forceinline__ void left_faces(const T (&sv)[R], T (&fv)[R]) const {
@@ -916,7 +949,7 @@ struct XRow {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // both upwind values, then a select (a branch per face costs more)
-      const T lo = sl[r] + T(0.5) * dl[r] * (T(1) - nu[r]), hi = sv[r] - T(0.5) * d[r] * (T(1) + nu[r]);
+      const T lo = sl[r] + dl[r] * hl[r], hi = sv[r] - d[r] * hh[r];
       fv[r] = a[r] > T(0) ? lo : hi;
     }
   }
@@ -1182,8 +1215,9 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       return F;
     }
   };
-  auto upwind = [&](V sl, V dl, V sr, V dr, V a, V nu) -> V {
-    const V lo = sl + T(0.5) * dl * (T(1) - nu), hi = sr - T(0.5) * dr * (T(1) + nu);
+  // the face's weights hl = (1 - nu)/2, hh = (1 + nu)/2 are exact halvings
+  auto upwind = [&](V sl, V dl, V sr, V dr, V a, V hl, V hh) -> V {
+    const V lo = sl + dl * hl, hi = sr - dr * hh;
     return a > T(0) ? lo : hi;
   };
   // departure of the specific value of quantity u from raw departures (q, rho)
@@ -1217,13 +1251,14 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     }
     const V da = face(c0);
     const V a = wind ? vb + da : da, nu = a * cour;
+    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
       if (u > nq) break;
       const V dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
       d0[u] = vleer(s1[u] - s0[u], s0[u] - sm1[u]);
-      const V fv = upwind(sm1[u], dm1, s0[u], d0[u], a, nu);
+      const V fv = upwind(sm1[u], dm1, s0[u], d0[u], a, hl, hh);
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
         M = wind ? M0 + dM : dM;
@@ -1250,12 +1285,13 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       if (u < nq) s2[u + 1] = spec(u, w2[u + 1], w2[0], ir2);
     const V da = va;
     const V a = wind ? vb + da : da, nu = a * cour;
+    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
       if (u > nq) break;
       const V d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
-      const V fv = upwind(s0[u], d0[u], s1[u], d1, a, nu);
+      const V fv = upwind(s0[u], d0[u], s1[u], d1, a, hl, hh);
       V F1;
       if (u == 0) {
         dM = (rho0 * da + fv * a) * mfac;
@@ -1317,13 +1353,96 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   }
 }
 
-// Rows of a column that are the x pass of whole level-0 rows (the fused x and
-// y passes): for row r (clamped to the active range, as the y pass reads its
-// ghosts under bc 1) the x-updated departures of the density and the group's
-// quantities, computed from the row's inputs exactly as k_xrow does; the
-// inputs of the next row are loaded while the y pass uses this one.
+// Fused x and y passes with the density's work done once per plane.  Every
+// quantity group needs the density's transfers: the mass transfers through the
+// x faces of each row, the row's x-updated density and the y pass's reciprocal
+// 1/(rho0 rho), and the mass transfers through the y faces.  The first wave of
+// a plane (the density leader) computes them one row ahead of the march and
+// hands them to the plane's waves (itself included) through LDS, so that the
+// waves move only their own quantities.  Row r sits in slot r mod XY_RS, face
+// f in slot f mod XY_FS; one barrier per row orders the hand-over.  The
+// arithmetic of every value is that of the separate passes (k_xrow, k_march).
+constexpr int XY_RS = 8, XY_FS = 4;
+
+template <typename T, int W>
+struct XyShare {
+  T *rows;   // [XY_RS][3][W][64]: x-face mass transfers, x-updated density, 1/(rho0 rho)
+  T *faces;  // [XY_FS][W][64]: y-face mass transfers
+  int lane;
+  using V = typename lanes_of<T, W>::type;
+  __device__ __forceinline__ T &row(int r, int f, int q) const {
+    return rows[(((r & (XY_RS - 1)) * 3 + f) * W + q) * 64 + lane];
+  }
+  __device__ __forceinline__ T &face(int f, int q) const { return faces[((f & (XY_FS - 1)) * W + q) * 64 + lane]; }
+  __device__ __forceinline__ V rowv(int r, int f) const {
+    T a[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) a[q] = row(r, f, q);
+    return to_lanes<V, T, W>(a);
+  }
+  __device__ __forceinline__ V facev(int f) const {
+    T a[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) a[q] = face(f, q);
+    return to_lanes<V, T, W>(a);
+  }
+  __device__ __forceinline__ void put_face(int f, V v) const {
+    T a[W];
+    from_lanes<V, T, W>(v, a);
+#pragma unroll
+    for (int q = 0; q < W; ++q) face(f, q) = a[q];
+  }
+};
+
+// density and x-face velocity departures of row r (clamped to the active
+// range, as the y pass reads its ghosts under bc 1) of plane t
+template <typename T, int W>
+__device__ __forceinline__ idx_t xy_row_in(const Geo &G, const PassArgs<T> &A, int r, int t, int x0, bool live,
+                                           T (&dr)[W], T (&da)[W]) {
+  const idx_t c = lin(G, x0, clampi(r, 0, G.n[1] - 1), t);
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    dr[q] = T(0);
+    da[q] = T(0);
+  }
+  if (live) {
+    row_load<T, W>(A.qi[0], c, dr);
+    row_load<T, W>(A.v[0], c, da);
+  }
+  return c;
+}
+
+// the leader's x pass of the density of row r: left-face mass transfers,
+// x-updated departure and reciprocal into the row's slot
+template <typename T, int W>
+__device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &G, const Phys &P, T dt,
+                                                                     const XyShare<T, W> &S, int r,
+                                                                     const T (&dr)[W], const T (&da)[W]) {
+  XRow<T, W> X;
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    X.dr[q] = dr[q];
+    X.da[q] = da[q];
+  }
+  X.flow(G, P, dt);
+  X.mass();
+  T out[W];
+  X.update(X.dr, X.dM, out);
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    S.row(r, 0, q) = X.dM[q];
+    S.row(r, 1, q) = out[q];
+    S.row(r, 2, q) = qdiv(T(1), X.rho0 * (X.rho0 + out[q]));
+  }
+  return to_lanes<typename lanes_of<T, W>::type, T, W>(out);
+}
+
+// Rows of a column for the y pass of a group's own quantities: the x pass of
+// those quantities on whole level-0 rows, with the row's mass transfers taken
+// from the leader; the inputs of the next row are loaded while the y pass uses
+// this one.
 template <typename T, int W, int GRP, int NG>
-struct XSrc {
+struct XyOwn {
   using V = typename lanes_of<T, W>::type;
   const Geo *G;
   const Phys *P;
@@ -1334,17 +1453,7 @@ struct XSrc {
   T dr[W], da[W], in[4][W];  // inputs of the next row
 
   __device__ __forceinline__ void load(int r) {
-    const int j = clampi(r, 0, G->n[1] - 1);
-    const idx_t c = lin(*G, x0, j, t);
-#pragma unroll
-    for (int q = 0; q < W; ++q) {
-      dr[q] = T(0);
-      da[q] = T(0);
-    }
-    if (live) {
-      row_load<T, W>(A->qi[0], c, dr);
-      row_load<T, W>(A->v[0], c, da);
-    }
+    const idx_t c = xy_row_in<T, W>(*G, *A, r, t, x0, live, dr, da);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (u < group_n(NG, GRP)) {
@@ -1353,22 +1462,24 @@ struct XSrc {
       }
     }
   }
-  __device__ __forceinline__ void get(int r, V (&w)[5]) {
+  __device__ __forceinline__ void get(int r, const XyShare<T, W> &S, V (&w)[4]) {
     XRow<T, W> X;
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       X.dr[q] = dr[q];
       X.da[q] = da[q];
     }
-    X.begin(*G, *P, dt);
-    T out[W];
-    X.update(X.dr, X.dM, out);
-    w[0] = to_lanes<V, T, W>(out);
+    X.flow(*G, *P, dt);
+    if (group_q(NG, GRP, 0) == 1) X.recip();  // the energy's specific value
+    T dm[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) dm[q] = S.row(r, 0, q);
+    X.take_mass(dm);
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (u < group_n(NG, GRP)) {
         const int m = group_q(NG, GRP, u);
-        T inq[W], sv[W], own[W], F[W];
+        T inq[W], sv[W], own[W], F[W], out[W];
         if (m == 2 || m == 3) xrow_input<T, W>(*G, *A, m, 0, live, X.da, inq);
         else
 #pragma unroll
@@ -1376,48 +1487,177 @@ struct XSrc {
         X.quantity(*P, m, inq, sv, own);
         X.transfers(*P, m, sv, F);
         X.update(own, F, out);
-        w[u + 1] = to_lanes<V, T, W>(out);
+        w[u] = to_lanes<V, T, W>(out);
       }
     }
     load(r + 1);
   }
 };
 
-template <typename T, int W, int GRP, int NG>
-__device__ __forceinline__ void xy_group(const Geo &G, const Phys &P, const PassArgs<T> &A, const MarchArgs<T> &M,
-                                         T dt, int t, int x0, bool live, int c0, int c1) {
-  XSrc<T, W, GRP, NG> src{&G, &P, &A, dt, t, x0, live};
-  src.load(c0 - 2);
-  march_column<T, 1, 1, GRP, false, W, NG>(G, P, M, x0, t, c0, c1, src, live);
+// One plane's y segment [c0, c1) of group GRP's own quantities; with LEAD
+// also the density (its x pass one row ahead, its y-face transfers one face
+// ahead, its update).  Each row is one step that ends in a barrier, so every
+// wave of the block meets the same barriers.  The values a step hands to the
+// next live in rings of three slots whose roles turn with the step's phase
+// (its row's distance from c0, mod 3), so that no value is copied from step
+// to step.  put: the lane writes its results (it is live and the plane
+// exists).
+template <typename T, int W, int GRP, int NG, bool LEAD>
+__device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, const PassArgs<T> &A,
+                                                const MarchArgs<T> &M, T dt, int t, int x0, bool live, bool put,
+                                                int c0, int c1, const XyShare<T, W> &S) {
+  using V = typename lanes_of<T, W>::type;
+  constexpr int nq = group_n(NG, GRP);
+  constexpr int mq[4] = {group_q(NG, GRP, 0), group_q(NG, GRP, 1), group_q(NG, GRP, 2), group_q(NG, GRP, 3)};
+  constexpr bool zq[4] = {mq[0] >= 4, mq[1] >= 4, mq[2] >= 4, mq[3] >= 4};
+  const T dx = (T)G.dx;
+  const T mfac = dt * dx * dx, ivol = T(1) / (dx * dx * dx), cour = dt / dx;
+  const T rho0 = (T)P.rho0;
+  const idx_t st = (idx_t)G.sy;
+  const idx_t base = lin(G, x0, 0, t);
+  T q0[4], sb[4];
+  T *qout[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    q0[u] = (T)qback(P, mq[u]);
+    sb[u] = (T)sback(P, mq[u]);
+    qout[u] = M.qo[mq[u]];
+  }
+  // the face's weights hl = (1 - nu)/2, hh = (1 + nu)/2 are exact halvings
+  auto upwind = [&](V sl, V dl, V sr, V dr, V a) -> V {
+    const V nu = a * cour;
+    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
+    const V lo = sl + dl * hl, hi = sr - dr * hh;
+    return a > T(0) ? lo : hi;
+  };
+  auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
+  auto face = [&](int c) -> V { return live ? gldv<V>(M.v, base + c * st) : V(0); };
+  // mass transfer through a y face from the density around it
+  auto mass_y = [&](V a, V sl, V dl, V sr, V dr) -> V { return (rho0 * a + upwind(sl, dl, sr, dr, a) * a) * mfac; };
+
+  // leader rings: x-updated density of rows c+1 .. c+3 (rr), its limited
+  // difference at c+1 (rd), the mass transfers of faces c, c+1 (rm), the
+  // velocity departure of face c+2 (rv); inputs of row c+4 (ldr, lda)
+  V rr[3], rd[3], rm[3], rv[3];
+  T ldr[W], lda[W];
+  if constexpr (LEAD) {
+    xy_row_in<T, W>(G, A, c0 - 2, t, x0, live, ldr, lda);
+    const V r_m2 = xy_lead_row<T, W>(G, P, dt, S, c0 - 2, ldr, lda);
+    xy_row_in<T, W>(G, A, c0 - 1, t, x0, live, ldr, lda);
+    const V r_m1 = xy_lead_row<T, W>(G, P, dt, S, c0 - 1, ldr, lda);
+    xy_row_in<T, W>(G, A, c0, t, x0, live, ldr, lda);
+    const V r_0 = xy_lead_row<T, W>(G, P, dt, S, c0, ldr, lda);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      xy_row_in<T, W>(G, A, c0 + 1 + k, t, x0, live, ldr, lda);
+      rr[k] = xy_lead_row<T, W>(G, P, dt, S, c0 + 1 + k, ldr, lda);
+    }
+    xy_row_in<T, W>(G, A, c0 + 4, t, x0, live, ldr, lda);
+    const V d_m1 = vleer(r_0 - r_m1, r_m1 - r_m2);
+    const V d_0 = vleer(rr[0] - r_0, r_0 - r_m1);
+    rm[0] = mass_y(face(c0), r_m1, d_m1, r_0, d_0);
+    S.put_face(c0, rm[0]);
+    rd[0] = vleer(rr[1] - rr[0], rr[0] - r_0);
+    rm[1] = mass_y(face(c0 + 1), r_0, d_0, rr[0], rd[0]);
+    S.put_face(c0 + 1, rm[1]);
+    rv[0] = face(min(c0 + 2, c1));
+  }
+  __syncthreads();
+
+  // own rings: specific values at c, c+1 (ss), limited difference at c (sd),
+  // transfer through face c (sF), x-updated departures of rows c .. c+2 (sw),
+  // velocity departure of face c+1 (sv)
+  XyOwn<T, W, GRP, NG> src{&G, &P, &A, dt, t, x0, live};
+  V ss[3][4], sd[3][4], sF[3][4], sw[3][4], sv[3];
+  if constexpr (nq > 0) {
+    V wm2[4], wm1[4];
+    src.load(c0 - 2);
+    src.get(c0 - 2, S, wm2);
+    src.get(c0 - 1, S, wm1);
+    src.get(c0, S, sw[0]);
+    src.get(c0 + 1, S, sw[1]);
+    const V r_m2 = S.rowv(c0 - 2, 1), r_m1 = S.rowv(c0 - 1, 1), r_0 = S.rowv(c0, 1), r_p1 = S.rowv(c0 + 1, 1);
+    const V i_m2 = S.rowv(c0 - 2, 2), i_m1 = S.rowv(c0 - 1, 2), i_0 = S.rowv(c0, 2), i_p1 = S.rowv(c0 + 1, 2);
+    const V a = face(c0);
+    const V dM = S.facev(c0);
+#pragma unroll
+    for (int u = 0; u < nq; ++u) {
+      const V sm2 = spec(u, wm2[u], r_m2, i_m2), sm1 = spec(u, wm1[u], r_m1, i_m1);
+      ss[0][u] = spec(u, sw[0][u], r_0, i_0);
+      ss[1][u] = spec(u, sw[1][u], r_p1, i_p1);
+      const V dm1 = vleer(ss[0][u] - sm1, sm1 - sm2);
+      sd[0][u] = vleer(ss[1][u] - ss[0][u], ss[0][u] - sm1);
+      const V fv = upwind(sm1, dm1, ss[0][u], sd[0][u], a);
+      sF[0][u] = zq[u] ? fv * dM : sb[u] * dM + fv * dM;
+    }
+    src.get(c0 + 2, S, sw[2]);
+    sv[0] = face(c0 + 1);
+  }
+
+  // row c in phase K0: ring slot K0 holds the oldest value, K1 the next, K2
+  // the newest (or the free slot)
+  auto step = [&](auto phase, int c) {
+    constexpr int K0 = decltype(phase)::value, K1 = (K0 + 1) % 3, K2 = (K0 + 2) % 3;
+    const idx_t ic = base + c * st;
+    if constexpr (nq > 0) {
+      const V r2 = S.rowv(c + 2, 1), ir2 = S.rowv(c + 2, 2);
+      const V a = sv[K0];
+      sv[K1] = face(min(c + 2, c1));
+      const V dM = S.facev(c + 1);
+#pragma unroll
+      for (int u = 0; u < nq; ++u) {
+        ss[K2][u] = spec(u, sw[K2][u], r2, ir2);
+        sd[K1][u] = vleer(ss[K2][u] - ss[K1][u], ss[K1][u] - ss[K0][u]);
+        const V fv = upwind(ss[K0][u], sd[K0][u], ss[K1][u], sd[K1][u], a);
+        sF[K1][u] = zq[u] ? fv * dM : sb[u] * dM + fv * dM;
+        if (put) gstv<V>(qout[u], ic, sw[K0][u] - (sF[K1][u] - sF[K0][u]) * ivol);
+      }
+      src.get(c + 3, S, sw[K0]);
+    }
+    if constexpr (LEAD) {
+      if (put) gstv<V>(M.qo[0], ic, S.rowv(c, 1) - (rm[K1] - rm[K0]) * ivol);
+      rd[K1] = vleer(rr[K2] - rr[K1], rr[K1] - rr[K0]);
+      rm[K2] = mass_y(rv[K0], rr[K0], rd[K0], rr[K1], rd[K1]);
+      S.put_face(c + 2, rm[K2]);
+      rv[K1] = face(min(c + 3, c1));
+      rr[K0] = xy_lead_row<T, W>(G, P, dt, S, c + 4, ldr, lda);
+      xy_row_in<T, W>(G, A, c + 5, t, x0, live, ldr, lda);
+    }
+    __syncthreads();
+  };
+  for (int c = c0; c < c1; c += 3) {
+    step(std::integral_constant<int, 0>(), c);
+    if (c + 1 < c1) step(std::integral_constant<int, 1>(), c + 1);
+    if (c + 2 < c1) step(std::integral_constant<int, 2>(), c + 2);
+  }
 }
 
 // Fused x and y passes of level 0 without a finer level (bc 1, rows of at most
-// 64 W cells): one wave per (plane t, quantity group, y segment) holds whole
-// rows, W cells per lane, takes the x pass of each row it needs in registers
-// and walks the y pass on it; only the y pass's results reach HBM.  Results
-// are those of the separate passes up to the pairing of products and sums
-// into fused multiply-adds.
-template <typename T, int W, int NG, bool FULL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_xymarch(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
-  constexpr int RB = 4 / NG;  // planes per block
-  const int lane = threadIdx.x, ty = threadIdx.y;
-  const int grp = __builtin_amdgcn_readfirstlane(ty) % NG;
-  const int ntb = (G.n[2] + RB - 1) / RB;
-  const int tb = (int)(blockIdx.x % (unsigned)ntb), ch = (int)(blockIdx.x / (unsigned)ntb);
-  const int t = tb * RB + ty / NG;
-  if (t >= G.n[2]) return;
+// 64 W cells): one block per (plane, y segment), one wave per quantity group
+// of four, each holding whole rows, W cells per lane; the first group's wave
+// leads the density.  Only the y pass's results reach HBM.  Results are those
+// of the separate passes up to the pairing of products and sums into fused
+// multiply-adds.
+template <typename T, int W, bool FULL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
+  constexpr int NG = 4;
+  __shared__ T rows[XY_RS * 3 * W * 64];
+  __shared__ T faces[XY_FS * W * 64];
+  const int lane = threadIdx.x;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const int t = (int)(blockIdx.x % (unsigned)G.n[2]), ch = (int)(blockIdx.x / (unsigned)G.n[2]);
   const int c0 = ch * M.chunk;
   const int c1 = min(c0 + M.chunk, G.n[1]);
-  if (c0 >= c1) return;
+  if (c0 >= c1) return;  // the whole block
   const int x0 = W * lane;
   const bool live = FULL || x0 < G.n[0];  // FULL: the rows fill the wave exactly
   const T dt = (T)(A.fac * A.dtp[0]);
-  if (grp == 0) xy_group<T, W, 0, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
-  else if (grp == 1) xy_group<T, W, 1, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
-  if constexpr (NG == 4) {
-    if (grp == 2) xy_group<T, W, 2, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
-    else if (grp == 3) xy_group<T, W, 3, NG>(G, P, A, M, dt, t, x0, live, c0, c1);
-  }
+  const XyShare<T, W> S{rows, faces, lane};
+  if (grp == 0) xy_shared_group<T, W, 0, NG, true>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else if (grp == 1) xy_shared_group<T, W, 1, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else if (grp == 2) xy_shared_group<T, W, 2, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else xy_shared_group<T, W, 3, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
 }
 
 // ------------------------------------------------------------ CommUp
@@ -2539,15 +2779,13 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   M.fac = fac;
   M.acc = nullptr;
   M.facc = nullptr;
-  // FP64 splits the quantities over four waves (the two-group form holds too
-  // many registers next to the x pass), FP32 over two
-  constexpr int NG = sizeof(T) == 8 ? 4 : 2;
-  const long ntb = (G.n[2] + 4 / NG - 1) / (4 / NG), nch = (G.n[1] + M.chunk - 1) / M.chunk;
-  const dim3 gr((unsigned)(ntb * nch)), bl(64, 4);
-  if (n == BX) DFK_LAUNCH((k_xymarch<T, 1, NG, true>), gr, bl, st, G, P, A, M);
-  else if (n < BX) DFK_LAUNCH((k_xymarch<T, 1, NG, false>), gr, bl, st, G, P, A, M);
-  else if (n == 2 * BX) DFK_LAUNCH((k_xymarch<T, 2, NG, true>), gr, bl, st, G, P, A, M);
-  else DFK_LAUNCH((k_xymarch<T, 2, NG, false>), gr, bl, st, G, P, A, M);
+  // one block of four waves per (plane, y segment)
+  const long nch = (G.n[1] + M.chunk - 1) / M.chunk;
+  const dim3 gr((unsigned)(G.n[2] * nch)), bl(64, 4);
+  if (n == BX) DFK_LAUNCH((k_xyshared<T, 1, true>), gr, bl, st, G, P, A, M);
+  else if (n < BX) DFK_LAUNCH((k_xyshared<T, 1, false>), gr, bl, st, G, P, A, M);
+  else if (n == 2 * BX) DFK_LAUNCH((k_xyshared<T, 2, true>), gr, bl, st, G, P, A, M);
+  else DFK_LAUNCH((k_xyshared<T, 2, false>), gr, bl, st, G, P, A, M);
   return true;
 }
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp, double fac,

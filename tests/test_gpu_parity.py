@@ -127,7 +127,7 @@ def test_x_pass_launch_forms(dfm, stage, dt, n):
 # Fused x and y passes against separate ones: one wave per row (32, 64 cells),
 # two cells per lane with every lane live (128) or some lanes past the row end
 # (96), y extents of one segment and of several with a ragged last one (40).
-FUSED_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 6), (128, 40, 6)]
+FUSED_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 6), (128, 40, 6), (64, 18, 4), (128, 34, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
