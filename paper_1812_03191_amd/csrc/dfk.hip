@@ -152,10 +152,10 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
 
 // Quotient and square root in the storage type, from the hardware reciprocal
 // and reciprocal square root instead of the correctly rounded expansions: in
-// FP64 the reciprocal takes two Newton steps and the quotient one residual
-// correction, the square root two Goldschmidt steps and one residual
-// correction (each within an ulp of the rounded result); in FP32 both are the
-// single hardware instructions (about 1 ulp each).  Every use has a normal
+// FP64 the reciprocal takes two Newton steps and the quotient is the dividend
+// times it (within about an ulp of the rounded quotient), the square root two
+// Goldschmidt steps and one residual correction (within an ulp); in FP32 both
+// are the single hardware instructions (about 1 ulp each).  Every use has a normal
 // positive operand or divisor (densities and energies near their background,
 // squared distances of at least a quarter cell, sums of two slopes of one
 // sign; a van Leer quotient of slopes of opposite signs is selected away).
@@ -163,8 +163,7 @@ __device__ __forceinline__ double qdiv(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(r, fma(-b, r, 1.0), r);
   r = fma(r, fma(-b, r, 1.0), r);
-  const double q = a * r;
-  return fma(r, fma(-b, q, a), q);
+  return a * r;
 }
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 template <typename V>
