@@ -35,6 +35,7 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {
     "kick": 8 * (5 + 3),          # read rho, e, vx, vy, vz; write vx, vy, vz
     "compress": 8 * (4 + 1),      # read e, vx, vy, vz; write e
+    "kick_compress": 8 * (5 + 4),  # read rho, e, vx, vy, vz; write vx, vy, vz, e
     "diffuse_heat": 8 * (2 + 1),  # read rho, e; write e
     "pass_x": 8 * (5 + 8),        # read rho, e, vx, vy, vz; write the 8 transported
     "pass_y": 8 * (9 + 8),        # read 8 transported + vy; write 8
@@ -266,7 +267,8 @@ def attainable_bandwidth(nbytes=1 << 30, reps=10):
 
 # kernel kind of each kernel name in a counter file (FP64 and FP32 alike):
 # every listed substring must occur in the demangled name
-PMC_KINDS = ((("k_kick0p<", ", false, true, false>"), "kick"), (("k_kick<", ", false, true>"), "kick"),
+PMC_KINDS = ((("k_kick0p<", ", false, true, false, false>"), "kick"), (("k_kick<", ", false, true>"), "kick"),
+             (("k_kick0p<", ", false, true, false, true>"), "kick_compress"),
              (("k_kick0p<", ", true, true, "), "rebuild_kick"), (("k_kick<", ", true, true>"), "rebuild_kick"),
              (("k_compress",), "compress"), (("k_diffuse_heat",), "diffuse_heat"),
              (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
@@ -339,6 +341,8 @@ def main():
                     help="storage of the timed 128^3 run (fp64 is the headline line; fp32 for profiling)")
     ap.add_argument("--serve-jobs", type=int, default=100,
                     help="jobs of the served workload to run (400 is the whole stream; 0 skips)")
+    ap.add_argument("--separate-launches", action="store_true",
+                    help="time the 128^3 run with every stage a launch of its own (no kernel fusion)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/pmc_traffic_config2.json from two counter passes and exit")
     args = ap.parse_args()
@@ -368,6 +372,9 @@ def main():
                   gamma=cfg["gamma"], cfl=cfg["cfl"], seed=cfg["seed"], noise_amp=cfg["noise_amp"],
                   precision=dfm.DF_FP32 if fp32 else dfm.DF_FP64)
     run.set_perturber(cfg["GM"], cfg["eps"], cfg["L"], cfg["mach"], cfg["chi"])
+    if args.separate_launches:
+        run.set_kick_fusion(False)
+        run.set_transport_fusion(False)
     stream = run.stream
     print(f"[bench] 128^3 {args.precision.upper()}: warmup {W}, timed {K}", file=sys.stderr, flush=True)
     run.step(W)
@@ -442,7 +449,8 @@ def main():
         "vs_baseline": None, "dtype": "f32" if fp32 else "f64", "data": "synthetic",
         "config": {"workload": f"128^3 single level {args.precision.upper()}, Mach 1.5, GM 0.01, chi 0.1, "
                                "L 1e-3, Gaussian heat width 2 cells, seed 2 (500-step run)",
-                   "cells": cells, "precision": args.precision},
+                   "cells": cells, "precision": args.precision,
+                   "launches": "separate" if args.separate_launches else "fused"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "force": {"Fx": F[0], "Fy": F[1], "Fz": F[2], "t": F[3]},

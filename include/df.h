@@ -172,6 +172,18 @@ int df_set_viscosity(df_run *run, double c2);
  * differently); DF_EINVAL for other values. */
 int df_set_transport_fusion(df_run *run, int32_t on);
 
+/* Launch shape of the first two sub-steps of a level-0 step (the velocity
+ * source S(dt/2) of eq. 15 and the compressional heating of Sect. 3.3, as
+ * SubStep1 and SubStep3): on (1, default) one launch when the artificial
+ * viscosity is off, whose threads kick their cells' faces and then compress
+ * their cells from the kicked velocities of all six faces (the faces of
+ * neighbouring cells are kicked again with the same arithmetic, not stored);
+ * the kicked velocities and the compressed energy go to buffers of their own,
+ * so that every thread reads the state before the step.  off (0): two
+ * launches.  The results agree to rounding either way; DF_EINVAL for other
+ * values. */
+int df_set_kick_fusion(df_run *run, int32_t on);
+
 /* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
  * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
  * every other boundary is zero-gradient outflow.  mode 1: the paper's list,
@@ -206,10 +218,12 @@ int df_debug_stage(df_run *run, int32_t stage, double dt);
  * signal speeds, with the one-block kernel that logs the force and sets the
  * next time step; DF_K_DT is the time step before the first step of a df_step
  * call (with a signal pass if the state was changed by other calls);
- * DF_K_PASSXY the fused x and y transport passes (df_set_transport_fusion). */
+ * DF_K_PASSXY the fused x and y transport passes (df_set_transport_fusion),
+ * DF_K_KICKCOMP the fused first kick and compression (df_set_kick_fusion). */
 enum {
   DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
-  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_PASSXY, DF_K_NKINDS
+  DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_PASSXY, DF_K_KICKCOMP,
+  DF_K_NKINDS
 };
 int df_timing_enable(df_run *run, int32_t max_launches);
 int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);

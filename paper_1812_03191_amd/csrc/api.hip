@@ -68,6 +68,7 @@ struct df_run {
   bool ready = false;
   bool sig_valid = false;  // the signal-speed partials are those of the current state
   bool fuse_xy = true;     // fuse the x and y passes where transport_xy applies
+  bool fuse_kc = true;     // fuse the first kick and the compression of level 0 (viscosity off)
   bool slot_mode = false;  // single level: the kicks take the step length from the signal-speed slots
   int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
   double visc = 0.0;       // artificial-viscosity coefficient (kept across df_set_perturber)
@@ -106,6 +107,7 @@ void carve(df_run *R, char *base) {
     for (int s = 0; s < 2; ++s)
       for (int m = 0; m < NQ; ++m) B.q[s][m] = c.take<char>(v);
     for (int d = 0; d < 3; ++d) B.v[d] = c.take<char>(v);
+    for (int d = 0; d < 3; ++d) B.vk[d] = l == 0 ? (void *)c.take<char>(v) : nullptr;
     B.etmp = c.take<char>(v);
     B.acc = R->acc_n[l] ? (void *)c.take<char>(R->acc_n[l] * e) : nullptr;
     const Geo &G = R->geo[l];
@@ -148,7 +150,7 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
 // ---------------------------------------------------------------- timing
 // Kernel kinds timed by df_timing_read (the order of the DF_K_* list in df.h).
 enum { K_KICK = 0, K_COMPRESS, K_DIFFUSE, K_PASSX, K_PASSY, K_PASSZ, K_REBUILD, K_COMMUP, K_COMMMEAN,
-       K_DT, K_FORCE, K_ZERO, K_VISC, K_PASSXY, K_NKINDS };
+       K_DT, K_FORCE, K_ZERO, K_VISC, K_PASSXY, K_KICKCOMP, K_NKINDS };
 
 struct TScope {
   df_run *R;
@@ -179,14 +181,28 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   // single level: the kick sets this step's length from the last end-of-step
   // pass's signal speeds, and the compression logs that pass's force
   Scal *slots = R->slot_mode ? R->scal : nullptr;
-  { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale, slots); }
-  if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, G, P, B, c, dtp, scale); }
-  { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale, slots, R->flog); }
-  { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
+  // level 0 may kick and compress in one launch; the transport passes then
+  // read the kicked velocities from vk, and the energy goes q[c][1] -> etmp
+  // (compression) -> q[c][1] (diffusion)
+  const bool kc = R->fuse_kc && G.level == 0 && B.vk[0] && !(P.visc > 0.0);
+  LevBufs Bt = B;  // buffers the transport passes read
+  if (kc) {
+    { TScope t(R, K_KICKCOMP); dfk::kick_compress(st, G, P, B, c, dtp, 0.5 * scale, scale, slots, R->flog); }
+    LevBufs Bd = B;
+    Bd.q[c][1] = B.etmp;
+    Bd.etmp = B.q[c][1];
+    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, Bd, c, dtp, scale, true, true, slots); }
+    for (int d = 0; d < 3; ++d) Bt.v[d] = B.vk[d];
+  } else {
+    { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale, slots); }
+    if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, G, P, B, c, dtp, scale); }
+    { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale, slots, R->flog); }
+    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
+  }
   // the x pass reads the new energy from the diffusion output; every buffer
   // keeps its role, so the launches of two consecutive steps repeat exactly
-  LevBufs Bx = B;
-  Bx.q[c][1] = B.etmp;
+  LevBufs Bx = Bt;
+  if (!kc) Bx.q[c][1] = B.etmp;
   // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
   const bool fused = R->fuse_xy && dfk::transport_xy_fits(G);
   if (fused) {
@@ -194,12 +210,12 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
     dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
   } else {
     { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
-    { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, B, 1 - c, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, Bt, 1 - c, dtp, scale, Gf, facc, R->chunk); }
   }
   // the z pass and the rebuild take the set the y pass wrote (q[c] after
   // separate passes, q[1-c] after the fused ones)
   const int cy = fused ? 1 - c : c;
-  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, B, cy, dtp, scale, Gf, facc, R->chunk); }
+  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
   // a single-level step ends here: the same launch forms the force and the
   // next step's signal-speed partials
   { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, R->nl == 1 ? R->scal : nullptr); }
@@ -515,6 +531,8 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
     R->cur[l] = 0;
     dfk::init_state(st, R->geo[l], P, B, 0, d.seed, d.noise_amp);
     if (B.acc) dfk::zero(st, B.acc, R->acc_n[l] * R->esz);
+    for (int k = 0; k < 3; ++k)
+      if (B.vk[k]) dfk::zero(st, B.vk[k], R->vol[l] * R->esz);
   }
   Scal zero{};
   rc = hip_check(hipMemcpyAsync(R->scal, &zero, sizeof(Scal), hipMemcpyHostToDevice, st), "scalars");
@@ -567,6 +585,14 @@ int df_set_transport_fusion(df_run *R, int32_t on) {
   if (rc) return rc;
   if (on != 0 && on != 1) return fail(DF_EINVAL, "transport fusion must be 0 or 1");
   R->fuse_xy = on == 1;
+  return DF_OK;
+}
+
+int df_set_kick_fusion(df_run *R, int32_t on) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (on != 0 && on != 1) return fail(DF_EINVAL, "kick fusion must be 0 or 1");
+  R->fuse_kc = on == 1;
   return DF_OK;
 }
 

@@ -68,7 +68,8 @@ constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
 struct LevBufs {
   void *q[2][NQ];     // ping-pong transported sets; q[cur][0], q[cur][1] are rho, e
   void *v[3];         // face velocities
-  void *etmp;         // diffusion output
+  void *vk[3];        // level 0: face velocities after the first kick of a fused kick and compression
+  void *etmp;         // diffusion output (the compressed energy after a fused kick and compression)
   void *acc;          // frontier transfers of this (fine) level: [dir][side][q][t2][t1]
   double *hw;         // heat weights on a box of hw_n[0] x hw_n[1] x hw_n[2] cells
                       // centred on the perturber vertex (x fastest)
@@ -99,9 +100,18 @@ void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, 
 // x pass writes them)
 void viscosity(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
                double fac);
-// writes etmp; the caller swaps etmp and q[cur][1]
+// writes etmp; the caller swaps etmp and q[cur][1]; with clear (level 0) the
+// first block also clears clear->smax (after a fused kick and compression)
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur,
-                  const double *dtp, double fac, bool do_diff, bool do_heat);
+                  const double *dtp, double fac, bool do_diff, bool do_heat, Scal *clear = nullptr);
+// level 0 without artificial viscosity: the first kick (fac kfac, as kick) and
+// the compression (fac cfac, as compress) in one launch.  Reads B.v and
+// q[cur]; writes the kicked face velocities to B.vk and the compressed energy
+// to B.etmp (q[cur][1] keeps the energy before the step).  With slots: the
+// step length from the slots and the pending force logged, as kick and
+// compress with log do; the slots are left for diffuse_heat to clear.
+void kick_compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+                   double kfac, double cfac, Scal *slots, double *flog);
 // one transport pass q[src] -> q[1-src]; dir 0 builds the momenta from the
 // face velocities; a fine level adds its frontier transfers into B.acc; a
 // level with a finer one (Gf, fine_acc) takes that level's sums on the frontier

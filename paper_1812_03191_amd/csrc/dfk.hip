@@ -322,10 +322,21 @@ struct KickArgs {
   Box b;                     // union of the three face ranges
   int flo[3][3], fhi[3][3];  // [normal dir][dim] face ranges
   const T *q[NQ];            // rho, e (and the momenta when rebuilding)
-  T *v[3];
+  T *v[3];                   // face velocities written
+  const T *vin[3];           // face velocities read (v itself, or the set a fused kick reads from)
   const double *dtp;
   double fac;
   Scal *slots;               // non-null: the step length from slots->smax (single-level runs)
+  // with the compression fused (level 0): the compressed energy departures
+  // (a buffer other than q[1], which every thread reads for the kick), the
+  // compression's share of the step length, and the force log of the last
+  // step's state (non-null log: the first block logs it, as k_compress2 does)
+  T *eo;
+  double cfac;
+  Scal *log;
+  const double *part;
+  int npart;
+  double *flog;
 };
 
 // Velocity source S(h) (eq. 15): each face velocity receives
@@ -539,6 +550,7 @@ struct DiffArgs {
   const double *dtp;
   double fac;
   int do_diff, do_heat;
+  Scal *clear;  // non-null (level 0 after a fused kick and compression): the first block clears clear->smax
 };
 
 // departure of e/rho from e0/rho0
@@ -591,7 +603,13 @@ template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffArgs<T> A) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  if (!thread_cell(A.b, p, j, k)) return;
+  const bool ok = thread_cell(A.b, p, j, k);
+  if (A.clear && blockIdx.x == 0) {
+    // the kick of this step has read the slots: clear them for this step's
+    // end-of-step pass
+    for (int q = threadIdx.y * BX + threadIdx.x; q < NSLOT; q += BX * BY) A.clear->smax[q] = 0ull;
+  }
+  if (!ok) return;
   const int i = 2 * p;
   const T dt = (T)(A.fac * A.dtp[0]);
   const T rho0 = (T)P.rho0, e0 = (T)P.e0;
@@ -2086,8 +2104,12 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
 // A block then covers the cells of up to two blocks of the one-cell-per-thread
 // grid whose blocks k_post and the final sums count: it writes its partials to
 // slot blockIdx.x and zeros to slot gridDim.x + blockIdx.x (when that is below
-// npart).
-template <typename T, int BCM, bool REBUILD, bool KICK, bool POST>
+// npart).  With COMP (the first kick of a step) it then compresses its cells
+// as k_compress2 does, from the kicked velocities of their six faces: the high
+// faces that other threads own (x face i+2, y face j+1, z face k+1) it kicks
+// again itself with their owners' arithmetic (they are not written); the
+// compressed energy goes to A.eo.
+template <typename T, int BCM, bool REBUILD, bool KICK, bool POST, bool COMP = false>
 __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
@@ -2174,6 +2196,9 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
       const T vb = (T)vback(P, d);
       return qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
     };
+    // kicked velocities of the low faces of both cells and, with COMP, of
+    // their high faces
+    V vlo[3], vhi[3];
     // x: faces i and i+1; below them cell i-1 (the own cell i again at x = 0,
     // the background under bc 2) and cell i
     {
@@ -2198,10 +2223,11 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         ppm.x = i > 0 ? gld(pp, c - 1) : (BCM == 2 ? T(0) : ppc.x);
         vf = rebuild(0, ppm, gldv<V>(pm, c), drm, drc);
       } else {
-        vf = gldv<V>(A.v[0], c);
+        vf = gldv<V>(A.vin[0], c);
       }
       vf = kickv(0, vf, drm, dem, drc, dec, xcx, r2c, dcen);
       gstv<V>(A.v[0], c, vf);
+      vlo[0] = vf;
       if (POST) {
         const V a = vabs((T)vback(P, 0) + vf);
         vmax(a + cs_own);
@@ -2221,13 +2247,15 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
       const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
       if (BCM == 2 && id[d] == 0) {
         gstv<V>(A.v[d], c, V(0));  // a wall: no normal velocity
+        vlo[d] = V(0);
         if (POST) vmax(cs_own);
       } else {
         const idx_t cm = id[d] > 0 ? c - sd : c;
         const V drm = gldv<V>(rho, cm), dem = gldv<V>(e, cm);
-        V vf = REBUILD ? rebuild(d, gldv<V>(pp, cm), gldv<V>(pm, c), drm, drc) : gldv<V>(A.v[d], c);
+        V vf = REBUILD ? rebuild(d, gldv<V>(pp, cm), gldv<V>(pm, c), drm, drc) : gldv<V>(A.vin[d], c);
         vf = kickv(d, vf, drm, dem, drc, dec, V(xd), r2c, dcen);
         gstv<V>(A.v[d], c, vf);
+        vlo[d] = vf;
         if (POST) {
           const V a = vabs((T)vback(P, d) + vf);
           vmax(a + cs_own);
@@ -2238,18 +2266,49 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         const idx_t cf = c + sd;
         if (BCM == 2) {
           gstv<V>(A.v[d], cf, V(0));  // a wall
+          vhi[d] = V(0);
           if (POST) vmax(cs_own);
         } else {
           // both sides read the last cells (zero-gradient outflow)
           const T xr = xcen<T>(G, d, id[d] + 1);
           const V r2r = r2c - xd * xd + xr * xr;
           const V dr_ = qsqrtv(r2r);
-          V vf = REBUILD ? rebuild(d, gldv<V>(pp, c), gldv<V>(pm, c), drc, drc) : gldv<V>(A.v[d], cf);
+          V vf = REBUILD ? rebuild(d, gldv<V>(pp, c), gldv<V>(pm, c), drc, drc) : gldv<V>(A.vin[d], cf);
           vf = kickv(d, vf, drc, dec, drc, dec, V(xr), r2r, dr_);
           gstv<V>(A.v[d], cf, vf);
+          vhi[d] = vf;
           if (POST) vmax(vabs((T)vback(P, d) + vf) + cs_own);
         }
+      } else if (COMP) {
+        // face id+1: the low face of the next cells, kicked as their thread
+        // does (the own cells below it)
+        const idx_t cn = c + sd;
+        const T xn = xcen<T>(G, d, id[d] + 1);
+        const V r2n = d == 1 ? xcx * xcx + xn * xn + zc * zc + eps2 : xcx * xcx + yc * yc + xn * xn + eps2;
+        vhi[d] = kickv(d, gldv<V>(A.vin[d], cn), drc, dec, gldv<V>(rho, cn), gldv<V>(e, cn), V(xn), r2n,
+                       qsqrtv(r2n));
       }
+    }
+    if (COMP) {
+      // x face i+2: the injection face (a zero departure) at x_max, else the
+      // first face of the next pair, kicked as its thread does (lane x)
+      V vx1;
+      vx1.x = vlo[0].y;
+      if (i + 2 == G.n[0]) {
+        vx1.y = T(0);
+      } else {
+        const idx_t cn = c + 2;
+        const T xn = xcen<T>(G, 0, i + 2);
+        const V xnv = V(xn);
+        const V r2n = xnv * xnv + yc * yc + zc * zc + eps2;
+        vx1.y = kickv(0, V(gld(A.vin[0], cn)), V(drc.y), V(dec.y), V(gld(rho, cn)), V(gld(e, cn)), xnv, r2n,
+                      qsqrtv(r2n)).x;
+      }
+      // compression over the step (as k_compress2)
+      const T dtc = (T)(A.cfac * (A.slots ? dtk : A.dtp[0]));
+      const V divv = qdiv((vx1 - vlo[0]) + (vhi[1] - vlo[1]) + (vhi[2] - vlo[2]), V(dx));
+      const V a = T(0.5) * gm1 * dtc * divv;
+      gstv<V>(A.eo, c, qdiv(dec * (T(1) - a) - T(2) * a * (T)P.e0, T(1) + a));
     }
     if (POST) {
       // force of the gas in these cells on the perturber, eq. 18: each cell's
@@ -2261,6 +2320,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
       if (!isfinite(sig)) bad = 1;
     }
   }
+  if (COMP && A.log && blockIdx.x == 0) log_pending_body<BX * BY>(A.part, A.npart, A.log, A.flog);
   if (POST) {
     block_sum3(fx, fy, fz, R.part, R.npart);
     block_signal((double)sig, bad, R.spart, R.S);
@@ -2474,7 +2534,7 @@ template <typename T>
 static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, void *const *v, const double *dtp,
                    double fac, bool rebuild, bool do_kick, LevBufs *post = nullptr, Scal *S = nullptr,
                    Scal *slots = nullptr) {
-  KickArgs<T> A;
+  KickArgs<T> A{};
   A.slots = nullptr;
   for (int d = 0; d < 3; ++d)
     for (int e = 0; e < 3; ++e) {
@@ -2494,7 +2554,10 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
     A.b.hi[e] = max(A.fhi[0][e], max(A.fhi[1][e], A.fhi[2][e]));
   }
   for (int m = 0; m < NQ; ++m) A.q[m] = tp<T>(q[m]);
-  for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(v[d]);
+  for (int d = 0; d < 3; ++d) {
+    A.v[d] = tp<T>(v[d]);
+    A.vin[d] = A.v[d];
+  }
   A.dtp = dtp;
   A.fac = fac;
   const dim3 bl(BX, BY);
@@ -2533,6 +2596,37 @@ void kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, cons
   if (!G.bc) slots = nullptr;  // the slots belong to level 0
   if (P.fp32) kick_t<float>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
   else kick_t<double>(st, G, P, B.q[cur], B.v, dtp, fac, false, true, nullptr, nullptr, slots);
+}
+
+template <typename T>
+static void kick_compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
+                            double kfac, double cfac, Scal *slots, double *flog) {
+  KickArgs<T> A{};
+  A.b = active_box(G);
+  A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
+  for (int m = 0; m < NQ; ++m) A.q[m] = tp<T>(B.q[cur][m]);
+  for (int d = 0; d < 3; ++d) {
+    A.v[d] = tp<T>(B.vk[d]);
+    A.vin[d] = tp<T>(B.v[d]);
+  }
+  A.dtp = dtp;
+  A.fac = kfac;
+  A.slots = slots;
+  A.eo = tp<T>(B.etmp);
+  A.cfac = cfac;
+  A.log = slots;
+  A.part = B.part;
+  A.npart = (int)part_count(G);
+  A.flog = flog;
+  RedArgs<T> R{};
+  const dim3 gr = grid_of(A.b), bl(BX, BY);
+  if (G.bc == 2) DFK_LAUNCH((k_kick0p<T, 2, false, true, false, true>), gr, bl, st, G, P, A, R);
+  else DFK_LAUNCH((k_kick0p<T, 1, false, true, false, true>), gr, bl, st, G, P, A, R);
+}
+void kick_compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double kfac,
+                   double cfac, Scal *slots, double *flog) {
+  if (P.fp32) kick_compress_t<float>(st, G, P, B, cur, dtp, kfac, cfac, slots, flog);
+  else kick_compress_t<double>(st, G, P, B, cur, dtp, kfac, cfac, slots, flog);
 }
 
 void rebuild_kick(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
@@ -2625,8 +2719,9 @@ void viscosity(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur,
 
 template <typename T>
 static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
-                           double fac, bool do_diff, bool do_heat) {
+                           double fac, bool do_diff, bool do_heat, Scal *clear) {
   DiffArgs<T> A;
+  A.clear = G.bc ? clear : nullptr;
   A.b = G.bc ? active_box(G) : uniform_box(G, 1, 1);
   A.rho = tp<T>(B.q[cur][0]);
   A.e = tp<T>(B.q[cur][1]);
@@ -2649,9 +2744,9 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   }
 }
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
-                  double fac, bool do_diff, bool do_heat) {
-  if (P.fp32) diffuse_heat_t<float>(st, G, P, B, cur, dtp, fac, do_diff, do_heat);
-  else diffuse_heat_t<double>(st, G, P, B, cur, dtp, fac, do_diff, do_heat);
+                  double fac, bool do_diff, bool do_heat, Scal *clear) {
+  if (P.fp32) diffuse_heat_t<float>(st, G, P, B, cur, dtp, fac, do_diff, do_heat, clear);
+  else diffuse_heat_t<double>(st, G, P, B, cur, dtp, fac, do_diff, do_heat, clear);
 }
 
 template <typename T, int BC, bool FRONT, int W>

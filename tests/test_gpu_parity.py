@@ -154,6 +154,36 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
     assert fa[3] == fb[3]
 
 
+KC_CASES = [((32, 16, 8), 1, 0), ((64, 12, 6), 1, 1), ((128, 20, 6), 1, 0), ((16, 16, 16), 2, 0),
+            ((16, 16, 16), 3, 1)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,nl,bcmode", KC_CASES)
+def test_fused_kick_compress_equals_separate(dfm, n, nl, bcmode, prec):
+    _say(f"[fused kick+compress] n={n} levels={nl} bc={bcmode} {prec}")
+    nx, ny, nz = n
+    p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
+    runs = []
+    for fuse in (False, True):
+        g = dfm.Run(nx, ny, nz, nlevels=nl, dx0=0.05 if nl == 1 else 0.16, seed=37, noise_amp=1e-3, precision=p)
+        g.set_perturber(0.01, 0.05, 2e-3, 1.3, 0.1)
+        g.set_boundaries(bcmode)
+        g.set_kick_fusion(fuse)
+        g.step(5)
+        runs.append(g)
+    # the kicked high faces of a cell are recomputed with their owner's
+    # arithmetic; only the pairing into fused multiply-adds may differ
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    for lev in range(nl):
+        for name in FIELD_NAMES:
+            a, b = runs[0].field(lev, name), runs[1].field(lev, name)
+            assert np.max(np.abs(a - b)) <= tol * SCALE[name], (lev, name, float(np.max(np.abs(a - b))))
+    fa, fb = runs[0].force(), runs[1].force()
+    assert np.max(np.abs(fa[:3] - fb[:3])) <= 1e2 * tol * np.linalg.norm(fa[:3]), (fa, fb)
+    assert fa[3] == fb[3]
+
+
 # ------------------------------------------------------- full single level
 
 def test_config1_parity_100_steps(dfm):
