@@ -7,7 +7,10 @@ choice changes only the launch shape, never the results (each face transfer is
 computed the same way whichever segment holds it).  ``best_chunk`` times a few
 steps of a scratch run for each candidate and caches the winner per
 (mesh, levels, precision) in a JSON file (``DFMESH_TUNE_CACHE`` or
-``~/.cache/dfmesh/autotune.json``).
+``~/.cache/dfmesh/autotune.json``).  The winner is the longest segment whose
+lone-run time is within ``SLACK`` of the fastest: jobs of the batching engine
+share the GPU, where the halo rows a short segment recomputes cost throughput
+that a lone run hides behind its extra waves.
 """
 from __future__ import annotations
 
@@ -16,6 +19,7 @@ import os
 import threading
 
 CANDIDATES = (8, 16, 32, 64)
+SLACK = float(os.environ.get("DFMESH_TUNE_SLACK", "0.15"))
 _lock = threading.Lock()
 _mem: dict = {}
 
@@ -81,7 +85,8 @@ def best_chunk(cfg: dict, precision: int, *, use_cache=True) -> int:
                 _mem[k] = int(d[k]["chunk"])
                 return _mem[k]
     times = {c: time_chunk(cfg, precision, c) for c in CANDIDATES}
-    best = min(times, key=times.get)
+    fastest = min(times.values())
+    best = max(c for c in CANDIDATES if times[c] <= (1.0 + SLACK) * fastest)
     with _lock:
         _mem[k] = best
         if use_cache:
