@@ -1703,41 +1703,75 @@ __device__ __forceinline__ int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i
 // CommUp (Sect. 3.2.1, Fig. 2): every fine entry outside the fine active set
 // from the 27 coarse entries around its host, interpolating along z, then y,
 // then x.  The background is uniform, so departures interpolate like values.
+// One thread per coarse host: its eight fine children share the 27 coarse
+// neighbours and, since the limited slope of a 1-D step does not depend on
+// which half of the host a child takes, every slope is formed once for both
+// children (19 slopes instead of 8 x 13).  A.b counts hosts relative to the
+// covered coarse box (host H = Gc.n/4 + h).
 template <typename T, int CBC>
 __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A) {
-  int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
-  const int id[3] = {i, j, k};
-  bool active = true;
+  int h[3];
+  if (!thread_cell(A.b, h[0], h[1], h[2])) return;
+  // children 2h, 2h+1 along each axis; the host is skipped when all eight are
+  // active entries (which the fine level owns)
+  bool inner = true;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int hi = Gf.n[d] + (d == A.stag ? 1 : 0);
-    if (id[d] < 0 || id[d] >= hi) active = false;
+    if (2 * h[d] < 0 || 2 * h[d] + 1 >= hi) inner = false;
   }
-  if (active) return;
-  int H[3], odd[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    H[d] = Gc.n[d] / 4 + fdiv2(id[d]);
-    odd[d] = id[d] - 2 * fdiv2(id[d]);
-  }
+  if (inner) return;
+  const int H0 = Gc.n[0] / 4 + h[0], H1 = Gc.n[1] / 4 + h[1], H2 = Gc.n[2] / 4 + h[2];
   auto C = [&](int a, int b, int cc) -> T {
-    const int ci = H[0] + a, cj = H[1] + b, ck = H[2] + cc;
+    const int ci = H0 + a, cj = H1 + b, ck = H2 + cc;
     if (CBC) {
       if (A.stag < 0) return cread<CBC>(A.Q, Gc, ci, cj, ck);
       return fread_bc<CBC>(A.Q, Gc, A.stag, ci, cj, ck);
     }
     return A.Q[lin(Gc, ci, cj, ck)];
   };
-  T r[3];
+  // both children of one 1-D step
+  auto up2 = [&](bool stag_axis, T m, T c, T p, T &lo, T &hi) {
+    if (stag_axis) {
+      lo = c;
+      hi = T(0.5) * (c + p);
+    } else {
+      const T sl = vleer(p - c, c - m);
+      lo = c + sl * T(-0.25);
+      hi = c + sl * T(0.25);
+    }
+  };
+  T qz[2][3][3];  // [z child][x offset][y offset]
 #pragma unroll
-  for (int a = -1; a <= 1; ++a) {
-    T qz[3];
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = -1; b <= 1; ++b) qz[b + 1] = up1d<T>(A.stag == 2, odd[2], C(a, b, -1), C(a, b, 0), C(a, b, 1));
-    r[a + 1] = up1d<T>(A.stag == 1, odd[1], qz[0], qz[1], qz[2]);
-  }
-  A.out[lin(Gf, i, j, k)] = up1d<T>(A.stag == 0, odd[0], r[0], r[1], r[2]);
+    for (int b = 0; b < 3; ++b) up2(A.stag == 2, C(a - 1, b - 1, -1), C(a - 1, b - 1, 0), C(a - 1, b - 1, 1),
+                                    qz[0][a][b], qz[1][a][b]);
+  T r[2][2][3];  // [z child][y child][x offset]
+#pragma unroll
+  for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) up2(A.stag == 1, qz[o2][a][0], qz[o2][a][1], qz[o2][a][2], r[o2][0][a], r[o2][1][a]);
+#pragma unroll
+  for (int o2 = 0; o2 < 2; ++o2)
+#pragma unroll
+    for (int o1 = 0; o1 < 2; ++o1) {
+      T v[2];
+      up2(A.stag == 0, r[o2][o1][0], r[o2][o1][1], r[o2][o1][2], v[0], v[1]);
+      const int k = 2 * h[2] + o2, j = 2 * h[1] + o1;
+#pragma unroll
+      for (int o0 = 0; o0 < 2; ++o0) {
+        const int i = 2 * h[0] + o0;
+        const int id[3] = {i, j, k};
+        bool in = true, active = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (id[d] < -Gf.g || id[d] >= Gf.s[d] - Gf.g) in = false;
+          if (id[d] < 0 || id[d] >= Gf.n[d] + (d == A.stag ? 1 : 0)) active = false;
+        }
+        if (in && !active) A.out[lin(Gf, i, j, k)] = v[o0];
+      }
+    }
 }
 
 // ------------------------------------------------------------ CommMean
@@ -2926,6 +2960,9 @@ void zero(hipStream_t st, void *p, size_t bytes) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<unsigned int *>(p), n);
 }
 
+// floor(i / 2)
+static int fdiv2_host(int i) { return (i >= 0) ? i / 2 : -((1 - i) / 2); }
+
 template <typename T>
 static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const Geo &Gf, LevBufs &Bf, int curf) {
   for (int f = 0; f < NSTATE; ++f) {
@@ -2933,7 +2970,11 @@ static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const
     A.stag = f >= 2 ? f - 2 : -1;
     A.Q = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
     A.out = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
-    A.b = full_box(Gf);
+    // hosts of the stored fine entries [-g, n+g) along each axis
+    for (int d = 0; d < 3; ++d) {
+      A.b.lo[d] = fdiv2_host(-Gf.g);
+      A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
+    }
     if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
     else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
     else DFK_LAUNCH((k_commup<T, 0>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
