@@ -409,10 +409,13 @@ def test_viscosity_run_parity(dfm, nl, n, steps, walls):
     assert fe < 1e-9, (fg, fo)
 
 
-def test_nested_wider_ghosts_parity(dfm):
+@pytest.mark.parametrize("gf", [11, 12])
+def test_nested_wider_ghosts_parity(dfm, gf):
+    # an odd width leaves one child of the outermost coarse hosts outside the
+    # stored fine box
     cfg = inputs.job(16, 2, 0.6, 5e-3, 0.1, 1e-3, seed=8)
-    _say("[parity] nested ghost width 12")
-    o, g = _pair(dfm, cfg, gf=12)
+    _say(f"[parity] nested ghost width {gf}")
+    o, g = _pair(dfm, cfg, gf=gf)
     o.step(4)
     g.step(4)
     errs = _field_errors(o, g, 2)
