@@ -156,14 +156,16 @@ struct TScope {
   df_run *R;
   bool on;
   TScope(df_run *r, int kind) : R(r), on(r->timing && r->ev_used + 1 < r->ev.size()) {
+    // a record that fails leaves its event unrecorded, which df_timing_read
+    // reports when it takes the pair's elapsed time
     if (on) {
       R->ev_kind[R->ev_used / 2] = kind;
-      hipEventRecord(R->ev[R->ev_used], R->stream);
+      (void)hipEventRecord(R->ev[R->ev_used], R->stream);
     }
   }
   ~TScope() {
     if (on) {
-      hipEventRecord(R->ev[R->ev_used + 1], R->stream);
+      (void)hipEventRecord(R->ev[R->ev_used + 1], R->stream);
       R->ev_used += 2;
     }
   }
@@ -803,7 +805,7 @@ int df_timing_enable(df_run *R, int32_t max_launches) {
   if (max_launches < 0 || max_launches > (1 << 20)) return fail(DF_EINVAL, "max_launches out of range");
   rc = hip_check(hipStreamSynchronize(R->stream), "timing");
   if (rc) return rc;
-  for (hipEvent_t e : R->ev) hipEventDestroy(e);
+  for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);  // idle after the synchronisation
   R->ev.clear();
   R->ev_kind.clear();
   R->ev_used = 0;
@@ -854,7 +856,7 @@ int df_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {
 
 int df_destroy(df_run *R) {
   if (!R) return fail(DF_EINVAL, "null run handle");
-  for (hipEvent_t e : R->ev) hipEventDestroy(e);
+  for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);  // released once any pending record completes
   delete R;
   return DF_OK;
 }
@@ -962,7 +964,7 @@ hipEvent_t engine_event(df_engine *E) {
     return e;
   }
   hipEvent_t e = nullptr;
-  hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  if (hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create")) return nullptr;
   return e;
 }
 
@@ -976,7 +978,7 @@ void engine_reap(df_engine *E, bool wait) {
       E->retired[k++] = r;
       continue;
     }
-    hipGraphExecDestroy(r.first);
+    (void)hipGraphExecDestroy(r.first);  // its last launch has completed
     E->ev_pool.push_back(r.second);
   }
   E->retired.resize(k);
@@ -986,6 +988,7 @@ int engine_capture(df_engine *E) {
   if (E->exec) {
     // launches of the old graph may be in flight on the caller's stream
     hipEvent_t ev = engine_event(E);
+    if (!ev) return DF_EDEVICE;
     int rc = hip_check(hipEventRecord(ev, E->main), "event record");
     if (rc) return rc;
     E->retired.push_back({E->exec, ev});
@@ -999,8 +1002,16 @@ int engine_capture(df_engine *E) {
   if (act.empty()) return DF_OK;
   int rc = hip_check(hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed), "graph capture");
   if (rc) return rc;
-  hipEventRecord(E->fork, E->cap);
-  for (hipStream_t w : E->workers) hipStreamWaitEvent(w, E->fork, 0);
+  // a failed fork or join leaves the capture unusable: end it and report
+  auto abandon = [&](int code) {
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(E->cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    return code;
+  };
+  rc = hip_check(hipEventRecord(E->fork, E->cap), "graph fork");
+  for (size_t w = 0; !rc && w < E->workers.size(); ++w)
+    rc = hip_check(hipStreamWaitEvent(E->workers[w], E->fork, 0), "graph fork");
+  if (rc) return abandon(rc);
   for (size_t q = 0; q < act.size(); ++q) {
     EngineJob &J = E->jobs[act[q]];
     J.worker = (int)(q % E->workers.size());
@@ -1011,15 +1022,16 @@ int engine_capture(df_engine *E) {
     enqueue_steps(R, ENGINE_STEPS_PER_REPLAY);
     R->timing = timing;
   }
-  for (size_t w = 0; w < E->workers.size(); ++w) {
-    hipEventRecord(E->join[w], E->workers[w]);
-    hipStreamWaitEvent(E->cap, E->join[w], 0);
+  for (size_t w = 0; !rc && w < E->workers.size(); ++w) {
+    rc = hip_check(hipEventRecord(E->join[w], E->workers[w]), "graph join");
+    if (!rc) rc = hip_check(hipStreamWaitEvent(E->cap, E->join[w], 0), "graph join");
   }
+  if (rc) return abandon(rc);
   hipGraph_t g = nullptr;
   rc = hip_check(hipStreamEndCapture(E->cap, &g), "graph capture end");
   if (rc) return rc;
   rc = hip_check(hipGraphInstantiate(&E->exec, g, nullptr, nullptr, 0), "graph instantiate");
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);  // the instantiated graph does not need it
   E->captures++;
   return rc;
 }
@@ -1151,7 +1163,9 @@ int df_engine_step(df_engine *E, int32_t n) {
     }
     if (!p.slots.empty()) {
       p.ev = engine_event(E);
-      hipEventRecord(p.ev, E->main);
+      if (!p.ev) return DF_EDEVICE;
+      const int rc = hip_check(hipEventRecord(p.ev, E->main), "event record");
+      if (rc) return rc;
       E->pending.push_back(p);
     }
   }
@@ -1250,22 +1264,24 @@ int df_engine_stats(df_engine *E, int64_t out[2]) {
 
 int df_engine_destroy(df_engine *E) {
   if (!E) return fail(DF_EINVAL, "null engine");
-  if (E->main) hipStreamSynchronize(E->main);
+  // a failed synchronisation is reported; the teardown below goes on (its
+  // destroy calls have nothing further to report)
+  const int rc = E->main ? hip_check(hipStreamSynchronize(E->main), "engine destroy") : DF_OK;
   engine_reap(E, true);
-  if (E->exec) hipGraphExecDestroy(E->exec);
+  if (E->exec) (void)hipGraphExecDestroy(E->exec);
   for (auto &J : E->jobs)
     if (J.used) delete J.run;
-  for (auto &p : E->pending) hipEventDestroy(p.ev);
-  for (hipEvent_t e : E->ev_pool) hipEventDestroy(e);
+  for (auto &p : E->pending) (void)hipEventDestroy(p.ev);
+  for (hipEvent_t e : E->ev_pool) (void)hipEventDestroy(e);
   for (hipEvent_t e : E->join)
-    if (e) hipEventDestroy(e);
-  if (E->fork) hipEventDestroy(E->fork);
+    if (e) (void)hipEventDestroy(e);
+  if (E->fork) (void)hipEventDestroy(E->fork);
   for (hipStream_t w : E->workers)
-    if (w) hipStreamDestroy(w);
-  if (E->admin) hipStreamDestroy(E->admin);
-  if (E->cap) hipStreamDestroy(E->cap);
+    if (w) (void)hipStreamDestroy(w);
+  if (E->admin) (void)hipStreamDestroy(E->admin);
+  if (E->cap) (void)hipStreamDestroy(E->cap);
   delete E;
-  return DF_OK;
+  return rc;
 }
 
 }  // extern "C"
