@@ -2190,9 +2190,13 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
     xcx.x = xcen<T>(G, 0, i);
     xcx.y = xcen<T>(G, 0, i + 1);
     const T yc = xcen<T>(G, 1, j), zc = xcen<T>(G, 2, k);
-    const V r2c = xcx * xcx + yc * yc + zc * zc + eps2;
+    // squared softened distance of cells at (xv, y, z): every cell's distance
+    // is formed by this one expression, whichever thread needs it
+    auto r2of = [&](V xv, T y, T z) -> V { return xv * xv + y * y + z * z + eps2; };
+    const V r2c = r2of(xcx, yc, zc);
     const V dcen = qsqrtv(r2c);
     const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
+    const int lane = threadIdx.x;  // pair p-1 is the lane before (BX is the wave width)
     auto sound1 = [&](T dr, T de) -> T {
       const T r = rho0 + dr, en = e0 + de;
       if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
@@ -2213,19 +2217,23 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
     };
     V cs_own = V(0);
     if (POST) cs_own = sound(drc, dec);
+    const T csprev = POST ? dpp_fill<DPP_WAVE_SHR1>(cs_own.y, T(0)) : T(0);
     // the kick of a face pair: cells below (drm, dem) and above (dcr, der) the
-    // faces, the position of the cell above (xr, r2r, dr_)
-    auto kickv = [&](int d, V vf, V drm, V dem, V dcr, V der, V xr, V r2r, V dr_) -> V {
+    // faces, the coordinate along d of the cell above (xr; the cell below is
+    // at xr - dx) and the distances of the cells below (dm) and above (dr_)
+    auto kickv = [&](int d, V vf, V drm, V dem, V dcr, V der, V xr, V dm, V dr_) -> V {
       if (KICK) {
         const V rface = rho0 + T(0.5) * (drm + dcr);
         const V gradp = qdiv(gm1 * (der - dem), dx * rface);
         const V xm = xr - dx;
-        const V dm = qsqrtv(r2r - xr * xr + xm * xm);
         const V gradphi = qdiv(GM * (xr + xm), dm * dr_ * (dm + dr_));
         vf = vf - h * (gradp + gradphi);
       }
       return vf;
     };
+    // the own cells' distances and sound speeds shifted by one lane: lane l
+    // gets pair l-1's second cell, cell i-1 (lane 0 forms it itself)
+    const T dprev = dpp_fill<DPP_WAVE_SHR1>(dcen.y, T(0));
     auto rebuild = [&](int d, V ppm, V pmc, V drm, V dcr) -> V {
       const T vb = (T)vback(P, d);
       return qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
@@ -2259,13 +2267,23 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
       } else {
         vf = gldv<V>(A.vin[0], c);
       }
-      vf = kickv(0, vf, drm, dem, drc, dec, xcx, r2c, dcen);
+      V dmx;
+      dmx.y = dcen.x;
+      if (i > 0 && lane > 0) {
+        dmx.x = dprev;
+      } else {
+        V xb;
+        xb.x = xcen<T>(G, 0, i - 1);  // cell i-1 (a ghost position at x = 0)
+        xb.y = xb.x;
+        dmx.x = qsqrtv(r2of(xb, yc, zc)).x;
+      }
+      vf = kickv(0, vf, drm, dem, drc, dec, xcx, dmx, dcen);
       gstv<V>(A.v[0], c, vf);
       vlo[0] = vf;
       if (POST) {
         const V a = vabs((T)vback(P, 0) + vf);
         vmax(a + cs_own);
-        if (i > 0) sig = fmax(sig, a.x + sound1(drm.x, dem.x));
+        if (i > 0) sig = fmax(sig, a.x + (lane > 0 ? csprev : sound1(drm.x, dem.x)));
         sig = fmax(sig, a.y + cs_own.x);
       }
       if (i + 1 == G.n[0] - 1) {
@@ -2287,7 +2305,10 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         const idx_t cm = id[d] > 0 ? c - sd : c;
         const V drm = gldv<V>(rho, cm), dem = gldv<V>(e, cm);
         V vf = REBUILD ? rebuild(d, gldv<V>(pp, cm), gldv<V>(pm, c), drm, drc) : gldv<V>(A.vin[d], c);
-        vf = kickv(d, vf, drm, dem, drc, dec, V(xd), r2c, dcen);
+        // the cell below id (a ghost position at id = 0)
+        const T xb = xcen<T>(G, d, id[d] - 1);
+        const V dmb = qsqrtv(d == 1 ? r2of(xcx, xb, zc) : r2of(xcx, yc, xb));
+        vf = kickv(d, vf, drm, dem, drc, dec, V(xd), dmb, dcen);
         gstv<V>(A.v[d], c, vf);
         vlo[d] = vf;
         if (POST) {
@@ -2305,10 +2326,9 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         } else {
           // both sides read the last cells (zero-gradient outflow)
           const T xr = xcen<T>(G, d, id[d] + 1);
-          const V r2r = r2c - xd * xd + xr * xr;
-          const V dr_ = qsqrtv(r2r);
+          const V dr_ = qsqrtv(d == 1 ? r2of(xcx, xr, zc) : r2of(xcx, yc, xr));
           V vf = REBUILD ? rebuild(d, gldv<V>(pp, c), gldv<V>(pm, c), drc, drc) : gldv<V>(A.vin[d], cf);
-          vf = kickv(d, vf, drc, dec, drc, dec, V(xr), r2r, dr_);
+          vf = kickv(d, vf, drc, dec, drc, dec, V(xr), dcen, dr_);
           gstv<V>(A.v[d], cf, vf);
           vhi[d] = vf;
           if (POST) vmax(vabs((T)vback(P, d) + vf) + cs_own);
@@ -2318,8 +2338,8 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         // does (the own cells below it)
         const idx_t cn = c + sd;
         const T xn = xcen<T>(G, d, id[d] + 1);
-        const V r2n = d == 1 ? xcx * xcx + xn * xn + zc * zc + eps2 : xcx * xcx + yc * yc + xn * xn + eps2;
-        vhi[d] = kickv(d, gldv<V>(A.vin[d], cn), drc, dec, gldv<V>(rho, cn), gldv<V>(e, cn), V(xn), r2n,
+        const V r2n = d == 1 ? r2of(xcx, xn, zc) : r2of(xcx, yc, xn);
+        vhi[d] = kickv(d, gldv<V>(A.vin[d], cn), drc, dec, gldv<V>(rho, cn), gldv<V>(e, cn), V(xn), dcen,
                        qsqrtv(r2n));
       }
     }
@@ -2334,9 +2354,8 @@ __global__ void __launch_bounds__(BX * BY) k_kick0p(Geo G, Phys P, KickArgs<T> A
         const idx_t cn = c + 2;
         const T xn = xcen<T>(G, 0, i + 2);
         const V xnv = V(xn);
-        const V r2n = xnv * xnv + yc * yc + zc * zc + eps2;
-        vx1.y = kickv(0, V(gld(A.vin[0], cn)), V(drc.y), V(dec.y), V(gld(rho, cn)), V(gld(e, cn)), xnv, r2n,
-                      qsqrtv(r2n)).x;
+        vx1.y = kickv(0, V(gld(A.vin[0], cn)), V(drc.y), V(dec.y), V(gld(rho, cn)), V(gld(e, cn)), xnv,
+                      V(dcen.y), qsqrtv(r2of(xnv, yc, zc))).x;
       }
       // compression over the step (as k_compress2)
       const T dtc = (T)(A.cfac * (A.slots ? dtk : A.dtp[0]));
