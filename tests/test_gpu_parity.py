@@ -184,6 +184,17 @@ def test_fused_kick_compress_equals_separate(dfm, n, nl, bcmode, prec):
     assert fa[3] == fb[3]
 
 
+def test_fusion_switches_reject_other_values(dfm):
+    # through the C ABI itself (the binding passes booleans)
+    from paper_1812_03191_amd import _lib
+
+    g = dfm.Run(16, dx0=0.1)
+    lib = _lib._load()
+    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion):
+        assert fn(g._h, 0) == 0 and fn(g._h, 1) == 0
+        assert fn(g._h, 2) == -1 and fn(g._h, -1) == -1
+
+
 # ------------------------------------------------------- full single level
 
 def test_config1_parity_100_steps(dfm):

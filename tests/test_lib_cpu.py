@@ -84,3 +84,17 @@ def test_serving_work_count():
     from paper_1812_03191_amd.serve import job_cell_updates
 
     assert job_cell_updates(dict(nx=32, ny=32, nz=32, nlevels=3), 10) == 10 * 32 ** 3 * 7
+
+
+def test_launch_switches_need_a_bound_run():
+    # before df_bind the fusion switches report an out-of-order call; a null
+    # handle is a bad argument (their values are checked on the GPU)
+    import paper_1812_03191_amd as dfm
+    from paper_1812_03191_amd import _lib
+
+    h = dfm.init_mesh(16, 16, 16, 1, 0.1)
+    lib = _lib._load()
+    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion):
+        assert fn(h, 1) == -2
+        assert fn(None, 1) == -1
+    dfm.destroy(h)
