@@ -1376,7 +1376,9 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
 // 1/(rho0 rho), and the mass transfers through the y faces.  The first wave of
 // a plane (the density leader) computes them one row ahead of the march and
 // hands them to the plane's waves (itself included) through LDS, so that the
-// waves move only their own quantities.  Row r sits in slot r mod XY_RS, face
+// waves move only their own quantities; the reciprocal of each row past the
+// segment's first ones is formed by the second wave, a row behind the leader
+// (whose step is the longest of the four).  Row r sits in slot r mod XY_RS, face
 // f in slot f mod XY_FS; one barrier per row orders the hand-over.  The
 // arithmetic of every value is that of the separate passes (k_xrow, k_march).
 constexpr int XY_RS = 8, XY_FS = 4;
@@ -1429,12 +1431,13 @@ __device__ __forceinline__ idx_t xy_row_in(const Geo &G, const PassArgs<T> &A, i
   return c;
 }
 
-// the leader's x pass of the density of row r: left-face mass transfers,
-// x-updated departure and reciprocal into the row's slot
+// the leader's x pass of the density of row r: left-face mass transfers and
+// x-updated departure into the row's slot, with ir also the reciprocal
 template <typename T, int W>
 __device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &G, const Phys &P, T dt,
                                                                      const XyShare<T, W> &S, int r,
-                                                                     const T (&dr)[W], const T (&da)[W]) {
+                                                                     const T (&dr)[W], const T (&da)[W],
+                                                                     bool ir = true) {
   XRow<T, W> X;
 #pragma unroll
   for (int q = 0; q < W; ++q) {
@@ -1449,7 +1452,7 @@ __device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &
   for (int q = 0; q < W; ++q) {
     S.row(r, 0, q) = X.dM[q];
     S.row(r, 1, q) = out[q];
-    S.row(r, 2, q) = qdiv(T(1), X.rho0 * (X.rho0 + out[q]));
+    if (ir) S.row(r, 2, q) = qdiv(T(1), X.rho0 * (X.rho0 + out[q]));
   }
   return to_lanes<typename lanes_of<T, W>::type, T, W>(out);
 }
@@ -1567,7 +1570,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       xy_row_in<T, W>(G, A, c0 + 1 + k, t, x0, live, ldr, lda);
-      rr[k] = xy_lead_row<T, W>(G, P, dt, S, c0 + 1 + k, ldr, lda);
+      rr[k] = xy_lead_row<T, W>(G, P, dt, S, c0 + 1 + k, ldr, lda, k < 2);
     }
     xy_row_in<T, W>(G, A, c0 + 4, t, x0, live, ldr, lda);
     const V d_m1 = vleer(r_0 - r_m1, r_m1 - r_m2);
@@ -1631,13 +1634,19 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
       }
       src.get(c + 3, S, sw[K0]);
     }
+    if constexpr (GRP == 1) {
+      // the reciprocal of row c+3 (its density came from the leader a step
+      // ago), for the y walk one step later; the leader carries more work
+#pragma unroll
+      for (int q = 0; q < W; ++q) S.row(c + 3, 2, q) = qdiv(T(1), rho0 * (rho0 + S.row(c + 3, 1, q)));
+    }
     if constexpr (LEAD) {
       if (put) gstv<V>(M.qo[0], ic, S.rowv(c, 1) - (rm[K1] - rm[K0]) * ivol);
       rd[K1] = vleer(rr[K2] - rr[K1], rr[K1] - rr[K0]);
       rm[K2] = mass_y(rv[K0], rr[K0], rd[K0], rr[K1], rd[K1]);
       S.put_face(c + 2, rm[K2]);
       rv[K1] = face(min(c + 3, c1));
-      rr[K0] = xy_lead_row<T, W>(G, P, dt, S, c + 4, ldr, lda);
+      rr[K0] = xy_lead_row<T, W>(G, P, dt, S, c + 4, ldr, lda, false);
       xy_row_in<T, W>(G, A, c + 5, t, x0, live, ldr, lda);
     }
     __syncthreads();
