@@ -2882,10 +2882,14 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   const long ntb = (M.hi[td] - M.lo[td] + 1) / 2;
   const long nch = (ext + M.chunk - 1) / M.chunk;
   const bool front = M.acc || M.facc;
-  // FP32 level 0 without frontier transfers: two adjacent columns per lane
-  // (its rows start 128-byte aligned and the x extent is even); FP64 keeps one
-  // (the two-column form holds twice the registers and was not faster)
-  const int w = (sizeof(T) == 4 && G.bc && !front && (M.hi[0] - M.lo[0]) % 2 == 0 && M.lo[0] % 2 == 0) ? 2 : 1;
+  // level 0 without frontier transfers: two adjacent columns per lane (its
+  // rows start 128-byte aligned and the x extent is even) in FP32, and in FP64
+  // for the z pass (its 16-byte accesses halve the address and load work per
+  // byte; the FP64 y pass is fused with the x pass or keeps one column)
+  const int w = ((sizeof(T) == 4 || dir == 2) && G.bc && !front && (M.hi[0] - M.lo[0]) % 2 == 0 &&
+                 M.lo[0] % 2 == 0)
+                    ? 2
+                    : 1;
   const long nbx = (M.hi[0] - M.lo[0] + 64 * w - 1) / (64 * w);
   const dim3 gr((unsigned)(nbx * ntb * nch)), bl(64, 4);
   if (!G.bc) {
