@@ -1141,7 +1141,10 @@ struct ColSrc {
     constexpr int pa = NG == 2 ? ((DIR == 1) ? 0 : 2) : 0;
     const T *q = u < 0 ? rho : qin[u];
     if (walls && (c < 0 || c >= n)) {
-      const idx_t m = base + mirror_idx(c, n) * st;
+      // rows c0-2 .. c1+1 have a mirror image in the active range for n >= 2;
+      // the row c1+2 fetched past the last one (never used) may not (n = 2)
+      // and is kept in range
+      const idx_t m = base + clampi(mirror_idx(c, n), 0, n - 1) * st;
       if (GRP == wg && (u == pa || u == pa + 1)) return -gldv<V>(qin[u ^ 1], m);
       return gldv<V>(q, m);
     }

@@ -127,7 +127,8 @@ def test_x_pass_launch_forms(dfm, stage, dt, n):
 # Fused x and y passes against separate ones: one wave per row (32, 64 cells),
 # two cells per lane with every lane live (128) or some lanes past the row end
 # (96), y extents of one segment and of several with a ragged last one (40).
-FUSED_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 6), (128, 40, 6), (64, 18, 4), (128, 34, 2)]
+FUSED_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 6), (128, 40, 6), (64, 18, 4), (128, 34, 2), (64, 2, 4),
+                (128, 4, 2)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -155,7 +156,7 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
 
 
 KC_CASES = [((32, 16, 8), 1, 0), ((64, 12, 6), 1, 1), ((128, 20, 6), 1, 0), ((16, 16, 16), 2, 0),
-            ((16, 16, 16), 3, 1)]
+            ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((8, 4, 2), 1, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
