@@ -559,8 +559,11 @@ static void heat(run_t *R, int lvl, double dt) {
  * interfaces by the sum of the 4 fine faces and 2 sub-cycles.
  * Pinned by: uniform invariance (bitwise), mass accounting to round-off on a
  * single level, composite mass conservation across levels, linear sound
- * speed.  The momentum pairing and the matching of momentum and energy
- * transfers are a reading: parity unpinned beyond those checks. */
+ * speed, and the conservation of energy and of the three momenta (the sum of
+ * the cell momenta the stage builds against the one its rebuilt faces hold)
+ * by the transport stage on one level, to round-off.  The choice of the
+ * momentum pairing and the matching of momentum and energy transfers across
+ * levels are a reading: parity unpinned beyond those checks. */
 static void build_momenta(run_t *R, int lvl) {
   lev_t *L = &R->lev[lvl];
   const double *rho = L->st[S_RHO];
@@ -968,7 +971,10 @@ static double dt_rule(run_t *R) {
  * sum is taken over (rho - rho0) to avoid cancellation.  Neumaier-compensated
  * sums per k-plane, then over planes in order.
  * Pinned by: zero for uniform data, mirror-odd components vanish, cold drag
- * negative and proportional to GM^2 at small GM. */
+ * negative and proportional to GM^2 at small GM, Newton's shell theorem (a
+ * Gaussian over-density pulls as its mass at its centre: to round-off on one
+ * level, at second order in the cell size across a frontier, which fixes the
+ * covered cells) and the softened point mass of a single cell. */
 typedef struct { double s, c; } nsum_t;
 static inline void nadd(nsum_t *a, double x) {
   double t = a->s + x;
