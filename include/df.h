@@ -106,9 +106,16 @@ int df_bind(df_run *run, void *dev_ptr, size_t bytes, void *stream);
  * stream.  Requires df_bind(). */
 int df_set_perturber(df_run *run, double GM, double eps, double L, double mach, double chi);
 
-/* Advance n >= 0 coarse steps (each: time step from the Courant and diffusion
- * limits, then the recursive sub-cycled update of every level).  Enqueues
- * kernels on the bound stream and returns without synchronising. */
+/* Advance n >= 0 coarse steps (Sect. 3.1, time step scheduling; Sect. 3.3,
+ * the staging list of sub-cycles and communications): each step takes its
+ * length from the Courant and diffusion limits of every level, then runs the
+ * recursive sub-cycled update -- the finer level's two steps first, then the
+ * level's own step S(dt/2) T(dt) S(dt/2) of eq. 15 with the thermal sources
+ * in between, then CommUp and CommMean (Sect. 3.2) -- and logs the force of
+ * eq. 18.  Enqueues kernels on the bound stream and returns without
+ * synchronising; DF_ESTATE before df_bind and df_set_perturber, DF_EINVAL
+ * for n < 0.  Errors raised by the device surface at the next synchronising
+ * call. */
 int df_step(df_run *run, int32_t n);
 
 /* Force on the perturber (eq. 18, FP64): out[0..2] = Fx, Fy, Fz, out[3] = t.
@@ -123,12 +130,19 @@ int df_force(df_run *run, double out[4]);
 int df_force_log(df_run *run, double *out, int32_t cap, int32_t *count);
 
 /* Composite totals over uncovered active cells (FP64): out[0] mass,
- * out[1] internal energy, out[2] kinetic energy.  Synchronises. */
+ * out[1] internal energy, out[2] kinetic energy (face velocities averaged to
+ * the cell centres) -- the conserved quantities whose transfers the levels
+ * match at their frontiers (Sect. 3.2.3), each coarse cell covered by a
+ * finer level left out.  Synchronises; DF_ENUMERIC as df_force. */
 int df_totals(df_run *run, double out[3]);
 
-/* Copy a field of one level to / from host memory (FP64 values, x fastest).
- * Centred fields: nx*ny*nz entries.  Face fields: one more entry along their
- * own axis (DF_VX: (nx+1)*ny*nz, x fastest).  Synchronises.  After
+/* Copy a field of one level to / from host memory (FP64 values, x fastest):
+ * the density and internal energy of eqs. 1 and 3, centred in the cells, and
+ * the velocity components of eq. 2, staggered on the cell faces normal to
+ * them (the centred and staggered quantities of Sect. 3.2.1).  Centred
+ * fields: nx*ny*nz entries.  Face fields: one more entry along their own axis
+ * (DF_VX: (nx+1)*ny*nz, x fastest).  The host buffer belongs to the caller.
+ * Synchronises; DF_EINVAL for a bad level or field or a null buffer.  After
  * df_set_field, call df_sync_levels() before stepping a nested run. */
 int df_get_field(df_run *run, int32_t level, int32_t field, double *host);
 int df_set_field(df_run *run, int32_t level, int32_t field, const double *host);

@@ -8,6 +8,7 @@
 //             CommUp l -> l+1 ; CommMean l+1 -> l
 // Every launch goes to the caller's stream; nothing in df_step waits on the
 // device, so a sequence of steps can be captured into a HIP graph.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -1247,6 +1248,11 @@ int df_engine_release(df_engine *E, int32_t slot) {
   if (rc) return rc;
   rc = engine_quiesce(E, J);
   if (rc) return rc;
+  // a job released before a poll reported it must not be reported later: by
+  // then its slot may hold a newly admitted job
+  for (auto &p : E->pending) p.slots.erase(std::remove(p.slots.begin(), p.slots.end(), slot), p.slots.end());
+  E->finished.erase(std::remove(E->finished.begin(), E->finished.end(), slot), E->finished.end());
+  if (J->active) E->dirty = true;  // the graph holds its launches
   arena_give(E, J->off, J->len);
   delete J->run;
   *J = EngineJob();
