@@ -47,6 +47,8 @@ ALG_BYTES = {
     "force": 0,
 }
 POST_BYTES = 8 * 5  # the separate end-of-step pass of nested runs: read rho, e, vx, vy, vz
+# the method's own minimum per cell-update: read and write rho, e, vx, vy, vz once (FP64)
+METHOD_BYTES_FP64 = 8 * (5 + 5)
 
 
 def workload():
@@ -78,10 +80,35 @@ def traffic_from_profiles(kernel: str):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def step_traffic_from_profiles():
+    """HBM bytes of one whole single-level step (every kernel kind once) from
+    the committed counter summary, if taken on the current kernel source"""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic_config2.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != dfk_hash():
+        return None
+    return sum(k["bytes_per_launch"] for k in d.get("kernels", {}).values())
+
+
+def host_threads():
+    """threads the oracle may use on this host: the CPUs this process may run
+    on, capped by OMP_NUM_THREADS when it is set (the host's share of cores)"""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    return (min(avail, cap) if cap > 0 else avail), avail
+
+
 def cpu_baseline(cfg, budget_s=12.0):
     """the FP64 oracle on the host: a bounded number of coarse steps of the
     same 128^3 workload, with all OpenMP threads and with one thread"""
-    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or min(16, os.cpu_count() or 1)
+    nthreads, avail = host_threads()
+    omp_env = os.environ.get("OMP_NUM_THREADS")
     from oracle.oracle import Oracle
 
     cells = cfg["nx"] * cfg["ny"] * cfg["nz"]
@@ -106,7 +133,10 @@ def cpu_baseline(cfg, budget_s=12.0):
             "sample": f"128^3 single level FP64, {n} coarse steps after one untimed step "
                       f"({el:.1f} s, OpenMP threads={nthreads})",
             "value_1thread": v1,
-            "sample_1thread": f"{n1} coarse steps after one untimed step ({el1:.1f} s, 1 thread)"}
+            "sample_1thread": f"{n1} coarse steps after one untimed step ({el1:.1f} s, 1 thread)",
+            "host": {"nproc": os.cpu_count(), "cpus_allowed": avail,
+                     "omp_num_threads": omp_env,
+                     "build": "gcc -O3 -march=x86-64-v3 -ffp-contract=off -fopenmp"}}
 
 
 def fp32_single(cfg, K, W):
@@ -135,6 +165,7 @@ def nested(steps=None, warm=2):
     steps, seed 3) in FP64 and with FP32 departures: cell-updates/s over all
     levels (level l advances 2^l sub-steps per coarse step) and the FP32
     force error against the FP64 run"""
+    import numpy as np
     import torch
 
     import paper_1812_03191_amd as dfm
@@ -164,6 +195,24 @@ def nested(steps=None, warm=2):
     f64, f32 = forces["fp64"], forces["fp32"]
     out["fp32_force_rel_err_vs_fp64"] = float(abs(f32[0] - f64[0]) / abs(f64[0]))
     out["cell_updates_per_coarse_step"] = cells
+    # against the FP64 oracle at reduced size: the same nesting with 32^3 levels, 20 coarse steps
+    from oracle.oracle import Oracle
+
+    small, Ks = inputs.config3(n=32)[0], 20
+    c = small
+    o = Oracle(c["nx"], c["ny"], c["nz"], nlevels=c["nlevels"], dx0=c["dx0"], gamma=c["gamma"], cfl=c["cfl"],
+               seed=c["seed"], noise_amp=c["noise_amp"], GM=c["GM"], eps=c["eps"], L=c["L"], mach=c["mach"],
+               chi=c["chi"], threads=host_threads()[0])
+    o.step(Ks)
+    fo = o.force()
+    rel = {}
+    for name, prec in (("fp64", dfm.DF_FP64), ("fp32", dfm.DF_FP32)):
+        run = dfm.Run(c["nx"], c["ny"], c["nz"], nlevels=c["nlevels"], dx0=c["dx0"], seed=c["seed"],
+                      noise_amp=c["noise_amp"], precision=prec)
+        run.set_perturber(c["GM"], c["eps"], c["L"], c["mach"], c["chi"])
+        run.step(Ks)
+        rel[name] = float(np.max(np.abs(run.force()[:3] - fo)) / np.linalg.norm(fo))
+    out["force_rel_err_vs_oracle_4x32cube_20_steps"] = rel
     return out
 
 
@@ -209,6 +258,28 @@ def batched_sweep(warm=2):
         del eng
     rel = np.abs(forces["fp32"] - forces["fp64"]) / np.abs(forces["fp64"])
     res["fp32"]["force_rel_err_vs_fp64"] = {"max": float(rel.max()), "median": float(np.median(rel))}
+    # against the FP64 oracle: one job per mesh size (a stratified subset)
+    from oracle.oracle import Oracle
+
+    sub, seen = [], set()
+    for j, c in enumerate(jobs):
+        if c["nx"] not in seen:
+            seen.add(c["nx"])
+            sub.append(j)
+    errs = {"fp32": [], "fp64": []}
+    for j in sub:
+        c = jobs[j]
+        o = Oracle(c["nx"], c["ny"], c["nz"], nlevels=1, dx0=c["dx0"], gamma=c["gamma"], cfl=c["cfl"],
+                   seed=c["seed"], noise_amp=c["noise_amp"], GM=c["GM"], eps=c["eps"], L=c["L"], mach=c["mach"],
+                   chi=c["chi"], threads=host_threads()[0])
+        o.step(steps + 2 * warm)
+        fo = o.force()[0]
+        for name in errs:
+            errs[name].append(abs(forces[name][j] - fo) / abs(fo))
+    for name in errs:
+        res[name]["force_rel_err_vs_oracle"] = {
+            "jobs": [f"{jobs[j]['nx']}^3 Mach {jobs[j]['mach']:.3f}" for j in sub],
+            "max": float(max(errs[name])), "per_job": [float(x) for x in errs[name]]}
     return res
 
 
@@ -339,7 +410,7 @@ def main():
                     help="extra legs to run: any of fp32, batched, nested (comma separated)")
     ap.add_argument("--precision", choices=("fp64", "fp32"), default="fp64",
                     help="storage of the timed 128^3 run (fp64 is the headline line; fp32 for profiling)")
-    ap.add_argument("--serve-jobs", type=int, default=100,
+    ap.add_argument("--serve-jobs", type=int, default=400,
                     help="jobs of the served workload to run (400 is the whole stream; 0 skips)")
     ap.add_argument("--separate-launches", action="store_true",
                     help="time the 128^3 run with every stage a launch of its own (no kernel fusion)")
@@ -401,20 +472,33 @@ def main():
         kern = dfm.timing_read(run.handle)
         dfm.timing_enable(run.handle, 0)
         busy = {k: v for k, v in kern.items() if v[1] > 0 and ALG_BYTES.get(k, 0) > 0}
-        dom = max(busy, key=lambda k: busy[k][0])
+        # the dominant kernel: the longest launch of a step
+        dom = max(busy, key=lambda k: busy[k][0] / busy[k][1])
         avg_ms = busy[dom][0] / busy[dom][1]
-        per_launch = ALG_BYTES[dom] * cells * esz // 8
+        # the method's algorithmic bytes per cell-update (read and write the
+        # five state fields once: 80 B in FP64, 40 B in FP32) times the active
+        # cells one launch advances
+        per_launch = METHOD_BYTES_FP64 * cells * esz // 8
         achieved = per_launch / (avg_ms / 1e3) / 1e9
+        traffic = None if fp32 else traffic_from_profiles(dom)
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if fp32 else traffic_from_profiles(dom), "avg_launch_us": round(avg_ms * 1e3, 2),
-                "alg_bytes_per_launch": per_launch}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "alg_bytes_per_launch": per_launch,
+                "alg_bytes_basis": f"{METHOD_BYTES_FP64 * esz // 8} B per cell-update x {cells} cells"}
         att = attainable_bandwidth()
         roof["attainable"] = round(att, 1)
         roof["frac_of_attainable"] = round(achieved / att, 4)
-        if roof["traffic"]:
+        # the kernel's own fields read and written once each, over its duration
+        own = ALG_BYTES[dom] * cells * esz // 8
+        roof["kernel_alg_frac"] = round(own / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        if traffic:
             # measured DRAM bytes of the same kernel over its duration
-            roof["traffic_frac"] = round(roof["traffic"] / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            roof["traffic_frac"] = round(traffic / (avg_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+            roof["traffic_over_alg"] = round(traffic / per_launch, 3)
+        step_traffic = None if fp32 else step_traffic_from_profiles()
+        if step_traffic:
+            roof["step_traffic_bytes"] = step_traffic
+            roof["step_traffic_over_alg"] = round(step_traffic / per_launch, 3)
         # every kind's algorithmic bandwidth and its fraction of the HBM peak
         kern = {k: {"ms_total": round(v[0], 3), "launches": v[1],
                     "avg_us": round(1e3 * v[0] / v[1], 2) if v[1] else None,
@@ -455,7 +539,8 @@ def main():
         "cpu_baseline": cpu,
         "force": {"Fx": F[0], "Fy": F[1], "Fz": F[2], "t": F[3]},
         "kernels": kern,
-        # the method's own minimum: read and write the 5 state fields once per cell-update
+        # the whole step against the method's own minimum (read and write the 5
+        # state fields once per cell-update) at the HBM peak
         "alg_efficiency": round(10.0 * esz * value / (HBM_PEAK_GBS * 1e9), 4),
     }
     out.update(extra)

@@ -192,3 +192,71 @@ def test_batched_sweep_subset_against_oracle(dfm):
             got = eng.force(s)[0]
             _say(f"[engine] n={c['nx']} mach={c['mach']:.3f} prec={prec} rel err {abs(got - w) / abs(w):.2e}")
             assert abs(got - w) <= tol * abs(w), (c["nx"], prec, got, w)
+
+
+def test_release_before_poll_is_never_reported(dfm):
+    # a job that finished on the device and is released before any poll
+    # reported it must not be reported later, when its slot holds a new job
+    import torch
+
+    eng = dfm.Engine(1 << 30)
+    a = eng.admit(inputs.job(16, 1, 0.5, 0.01, 0.1, 0.0, seed=14), 2, precision=1)
+    eng.step(1)
+    torch.cuda.synchronize()
+    eng.release(a)
+    b = eng.admit(inputs.job(16, 1, 0.5, 0.01, 0.1, 0.0, seed=15), 4, precision=1)
+    assert b == a  # the lowest free slot is reused
+    assert eng.poll() == []
+    eng.step(2)
+    got = _wait_done(eng, [b])
+    assert got == {b}
+    assert eng.poll() == []
+    ref = _eager(dfm, inputs.job(16, 1, 0.5, 0.01, 0.1, 0.0, seed=15), 4, 1)
+    assert np.array_equal(eng.force(b), ref.force())
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_engine_jobs_at_other_segment_lengths(dfm, precision):
+    # jobs admitted with the column-segment lengths the autotuner chooses run
+    # in one engine and give bitwise the eager run at the same length
+    cases = [(inputs.job(48, 1, 1.2, 0.01, 0.1, 1e-3, seed=46), 8),
+             (inputs.job(32, 2, 0.4, 2e-3, 0.1, 1e-3, seed=47), 64),
+             (inputs.job(64, 1, 2.5, 0.01, 0.1, 0.0, seed=48), 16)]
+    steps = 6
+    _say(f"[engine] segment lengths 8, 64, 16, precision {precision}")
+    eng = dfm.Engine(2 << 30)
+    slots = [eng.admit(c, steps, precision=precision, tile_chunk=ch) for c, ch in cases]
+    eng.step(steps // 2)
+    assert set(_wait_done(eng, slots)) >= set(slots)
+    for (c, ch), s in zip(cases, slots):
+        ref = _eager(dfm, c, steps, precision, chunk=ch)
+        for lev in range(c["nlevels"]):
+            for name in FIELDS:
+                assert np.array_equal(eng.field(s, lev, name, _shape(c, name)), ref.field(lev, name)), (ch, name)
+        assert np.array_equal(eng.force(s), ref.force()), ch
+
+
+def test_serve_results_equal_jobs_run_alone(dfm):
+    # a small stream through the continuous-batching loop under a budget that
+    # holds only some of the jobs at once: every job's force is bitwise that of
+    # the same job run alone
+    from paper_1812_03191_amd.serve import serve
+
+    rng = np.random.default_rng(51)
+    jobs = []
+    for j in range(7):
+        n = int(rng.choice([16, 24, 32]))
+        nl = int(rng.integers(1, 3)) if n % 16 == 0 else 1
+        mach = float(np.exp(rng.uniform(np.log(0.2), np.log(2.5))))
+        jobs.append(inputs.job(n, nl, mach, 0.01, 0.1, 1e-3, seed=5100 + j))
+    arrivals = np.cumsum(rng.exponential(0.02, size=len(jobs)))
+    steps = 10
+    need = max(dfm.engine_job_bytes(c, dfm.DF_FP32) for c in jobs)
+    budget = int(2.2 * need)
+    _say(f"[serve] {len(jobs)} jobs, budget {budget / 2**20:.1f} MiB")
+    r = serve(arrivals, jobs, steps, budget_bytes=budget, precision=dfm.DF_FP32, tune=False)
+    assert r["max_active"] < len(jobs)  # admission was bound by the budget
+    assert r["p99_latency_s"] >= r["p50_latency_s"] > 0.0
+    for j, c in enumerate(jobs):
+        ref = _eager(dfm, c, steps, dfm.DF_FP32)
+        assert np.array_equal(r["forces"][j], ref.force()), j

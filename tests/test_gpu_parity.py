@@ -156,7 +156,7 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
 
 
 KC_CASES = [((32, 16, 8), 1, 0), ((64, 12, 6), 1, 1), ((128, 20, 6), 1, 0), ((16, 16, 16), 2, 0),
-            ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((8, 4, 2), 1, 1)]
+            ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((16, 2, 4), 1, 1), ((8, 4, 2), 1, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -550,6 +550,7 @@ def test_fp32_config1_force_error(dfm):
     _say(f"[fp32] config1 errors {rep}")
     assert rep["force_rel"] < 1e-4, rep
     assert rep["mass_rel"] < 1e-7, rep
+    assert rep["eint_rel"] < 1e-6 and rep["ekin_rel"] < 1e-6, rep
 
 
 def test_fp32_nested_force_error(dfm):
@@ -561,3 +562,4 @@ def test_fp32_nested_force_error(dfm):
     rep = _fp32_report(o, g, 3)
     _say(f"[fp32] nested errors {rep}")
     assert rep["force_rel"] < 1e-4, rep
+    assert rep["mass_rel"] < 1e-6 and rep["eint_rel"] < 1e-6 and rep["ekin_rel"] < 1e-6, rep
