@@ -302,6 +302,27 @@ int df_engine_destroy(df_engine *eng);
  * attainable HBM bandwidth the kernels' rooflines are set beside. */
 int df_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the force on
+ * the perturber of one level's density field, as df_force computes it for a
+ * single-level run, with no arena, no handle and no allocation.
+ *  rho    : device pointer, nx*ny*nz total densities (FP64, x fastest, no
+ *           padding), read only; the perturber sits at the central vertex and
+ *           cell (i,j,k) is centred at ((i - nx/2 + 1/2) dx, ...);
+ *  nx, ny, nz : even, >= 2, at most DF_FORCE_DENSITY_MAX_CELLS cells;
+ *  dx > 0, GM >= 0, eps >= 0 (Plummer length), rho0 the background density;
+ *  out    : device pointer to 3 doubles, receives (Fx, Fy, Fz);
+ *  stream : hipStream_t (or NULL); asynchronous, launches two kernels.
+ * The per-block partials live in a 96 KiB device array of the library, one
+ * per GPU, held until the process ends: calls that overlap on one GPU (two
+ * streams, or two host threads) race on it and must be serialised.  No step
+ * allocates or synchronises, so the call can be captured into a HIP graph.
+ * DF_EINVAL for bad sizes or parameters or null pointers, DF_EDEVICE when the
+ * array's device address cannot be obtained or a launch fails. */
+#define DF_FORCE_DENSITY_MAX_CELLS (1L << 31)
+int df_force_density(const double *rho, int32_t nx, int32_t ny, int32_t nz, double dx, double GM, double eps,
+                     double rho0, double *out, void *stream);
+
 const char *df_strerror(int code);
 const char *df_last_error(void);
 

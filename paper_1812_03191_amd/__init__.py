@@ -7,7 +7,7 @@ fallback: importing this package without the built library raises.
 """
 from ._lib import (  # noqa: F401
     DF_FP32, DF_FP64, FIELDS, KERNEL_KINDS, DFError, Engine, Run, bind, debug_stage, destroy,
-    engine_job_bytes, force,
+    engine_job_bytes, force, force_density,
     force_log, get_dt, get_field, init_mesh, lib_path, required_bytes, set_field, set_perturber,
     step, stream_copy, sync_levels, timing_enable, timing_read, totals,
 )

@@ -76,6 +76,7 @@ def _load():
         "df_set_kick_fusion": [vp, i32],
         "df_set_viscosity": [vp, ctypes.c_double],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
+        "df_force_density": [vp, i32, i32, i32] + [ctypes.c_double] * 4 + [vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -205,6 +206,26 @@ def stream_copy(dst, src, stream=None) -> None:
         raise ValueError("sizes differ")
     st = stream if stream is not None else torch.cuda.current_stream()
     _ck(_load().df_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, st.cuda_stream))
+
+
+def force_density(rho, dx, GM, eps, rho0=1.0, out=None, stream=None):
+    """eq. 18 over one level's density field with no device allocation
+    (df_force_density): rho a contiguous float64 CUDA tensor of shape
+    (nz, ny, nx); out a float64 CUDA tensor of 3 entries (made if None);
+    asynchronous on `stream` (default: the current).  Returns out."""
+    import torch
+
+    if rho.dtype != torch.float64 or not rho.is_cuda or not rho.is_contiguous() or rho.dim() != 3:
+        raise ValueError("rho must be a contiguous 3-D float64 CUDA tensor")
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=rho.device)
+    if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 3:
+        raise ValueError("out must be a float64 CUDA tensor of 3 entries")
+    st = stream if stream is not None else torch.cuda.current_stream(rho.device)
+    nz, ny, nx = rho.shape
+    _ck(_load().df_force_density(rho.data_ptr(), nx, ny, nz, float(dx), float(GM), float(eps), float(rho0),
+                                 out.data_ptr(), st.cuda_stream))
+    return out
 
 
 # ------------------------------------------------------------------ Run

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("dfk.hip", "api.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("dfk.hip", "api.hip", "force_noalloc.hip")]
 LIB = os.path.join(HERE, "libdfmesh.so")
 
 HIPCC_FLAGS = [

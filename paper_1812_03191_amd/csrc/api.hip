@@ -47,6 +47,8 @@ inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 }  // namespace
 
+int df_fail_internal(int code, const char *msg) { return fail(code, msg); }
+
 struct df_run {
   df_mesh_desc desc{};
   int nl = 0;

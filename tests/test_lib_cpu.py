@@ -98,3 +98,24 @@ def test_launch_switches_need_a_bound_run():
         assert fn(h, 1) == -2
         assert fn(None, 1) == -1
     dfm.destroy(h)
+
+
+def test_force_density_validates_before_any_device_call():
+    # argument checks come first: no GPU is touched for a rejected call
+    import paper_1812_03191_amd as dfm
+    from paper_1812_03191_amd import _lib
+
+    lib = _lib._load()
+    out = ctypes.c_void_p(16)  # never dereferenced: every call below is rejected
+    rho = ctypes.c_void_p(16)
+    assert lib.df_force_density(None, 8, 8, 8, 0.1, 0.01, 0.0, 1.0, out, None) == -1
+    assert lib.df_force_density(rho, 8, 8, 8, 0.1, 0.01, 0.0, 1.0, None, None) == -1
+    assert lib.df_force_density(rho, 7, 8, 8, 0.1, 0.01, 0.0, 1.0, out, None) == -1
+    assert lib.df_force_density(rho, 8, 8, 0, 0.1, 0.01, 0.0, 1.0, out, None) == -1
+    assert lib.df_force_density(rho, 8, 8, 8, 0.0, 0.01, 0.0, 1.0, out, None) == -1
+    assert lib.df_force_density(rho, 8, 8, 8, 0.1, -1.0, 0.0, 1.0, out, None) == -1
+    assert lib.df_force_density(rho, 8, 8, 8, 0.1, 0.01, float("nan"), 1.0, out, None) == -1
+    big = 2048  # 2^33 cells: above the stated maximum
+    assert lib.df_force_density(rho, big, big, big, 0.1, 0.01, 0.0, 1.0, out, None) == -1
+    assert "MAX_CELLS" in lib.df_last_error().decode()
+    assert dfm.DFError
