@@ -42,6 +42,8 @@ ALG_BYTES = {
     "pass_z": 8 * (9 + 8),        # read 8 transported + vz; write 8
     "pass_xy": 8 * (5 + 8),       # fused x and y: read rho, e, vx, vy, vz; write the 8 transported
     "rebuild_kick": 8 * (8 + 3),  # read 8 transported; write vx, vy, vz
+    # z pass fused with the rebuild and kick: read 8 transported + vz; write rho, e, vx, vy, vz
+    "pass_z_finish": 8 * (9 + 5),
     # single level: the one-block kernel that sums the partials (the rebuild
     # kick forms them from the fields it already reads)
     "force": 0,
@@ -345,7 +347,7 @@ PMC_KINDS = ((("k_kick0p<", ", false, true, false, false>"), "kick"), (("k_kick<
              (("k_xrow<",), "pass_x"), (("k_xpass<",), "pass_x"),
              (("k_march<double, 1,",), "pass_y"), (("k_march<float, 1,",), "pass_y"),
              (("k_march<double, 2,",), "pass_z"), (("k_march<float, 2,",), "pass_z"),
-             (("k_xyshared<",), "pass_xy"),
+             (("k_xyshared<",), "pass_xy"), (("k_zfinish<",), "pass_z_finish"),
              (("k_step_final",), "force"), (("k_post<",), "post"))
 
 
@@ -446,6 +448,7 @@ def main():
     if args.separate_launches:
         run.set_kick_fusion(False)
         run.set_transport_fusion(False)
+        run.set_finish_fusion(False)
     stream = run.stream
     print(f"[bench] 128^3 {args.precision.upper()}: warmup {W}, timed {K}", file=sys.stderr, flush=True)
     run.step(W)

@@ -198,6 +198,20 @@ int df_set_transport_fusion(df_run *run, int32_t on);
  * values. */
 int df_set_kick_fusion(df_run *run, int32_t on);
 
+/* Launch shape of the end of a single-level step (the z pass of T, the
+ * velocity rebuild after it and the second velocity source S(dt/2) of eq. 15,
+ * with the force of eq. 18 and the next step's signal speeds): on (1,
+ * default) one launch when the level has at most 128 cells along x, an even
+ * count of rows and the default boundaries, and the first kick is fused with
+ * the compression (df_set_kick_fusion, so that the z pass reads that kick's
+ * own copy of the face velocities) -- the z pass's results go from
+ * the waves that compute them to the waves that rebuild and kick the face
+ * velocities through LDS, one plane at a time, so the eight transported
+ * fields never reach device memory; off (0): the z pass and the rebuild and
+ * kick are launches of their own.  The results agree to rounding either way;
+ * DF_EINVAL for other values. */
+int df_set_finish_fusion(df_run *run, int32_t on);
+
 /* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
  * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
  * every other boundary is zero-gradient outflow.  mode 1: the paper's list,
@@ -233,11 +247,13 @@ int df_debug_stage(df_run *run, int32_t stage, double dt);
  * next time step; DF_K_DT is the time step before the first step of a df_step
  * call (with a signal pass if the state was changed by other calls);
  * DF_K_PASSXY the fused x and y transport passes (df_set_transport_fusion),
- * DF_K_KICKCOMP the fused first kick and compression (df_set_kick_fusion). */
+ * DF_K_KICKCOMP the fused first kick and compression (df_set_kick_fusion),
+ * DF_K_ZFINISH the z pass fused with the rebuild and kick
+ * (df_set_finish_fusion). */
 enum {
   DF_K_KICK = 0, DF_K_COMPRESS, DF_K_DIFFUSE, DF_K_PASSX, DF_K_PASSY, DF_K_PASSZ, DF_K_REBUILD,
   DF_K_COMMUP, DF_K_COMMMEAN, DF_K_DT, DF_K_FORCE, DF_K_ZERO, DF_K_VISC, DF_K_PASSXY, DF_K_KICKCOMP,
-  DF_K_NKINDS
+  DF_K_ZFINISH, DF_K_NKINDS
 };
 int df_timing_enable(df_run *run, int32_t max_launches);
 int df_timing_read(df_run *run, double *ms, int32_t *count, int32_t nkinds);

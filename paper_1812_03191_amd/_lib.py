@@ -74,6 +74,7 @@ def _load():
         "df_set_boundaries": [vp, i32],
         "df_set_transport_fusion": [vp, i32],
         "df_set_kick_fusion": [vp, i32],
+        "df_set_finish_fusion": [vp, i32],
         "df_set_viscosity": [vp, ctypes.c_double],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
         "df_force_density": [vp, i32, i32, i32] + [ctypes.c_double] * 4 + [vp, vp],
@@ -181,7 +182,8 @@ def force_log(h, cap: int = 4096) -> np.ndarray:
 
 
 KERNEL_KINDS = ("kick", "compress", "diffuse_heat", "pass_x", "pass_y", "pass_z", "rebuild_kick",
-                "commup", "commmean", "dt", "force", "zero", "viscosity", "pass_xy", "kick_compress")
+                "commup", "commmean", "dt", "force", "zero", "viscosity", "pass_xy", "kick_compress",
+                "pass_z_finish")
 
 
 def timing_enable(h, max_launches: int) -> None:
@@ -297,6 +299,10 @@ class Run:
     def set_kick_fusion(self, on: bool) -> None:
         """kick and compress level 0 in one launch where it qualifies (default on)"""
         _ck(_load().df_set_kick_fusion(self._h, int(bool(on))))
+
+    def set_finish_fusion(self, on: bool) -> None:
+        """fuse a single-level step's z pass with the rebuild and kick where it qualifies (default on)"""
+        _ck(_load().df_set_finish_fusion(self._h, int(bool(on))))
 
     def schedule(self) -> list:
         """sub-steps of level l+1 per step of level l in the last coarse step"""

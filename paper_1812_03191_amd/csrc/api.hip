@@ -72,6 +72,7 @@ struct df_run {
   bool sig_valid = false;  // the signal-speed partials are those of the current state
   bool fuse_xy = true;     // fuse the x and y passes where transport_xy applies
   bool fuse_kc = true;     // fuse the first kick and the compression of level 0 (viscosity off)
+  bool fuse_zf = true;     // fuse the z pass with the rebuild, the kick and the end-of-step partials (single level)
   bool slot_mode = false;  // single level: the kicks take the step length from the signal-speed slots
   int subcycle = 0;        // 0: two sub-steps per level; 1: criterion of App. A
   double visc = 0.0;       // artificial-viscosity coefficient (kept across df_set_perturber)
@@ -153,7 +154,8 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
 // ---------------------------------------------------------------- timing
 // Kernel kinds timed by df_timing_read (the order of the DF_K_* list in df.h).
 enum { K_KICK = 0, K_COMPRESS, K_DIFFUSE, K_PASSX, K_PASSY, K_PASSZ, K_REBUILD, K_COMMUP, K_COMMMEAN,
-       K_DT, K_FORCE, K_ZERO, K_VISC, K_PASSXY, K_KICKCOMP, K_NKINDS };
+       K_DT, K_FORCE, K_ZERO, K_VISC, K_PASSXY, K_KICKCOMP, K_ZFINISH, K_NKINDS };
+static_assert(K_NKINDS == DF_K_NKINDS, "timing kinds follow the DF_K_* list");
 
 struct TScope {
   df_run *R;
@@ -220,10 +222,20 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   // the z pass and the rebuild take the set the y pass wrote (q[c] after
   // separate passes, q[1-c] after the fused ones)
   const int cy = fused ? 1 - c : c;
-  { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
   // a single-level step ends here: the same launch forms the force and the
-  // next step's signal-speed partials
-  { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, R->nl == 1 ? R->scal : nullptr); }
+  // next step's signal-speed partials; on level 0 without a finer level the z
+  // pass joins them (only the new density, energy and face velocities are
+  // written)
+  Scal *post = R->nl == 1 ? R->scal : nullptr;
+  bool zf = false;
+  if (R->fuse_zf && post && dfk::transport_z_finish_fits(G)) {
+    TScope t(R, K_ZFINISH);
+    zf = dfk::transport_z_finish(st, G, P, B, Bt.v, cy, dtp, scale, 0.5 * scale, post, R->chunk);
+  }
+  if (!zf) {
+    { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, post); }
+  }
   R->cur[l] = 1 - cy;
 }
 
@@ -598,6 +610,14 @@ int df_set_kick_fusion(df_run *R, int32_t on) {
   if (rc) return rc;
   if (on != 0 && on != 1) return fail(DF_EINVAL, "kick fusion must be 0 or 1");
   R->fuse_kc = on == 1;
+  return DF_OK;
+}
+
+int df_set_finish_fusion(df_run *R, int32_t on) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (on != 0 && on != 1) return fail(DF_EINVAL, "finish fusion must be 0 or 1");
+  R->fuse_zf = on == 1;
   return DF_OK;
 }
 

@@ -124,6 +124,16 @@ void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBuf
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
                   double fac, int chunk);
 bool transport_xy_fits(const Geo &G);
+// the z pass q[src] -> q[1-src] (face velocities vin[2]) fused with the
+// velocity rebuild, the kick (fac kfac) into B.v and the end-of-step partials
+// of post_partials (as rebuild_kick with post S) on level 0 without a finer
+// level (bc 1, at most 128 cells along x, an even row count); only the new
+// density and energy of q[1-src] are written.  false, launching nothing, when
+// the level does not qualify, S is null or vin[2] is B.v[2] (the walk reads
+// the face velocities the finish writes)
+bool transport_z_finish(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, void *const *vin, int src,
+                        const double *dtp, double fac, double kfac, Scal *S, int chunk);
+bool transport_z_finish_fits(const Geo &G);
 void zero(hipStream_t st, void *p, size_t bytes);
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf,
             LevBufs &Bf, int curf);

@@ -1118,10 +1118,13 @@ struct MarchArgs {
 // P-z, P+z}, or four groups {e}, {P-x, P+x}, {P-y, P+y}, {P-z, P+z}.  Every
 // group also transports the density (its mass transfers carry the others);
 // the first one stores it.
+// NG = 3 is the one group {e, P+y} of the neighbour row a fused z finish
+// walks for the y faces of its first row.
 constexpr int group_q(int NG, int GRP, int u) {
-  return NG == 2 ? (GRP ? 4 + u : (u < 3 ? 1 + u : 1)) : (GRP == 0 ? 1 : (u < 2 ? 2 * GRP + u : 1));
+  return NG == 2 ? (GRP ? 4 + u : (u < 3 ? 1 + u : 1))
+                 : (NG == 3 ? (u == 1 ? 5 : 1) : (GRP == 0 ? 1 : (u < 2 ? 2 * GRP + u : 1)));
 }
-constexpr int group_n(int NG, int GRP) { return NG == 2 ? (GRP ? 4 : 3) : (GRP ? 2 : 1); }
+constexpr int group_n(int NG, int GRP) { return NG == 2 ? (GRP ? 4 : 3) : (NG == 3 ? 2 : (GRP ? 2 : 1)); }
 
 // Rows of a column read from the transported set (the y and z passes): the
 // raw departures of row c (w[0] the density, w[1..] the group's quantities)
@@ -1165,9 +1168,9 @@ struct ColSrc {
 // use; lanes that are not live (past the row end) neither read nor write.
 // FRONT: the level has frontier transfers (a finer level's sums to take, or
 // its own to accumulate); without them the solver's transfers stand.
-template <typename T, int DIR, int BC, int GRP, bool FRONT, int W, int NG, typename Src>
+template <typename T, int DIR, int BC, int GRP, bool FRONT, int W, int NG, typename Src, typename Sink>
 __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
-                                             int i, int t, int c0, int c1, Src &src, bool live) {
+                                             int i, int t, int c0, int c1, Src &src, Sink &snk, bool live) {
   static_assert(W == 1 || !FRONT, "frontier transfers are per column");
   using V = typename lanes_of<T, W>::type;  // the W adjacent columns of a lane
   constexpr int TD = (DIR == 1) ? 2 : 1;
@@ -1196,12 +1199,10 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   constexpr bool zq[4] = {mq[0] >= 4, mq[1] >= 4, mq[2] >= 4, mq[3] >= 4};
   constexpr bool wind = DIR == 0;
   T q0[4], sb[4];
-  T *qout[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     q0[u] = (T)qback(P, mq[u]);
     sb[u] = (T)sback(P, mq[u]);
-    qout[u] = A.qo[mq[u]];
   }
 
   const int tv1 = id3[T1], tv2 = id3[T2];
@@ -1320,8 +1321,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       } else {
         F1 = fix(c + 1, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
       }
-      T *qo = (u == 0) ? A.qo[0] : qout[u - 1];
-      if ((u > 0 || GRP == 0) && live) gstv<V>(qo, ic, w0[u] - (F1 - F0[u]) * ivol);
+      snk.put(u, ic, w0[u] - (F1 - F0[u]) * ivol);
       F0[u] = F1;
       d0[u] = d1;
       s0[u] = s1[u];
@@ -1334,8 +1334,27 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       w2[u] = nn[u];
     }
     va = vn;
+    snk.done(c);
   }
 }
+
+// The usual sink of a column walk: cell c's new departures of the group's
+// quantities (u = 1..) and, for the first group, of the density (u = 0) go to
+// the output set.
+template <typename T, typename V, int GRP, int NG>
+struct OutSink {
+  T *q[5];
+  bool live;
+  __device__ __forceinline__ OutSink(const MarchArgs<T> &A, bool lv) : live(lv) {
+    q[0] = A.qo[0];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) q[u + 1] = A.qo[group_q(NG, GRP, u)];
+  }
+  __device__ __forceinline__ void put(int u, idx_t ic, V val) {
+    if ((u > 0 || GRP == 0) && live) gstv<V>(q[u], ic, val);
+  }
+  __device__ __forceinline__ void done(int) {}
+};
 
 template <typename T, int DIR, int BC, bool FRONT, int W>
 __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
@@ -1366,10 +1385,12 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   const idx_t base = lin(G, id3[0], id3[1], id3[2]);
   if (grp) {
     ColSrc<T, V, DIR, BC, 1, 2> src{A.qi[0], {A.qi[4], A.qi[5], A.qi[6], A.qi[7]}, base, dstride(G, DIR), G.n[DIR]};
-    march_column<T, DIR, BC, 1, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, true);
+    OutSink<T, V, 1, 2> snk(A, true);
+    march_column<T, DIR, BC, 1, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, snk, true);
   } else {
     ColSrc<T, V, DIR, BC, 0, 2> src{A.qi[0], {A.qi[1], A.qi[2], A.qi[3], A.qi[1]}, base, dstride(G, DIR), G.n[DIR]};
-    march_column<T, DIR, BC, 0, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, true);
+    OutSink<T, V, 0, 2> snk(A, true);
+    march_column<T, DIR, BC, 0, FRONT, W, 2>(G, P, A, i, t, c0, c1, src, snk, true);
   }
 }
 
@@ -2402,6 +2423,312 @@ k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
   }
 }
 
+// ------------------------------------------ z pass fused with the step's end
+//
+// The z pass of a level-0 step without a finer level (bc 1, rows of at most
+// 128 cells), the velocity rebuild, the second half kick S(dt/2) of eq. 15
+// and the end-of-step reductions in one launch.  One block per (band of ZF_TY
+// rows, z segment), 3 ZF_TY + 1 waves, each lane holding two adjacent cells of
+// a row:
+//  - per band row two walker waves stream the z pass's column segments
+//    (march_column, groups {rho, e, P-x, P+x} and {P-y, P+y, P-z, P+z}), and
+//    one more walker takes the row below the band ({rho, e, P+y}: the first
+//    row's y faces need that row's new values);
+//  - per band row one finisher wave takes each plane's new departures from
+//    LDS and does what k_kick0p's end-of-step form does: rebuilds the face
+//    velocities of its cells' low faces (and of the boundary faces after the
+//    last cells), kicks them, forms the signal speeds and the force partials.
+// Walkers write plane k into one of two LDS buffers and a barrier hands it
+// over: the finishers work on plane k while the walkers compute plane k+1.
+// The walk starts one plane below the segment, so that the segment's first
+// z faces have their lower cells.  Only the new density and energy (written
+// by the first group's walkers) and the face velocities reach HBM; the eight
+// transported fields of the z pass never do.
+constexpr int ZF_TY = 2;
+constexpr int ZF_WAVES = 3 * ZF_TY + 1;
+
+// LDS planes: [2 buffers][ZF_TY + 1 row slots (slot 0: the row below the
+// band)][NQ quantities][2 * 64 cells]
+template <typename T>
+struct ZfLds {
+  T *base;
+  __device__ __forceinline__ T *at(int buf, int r, int m) const {
+    return base + ((buf * (ZF_TY + 1) + r) * NQ + m) * 128;
+  }
+};
+
+// A walker's sink: the plane's new departures into its row slot of the
+// current buffer, the density and energy of a band row (OUT) also to the
+// output set -- for the segment's own planes only: the plane below it
+// belongs to the segment below, whose block writes it (its value there may
+// differ in the last bit, its first face transfer being formed by the walk's
+// first step rather than its loop); done() hands the plane over.
+template <typename T, int GRP, int NG, bool OUT>
+struct ZfSink {
+  using V = typename lanes_of<T, 2>::type;
+  ZfLds<T> L;
+  T *rho_out, *e_out;
+  int r, x0, buf, plane, c0;
+  bool live;
+  __device__ __forceinline__ void put(int u, idx_t ic, V val) {
+    if (u == 0 && GRP != 0) return;  // the first group holds the density
+    const int m = u == 0 ? 0 : group_q(NG, GRP, u - 1);
+    *reinterpret_cast<V *>(L.at(buf, r, m) + x0) = val;
+    if (OUT && m <= 1 && live && plane >= c0) gstv<V>(m == 0 ? rho_out : e_out, ic, val);
+  }
+  __device__ __forceinline__ void done(int) {
+    __syncthreads();
+    buf ^= 1;
+    ++plane;
+  }
+};
+
+template <typename T, int GRP, int NG, bool OUT>
+__device__ __forceinline__ void zf_walk(const Geo &G, const Phys &P, const MarchArgs<T> &M, ZfLds<T> L, int r,
+                                        int row, int x0, bool live, int cs, int c0, int c1) {
+  using V = typename lanes_of<T, 2>::type;
+  // lanes past the row end read the row's first cells (in bounds, unused)
+  const idx_t base = lin(G, live ? x0 : 0, row, 0);
+  const T *qi = M.qi[0];
+  ColSrc<T, V, 2, 1, GRP, NG> src{qi, {M.qi[group_q(NG, GRP, 0)], M.qi[group_q(NG, GRP, 1)],
+                                       M.qi[group_q(NG, GRP, 2)], M.qi[group_q(NG, GRP, 3)]},
+                                  base, (idx_t)G.sz, G.n[2]};
+  ZfSink<T, GRP, NG, OUT> snk{L, M.qo[0], M.qo[1], r, x0, 0, cs, c0, live};
+  march_column<T, 2, 1, GRP, false, 2, NG>(G, P, M, live ? x0 : 0, row, cs, c1, src, snk, live);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchArgs<T> M, KickArgs<T> K,
+                                                            RedArgs<T> R) {
+  using V = typename lanes_of<T, 2>::type;
+  __shared__ __align__(16) T zl[2 * (ZF_TY + 1) * NQ * 128];
+  __shared__ double sh[5][ZF_WAVES];
+  const ZfLds<T> L{zl};
+  const int lane = threadIdx.x;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  // block -> (row band, z segment): each XCD (block h runs on XCD h % 8)
+  // takes one contiguous range of bands through all segments
+  const int nch = (G.n[2] + M.chunk - 1) / M.chunk;
+  const unsigned N = gridDim.x, h = blockIdx.x;
+  const unsigned q8 = N / 8, r8 = N % 8, xcd = h % 8, s8 = h / 8;
+  const unsigned Lg = (xcd < r8) ? xcd * (q8 + 1) + s8 : r8 * (q8 + 1) + (xcd - r8) * q8 + s8;
+  const int band = (int)(Lg / (unsigned)nch), ch = (int)(Lg % (unsigned)nch);
+  const int j0 = band * ZF_TY;
+  const int c0 = ch * M.chunk, c1 = min(c0 + M.chunk, G.n[2]);
+  const int cs = c0 > 0 ? c0 - 1 : 0;  // first plane walked
+  const int x0 = 2 * lane;
+  const bool live = x0 < G.n[0];
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  T sig = T(0);
+  int bad = 0;
+  if (blockIdx.x == 0 && lane == 0 && wv == 0) {
+    R.S->tlog = R.S->t;  // the force partials of this state await the log
+    R.S->pending = 1;
+  }
+  if (wv == 0) {
+    // the row below the band (row 0 again for the first band: not used)
+    zf_walk<T, 0, 3, false>(G, P, M, L, 0, max(j0 - 1, 0), x0, live, cs, c0, c1);
+  } else if (wv <= 2 * ZF_TY) {
+    const int y = (wv - 1) >> 1;
+    if ((wv - 1) & 1) zf_walk<T, 1, 2, false>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1);
+    else zf_walk<T, 0, 2, true>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1);
+  } else {
+    // finisher of band row y, cells x0, x0 + 1 of row j
+    const int y = wv - 1 - 2 * ZF_TY, j = j0 + y, r = 1 + y;
+    const int i = x0;
+    const T h = (T)(K.fac * K.dtp[0]);
+    const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
+    const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
+    V xcx;
+    xcx.x = xcen<T>(G, 0, i);
+    xcx.y = xcen<T>(G, 0, i + 1);
+    const T yc = xcen<T>(G, 1, j);
+    auto r2of = [&](V xv, T yy, T zz) -> V { return xv * xv + yy * yy + zz * zz + eps2; };
+    auto sound1 = [&](T dr, T de) -> T {
+      const T rr = rho0 + dr, en = e0 + de;
+      if (!(rr > T(0)) || !(en > T(0)) || !isfinite(rr) || !isfinite(en)) bad = 1;
+      return qsqrt(qdiv(gg * en, rr));
+    };
+    auto sound = [&](V dr, V de) -> V {
+      V s;
+      s.x = sound1(dr.x, de.x);
+      s.y = sound1(dr.y, de.y);
+      return s;
+    };
+    auto vmax = [&](V a) { sig = fmax(sig, fmax(a.x, a.y)); };
+    auto vabs = [&](V a) -> V {
+      V o;
+      o.x = fabs(a.x);
+      o.y = fabs(a.y);
+      return o;
+    };
+    auto kickv = [&](V vf, V drm, V dem, V dcr, V der, V xr, V dm, V dr_) -> V {
+      const V rface = rho0 + T(0.5) * (drm + dcr);
+      const V gradp = qdiv(gm1 * (der - dem), dx * rface);
+      const V xm = xr - dx;
+      const V gradphi = qdiv(GM * (xr + xm), dm * dr_ * (dm + dr_));
+      return vf - h * (gradp + gradphi);
+    };
+    auto rebuild = [&](int d, V ppm, V pmc, V drm, V dcr) -> V {
+      const T vb = (T)vback(P, d);
+      return qdiv(ppm + pmc - vb * (drm + dcr), T(2) * rho0 + drm + dcr);
+    };
+    auto ldv = [&](int buf, int rr, int m) -> V { return *reinterpret_cast<const V *>(L.at(buf, rr, m) + x0); };
+    // the cells below the z faces: new departures, sound speeds and
+    // distances of the plane before
+    V zr = V(0), ze = V(0), zp = V(0), zc = V(0), zd = V(0);
+    for (int k = cs; k < c1; ++k) {
+      __syncthreads();
+      const int buf = (k - cs) & 1;
+      if (!live) continue;
+      const V drc = ldv(buf, r, 0), dec = ldv(buf, r, 1);
+      const T zcen = xcen<T>(G, 2, k);
+      const V r2c = r2of(xcx, yc, zcen);
+      const V dcen = qsqrtv(r2c);
+      const V cs_own = sound(drc, dec);
+      const V ppz = ldv(buf, r, 7);
+      if (k >= c0) {
+        const idx_t c = lin(G, i, j, k);
+        const T csprev = dpp_fill<DPP_WAVE_SHR1>(cs_own.y, T(0));
+        const T dprev = dpp_fill<DPP_WAVE_SHR1>(dcen.y, T(0));
+        // x: faces i and i+1; below them cell i-1 (the cell itself at x = 0) and cell i
+        {
+          V drm, dem, ppm;
+          drm.y = drc.x;
+          dem.y = dec.x;
+          const V ppc = ldv(buf, r, 3);
+          ppm.y = ppc.x;
+          if (i > 0) {
+            drm.x = L.at(buf, r, 0)[x0 - 1];
+            dem.x = L.at(buf, r, 1)[x0 - 1];
+            ppm.x = L.at(buf, r, 3)[x0 - 1];
+          } else {
+            drm.x = drc.x;
+            dem.x = dec.x;
+            ppm.x = ppc.x;
+          }
+          V vf = rebuild(0, ppm, ldv(buf, r, 2), drm, drc);
+          V dmx;
+          dmx.y = dcen.x;
+          if (i > 0 && lane > 0) {
+            dmx.x = dprev;
+          } else {
+            V xb;
+            xb.x = xcen<T>(G, 0, i - 1);  // cell i-1 (a ghost position at x = 0)
+            xb.y = xb.x;
+            dmx.x = qsqrtv(r2of(xb, yc, zcen)).x;
+          }
+          vf = kickv(vf, drm, dem, drc, dec, xcx, dmx, dcen);
+          gstv<V>(K.v[0], c, vf);
+          const V a = vabs((T)vback(P, 0) + vf);
+          vmax(a + cs_own);
+          if (i > 0) sig = fmax(sig, a.x + (lane > 0 ? csprev : sound1(drm.x, dem.x)));
+          sig = fmax(sig, a.y + cs_own.x);
+          if (i + 1 == G.n[0] - 1) {
+            K.v[0][c + 2] = T(0);  // injection face at x_max carries the wind
+            sig = fmax(sig, fabs((T)vback(P, 0)) + cs_own.y);
+          }
+        }
+        // y: face j (the row below from slot r-1; the row itself at y = 0),
+        // and face n after the last row
+        {
+          const V pmy = ldv(buf, r, 4), ppy = ldv(buf, r, 5);
+          const bool lo = j > 0;
+          const V drm = lo ? ldv(buf, r - 1, 0) : drc, dem = lo ? ldv(buf, r - 1, 1) : dec;
+          V vf = rebuild(1, lo ? ldv(buf, r - 1, 5) : ppy, pmy, drm, drc);
+          const V dmb = qsqrtv(r2of(xcx, xcen<T>(G, 1, j - 1), zcen));
+          vf = kickv(vf, drm, dem, drc, dec, V(yc), dmb, dcen);
+          gstv<V>(K.v[1], c, vf);
+          const V a = vabs(vf);
+          vmax(a + cs_own);
+          if (lo) vmax(a + sound(drm, dem));
+          if (j == G.n[1] - 1) {
+            const T xr = xcen<T>(G, 1, j + 1);
+            const V dr_ = qsqrtv(r2of(xcx, xr, zcen));
+            V vh = rebuild(1, ppy, pmy, drc, drc);
+            vh = kickv(vh, drc, dec, drc, dec, V(xr), dcen, dr_);
+            gstv<V>(K.v[1], c + (idx_t)G.sy, vh);
+            vmax(vabs(vh) + cs_own);
+          }
+        }
+        // z: face k (the plane before from the walk's previous plane; the
+        // plane itself at z = 0), and face n after the last plane
+        {
+          const V pmz = ldv(buf, r, 6);
+          const bool lo = k > 0;
+          const V drm = lo ? zr : drc, dem = lo ? ze : dec;
+          V vf = rebuild(2, lo ? zp : ppz, pmz, drm, drc);
+          const V dmb = lo ? zd : qsqrtv(r2of(xcx, yc, xcen<T>(G, 2, k - 1)));
+          vf = kickv(vf, drm, dem, drc, dec, V(zcen), dmb, dcen);
+          gstv<V>(K.v[2], c, vf);
+          const V a = vabs(vf);
+          vmax(a + cs_own);
+          if (lo) vmax(a + zc);
+          if (k == G.n[2] - 1) {
+            const T xr = xcen<T>(G, 2, k + 1);
+            const V dr_ = qsqrtv(r2of(xcx, yc, xr));
+            V vh = rebuild(2, ppz, pmz, drc, drc);
+            vh = kickv(vh, drc, dec, drc, dec, V(xr), dcen, dr_);
+            gstv<V>(K.v[2], c + (idx_t)G.sz, vh);
+            vmax(vabs(vh) + cs_own);
+          }
+        }
+        // force of the gas in these cells on the perturber, eq. 18: each
+        // cell's term in the storage type, the sum in FP64
+        const V w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
+        fx += (double)(w.x * xcx.x) + (double)(w.y * xcx.y);
+        fy += (double)(w.x * yc) + (double)(w.y * yc);
+        fz += (double)(w.x * zcen) + (double)(w.y * zcen);
+      }
+      zr = drc;
+      ze = dec;
+      zp = ppz;
+      zc = cs_own;
+      zd = dcen;
+    }
+    if (!isfinite(sig)) bad = 1;
+  }
+  // block sums of the force partials and maximum of the signal speeds (every
+  // wave takes part; walkers contribute zeros), written to slot blockIdx.x;
+  // the slots of the one-cell-per-thread grid past the launch are zeroed
+  fx = wave_sum(fx);
+  fy = wave_sum(fy);
+  fz = wave_sum(fz);
+  double sg = wave_max(bad ? 0.0 : (double)sig);
+  const bool anybad = __any(bad);
+  if (lane == 0) {
+    sh[0][wv] = fx;
+    sh[1][wv] = fy;
+    sh[2][wv] = fz;
+    sh[3][wv] = sg;
+    if (anybad) atomicOr(&R.S->health, 1);
+  }
+  __syncthreads();
+  if (lane == 0 && wv == 0) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, m = 0.0;
+    for (int w = 0; w < ZF_WAVES; ++w) {
+      s0 += sh[0][w];
+      s1 += sh[1][w];
+      s2 += sh[2][w];
+      m = fmax(m, sh[3][w]);
+    }
+    const long nb = R.npart;
+    R.part[blockIdx.x] = s0;
+    R.part[nb + blockIdx.x] = s1;
+    R.part[2 * nb + blockIdx.x] = s2;
+    R.spart[blockIdx.x] = m;
+    __hip_atomic_fetch_max(&R.S->smax[blockIdx.x & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  for (unsigned z = gridDim.x + blockIdx.x + (unsigned)(wv * 64 + lane) * gridDim.x; z < (unsigned)R.npart;
+       z += gridDim.x * 64u * ZF_WAVES) {
+    R.part[z] = 0.0;
+    R.part[R.npart + z] = 0.0;
+    R.part[2 * (size_t)R.npart + z] = 0.0;
+    R.spart[z] = 0.0;
+  }
+}
+
 struct DtArgs {
   // advance: 0 set dt, 1 set dt and advance the time, 2 per-level limits only
   double dx[MAXLEV];
@@ -2958,6 +3285,53 @@ bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int s
                   int chunk) {
   if (P.fp32) return transport_xy_t<float>(st, G, P, B, src, dtp, fac, chunk);
   return transport_xy_t<double>(st, G, P, B, src, dtp, fac, chunk);
+}
+
+bool transport_z_finish_fits(const Geo &G) {
+  return G.bc == 1 && !G.has_fine && G.n[0] <= 2 * BX && G.n[0] % 2 == 0 && G.n[1] % ZF_TY == 0;
+}
+
+template <typename T>
+static bool transport_z_finish_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, void *const *vin, int src,
+                                 const double *dtp, double fac, double kfac, Scal *S, int chunk) {
+  // the walk reads the z-face velocities the finish rewrites: they must be
+  // another set (the first kick's, when it was fused with the compression)
+  if (!transport_z_finish_fits(G) || !S || vin[2] == B.v[2]) return false;
+  MarchArgs<T> M{};
+  const Box b = active_box(G);
+  for (int d = 0; d < 3; ++d) {
+    M.lo[d] = b.lo[d];
+    M.hi[d] = b.hi[d];
+    M.fn[d] = 0;
+  }
+  M.chunk = G.n[2] <= chunk ? G.n[2] : chunk;
+  for (int m = 0; m < NQ; ++m) {
+    M.qi[m] = tp<T>(B.q[src][m]);
+    M.qo[m] = tp<T>(B.q[1 - src][m]);
+  }
+  M.v = tp<T>(vin[2]);
+  M.dtp = dtp;
+  M.fac = fac;
+  M.acc = nullptr;
+  M.facc = nullptr;
+  KickArgs<T> K{};
+  for (int d = 0; d < 3; ++d) {
+    K.v[d] = tp<T>(B.v[d]);
+    K.vin[d] = K.v[d];
+  }
+  K.dtp = dtp;
+  K.fac = kfac;
+  const RedArgs<T> R = red_args<T>(G, B, 1 - src, S);
+  const long nch = (G.n[2] + M.chunk - 1) / M.chunk;
+  const long nblk = (long)(G.n[1] / ZF_TY) * nch;
+  if (nblk > R.npart) return false;  // every block needs a partial slot (never the case for a fitting mesh)
+  DFK_LAUNCH(k_zfinish<T>, dim3((unsigned)nblk), dim3(64, ZF_WAVES), st, G, P, M, K, R);
+  return true;
+}
+bool transport_z_finish(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, void *const *vin, int src,
+                        const double *dtp, double fac, double kfac, Scal *S, int chunk) {
+  if (P.fp32) return transport_z_finish_t<float>(st, G, P, B, vin, src, dtp, fac, kfac, S, chunk);
+  return transport_z_finish_t<double>(st, G, P, B, vin, src, dtp, fac, kfac, S, chunk);
 }
 
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,

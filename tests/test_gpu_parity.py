@@ -185,13 +185,69 @@ def test_fused_kick_compress_equals_separate(dfm, n, nl, bcmode, prec):
     assert fa[3] == fb[3]
 
 
+# The z pass fused with the rebuild, the kick and the end-of-step partials
+# against the separate launches: rows of 32, 64 and 128 cells, 96 (a quarter of
+# the lanes past the row end), 200 (too long: both sides run the separate
+# launches), z extents of one segment, of several with a ragged last one (40)
+# and of 2 cells, y extents of 2 to 40 rows.
+FINISH_SHAPES = [(32, 16, 8), (64, 12, 6), (96, 10, 40), (128, 40, 6), (128, 2, 2), (64, 18, 70), (200, 6, 4),
+                 (16, 4, 34)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", FINISH_SHAPES)
+def test_fused_finish_equals_separate(dfm, n, prec):
+    _say(f"[fused finish] n={n} {prec}")
+    nx, ny, nz = n
+    p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
+    runs = []
+    for fuse in (False, True):
+        g = dfm.Run(nx, ny, nz, dx0=0.05, seed=43, noise_amp=1e-3, precision=p)
+        g.set_perturber(0.01, 0.05, 2e-3, 1.3, 0.1)
+        g.set_finish_fusion(fuse)
+        g.step(6)
+        runs.append(g)
+    # the same operations in the same order; only the pairing into fused
+    # multiply-adds and the grouping of the force partials may differ
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    for name in FIELD_NAMES:
+        a, b = runs[0].field(0, name), runs[1].field(0, name)
+        assert np.max(np.abs(a - b)) <= tol * SCALE[name], (name, float(np.max(np.abs(a - b))))
+    fa, fb = runs[0].force(), runs[1].force()
+    assert np.max(np.abs(fa[:3] - fb[:3])) <= 1e2 * tol * np.linalg.norm(fa[:3]), (fa, fb)
+    assert fa[3] == fb[3]
+    la, lb = runs[0].force_log(), runs[1].force_log()
+    assert la.shape == lb.shape and np.array_equal(la[:, 3], lb[:, 3])  # the same step lengths
+    assert np.max(np.abs(la[:, :3] - lb[:, :3])) <= 1e2 * tol * np.max(np.abs(la[:, :3]))
+
+
+@pytest.mark.parametrize("n,prec,steps", [((24, 24, 24), "fp32", 10), ((128, 64, 96), "fp64", 6),
+                                          ((96, 40, 70), "fp32", 6)])
+def test_runs_repeat_bitwise(dfm, n, prec, steps):
+    # the same run three times gives bitwise the same fields and force: no
+    # kernel depends on the order in which its blocks run
+    _say(f"[repeat] n={n} {prec} x {steps}")
+    nx, ny, nz = n
+    p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
+    out = []
+    for _ in range(3):
+        g = dfm.Run(nx, ny, nz, dx0=0.05, seed=47, noise_amp=1e-3, precision=p)
+        g.set_perturber(0.01, 0.05, 2e-3, 0.3, 0.1)
+        g.step(steps)
+        out.append(({name: g.field(0, name) for name in FIELD_NAMES}, g.force()))
+    for other in out[1:]:
+        for name in FIELD_NAMES:
+            assert np.array_equal(out[0][0][name], other[0][name]), name
+        assert np.array_equal(out[0][1], other[1])
+
+
 def test_fusion_switches_reject_other_values(dfm):
     # through the C ABI itself (the binding passes booleans)
     from paper_1812_03191_amd import _lib
 
     g = dfm.Run(16, dx0=0.1)
     lib = _lib._load()
-    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion):
+    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion, lib.df_set_finish_fusion):
         assert fn(g._h, 0) == 0 and fn(g._h, 1) == 0
         assert fn(g._h, 2) == -1 and fn(g._h, -1) == -1
 
