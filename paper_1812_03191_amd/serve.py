@@ -26,7 +26,7 @@ def job_cell_updates(cfg: dict, steps: int) -> int:
 
 
 def serve(arrivals, jobs, steps, *, budget_bytes, precision=DF_FP32, nstreams=4, tune=True,
-          inflight=2, log=None):
+          inflight=4, log=None):
     import torch
 
     from .autotune import best_chunk
