@@ -50,6 +50,7 @@ typedef struct {
   int subcycle;       /* 0: two sub-steps per level; 1: App. A criterion    */
   int bcmode;         /* level-0 boundaries: 0 inflow/outflow; 1 Sect. 3.4  */
   double visc;        /* artificial-viscosity coefficient C2 (0: off)       */
+  int nx1, ny1, nz1;  /* cells of every level >= 1 (0: those of level 0)    */
 } dfo_params;
 
 typedef struct {
@@ -73,6 +74,12 @@ typedef struct {
 } run_t;
 
 /* ------------------------------------------------------------------ index */
+/* The finer level l+1 covers the central n_{l+1}/2 cells of level l in each
+ * dimension (every level has the perturber's vertex at its centre): with
+ * equal cell counts that is the central half (Sect. 3.4), with the finer
+ * levels half as wide as level 0 level 1 covers the central quarter of it
+ * (the mesh of Sect. 4.1.3 and 4.2.2).  o: first covered cell, h: count. */
+static void cov_box(const run_t *R, int lc, int o[3], int h[3]);
 
 static inline size_t IX(const lev_t *L, int i, int j, int k) {
   return ((size_t)(k + L->g) * (size_t)L->s[1] + (size_t)(j + L->g)) * (size_t)L->s[0] +
@@ -650,11 +657,12 @@ static void transport_pass(run_t *R, int lvl, int dn, double dt) {
   /* coarse level under a finer one: overwrite transfers on the frontier */
   if (lvl < R->nl - 1) {
     lev_t *F = &R->lev[lvl + 1];
-    int o[3] = {L->n[0] / 4, L->n[1] / 4, L->n[2] / 4};
+    int o[3], h[3];
+    cov_box(R, lvl, o, h);
     for (int side = 0; side < 2; ++side) {
-      int fi = side ? (3 * L->n[dn]) / 4 : o[dn];
-      for (int b2 = o[t2]; b2 < o[t2] + L->n[t2] / 2; ++b2)
-        for (int b1 = o[t1]; b1 < o[t1] + L->n[t1] / 2; ++b1) {
+      int fi = side ? o[dn] + h[dn] : o[dn];
+      for (int b2 = o[t2]; b2 < o[t2] + h[t2]; ++b2)
+        for (int b1 = o[t1]; b1 < o[t1] + h[t1]; ++b1) {
           int id[3];
           id[dn] = fi; id[t1] = b1; id[t2] = b2;
           size_t f = IX(L, id[0], id[1], id[2]);
@@ -768,7 +776,8 @@ static inline int fdiv2(int i) { return (i >= 0) ? i / 2 : -((-i + 1) / 2); }
 
 static void commup_fill(run_t *R, int lc, int all) {
   lev_t *C = &R->lev[lc], *F = &R->lev[lc + 1];
-  int o[3] = {C->n[0] / 4, C->n[1] / 4, C->n[2] / 4};
+  int o[3], hc[3];
+  cov_box(R, lc, o, hc);
   int g = F->g;
   for (int fld = 0; fld < NSTATE; ++fld) {
     int stag = (fld >= S_VX) ? fld - S_VX : -1;
@@ -825,8 +834,8 @@ static void commup(run_t *R, int lc) { commup_fill(R, lc, 0); }
  * exactness on uniform data. */
 static void commmean(run_t *R, int lc) {
   lev_t *C = &R->lev[lc], *F = &R->lev[lc + 1];
-  int o[3] = {C->n[0] / 4, C->n[1] / 4, C->n[2] / 4};
-  int h[3] = {C->n[0] / 2, C->n[1] / 2, C->n[2] / 2};
+  int o[3], h[3];
+  cov_box(R, lc, o, h);
   for (int fld = 0; fld < NSTATE; ++fld) {
     int stag = (fld >= S_VX) ? fld - S_VX : -1;
     const double *Q = F->st[fld];
@@ -985,10 +994,10 @@ static inline void nadd(nsum_t *a, double x) {
 
 static int covered(const run_t *R, int l, int i, int j, int k) {
   if (l >= R->nl - 1) return 0;
-  const lev_t *L = &R->lev[l];
-  int id[3] = {i, j, k};
+  int id[3] = {i, j, k}, o[3], h[3];
+  cov_box(R, l, o, h);
   for (int d = 0; d < 3; ++d)
-    if (id[d] < L->n[d] / 4 || id[d] >= (3 * L->n[d]) / 4) return 0;
+    if (id[d] < o[d] || id[d] >= o[d] + h[d]) return 0;
   return 1;
 }
 
@@ -1092,6 +1101,14 @@ static void init_state(run_t *R) {
   restrict_prolong_all(R);
 }
 
+static void cov_box(const run_t *R, int lc, int o[3], int h[3]) {
+  const lev_t *C = &R->lev[lc], *F = &R->lev[lc + 1];
+  for (int d = 0; d < 3; ++d) {
+    h[d] = F->n[d] / 2;
+    o[d] = (C->n[d] - h[d]) / 2;
+  }
+}
+
 /* ============================================================== C API */
 
 static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
@@ -1100,6 +1117,12 @@ void dfo_destroy(void *h);
 
 void *dfo_create(const dfo_params *p) {
   if (p->nlevels < 1 || p->nlevels > DFO_MAXLEV) return NULL;
+  if (p->nx1 > 0) {
+    /* finer levels: even halves that fit inside level 0 around its centre */
+    const int n0[3] = {p->nx, p->ny, p->nz}, n1[3] = {p->nx1, p->ny1, p->nz1};
+    for (int d = 0; d < 3; ++d)
+      if (n1[d] % 4 || n1[d] / 2 > n0[d] || (n0[d] - n1[d] / 2) % 2) return NULL;
+  }
   run_t *R = (run_t *)calloc(1, sizeof(run_t));
   R->p = *p;
   R->nl = p->nlevels;
@@ -1109,6 +1132,7 @@ void *dfo_create(const dfo_params *p) {
   for (int l = 0; l < R->nl; ++l) {
     lev_t *L = &R->lev[l];
     L->n[0] = p->nx; L->n[1] = p->ny; L->n[2] = p->nz;
+    if (l > 0 && p->nx1 > 0) { L->n[0] = p->nx1; L->n[1] = p->ny1; L->n[2] = p->nz1; }
     L->g = (l == 0) ? p->g0 : p->gf;
     L->vol = 1;
     for (int d = 0; d < 3; ++d) { L->s[d] = L->n[d] + 2 * L->g; L->vol *= (size_t)L->s[d]; }

@@ -48,6 +48,7 @@ class _Params(ctypes.Structure):
         ("GM", ctypes.c_double), ("eps", ctypes.c_double), ("L", ctypes.c_double),
         ("mach", ctypes.c_double), ("chi", ctypes.c_double),
         ("subcycle", ctypes.c_int), ("bcmode", ctypes.c_int), ("visc", ctypes.c_double),
+        ("nx1", ctypes.c_int), ("ny1", ctypes.c_int), ("nz1", ctypes.c_int),
     ]
 
 
@@ -106,7 +107,7 @@ class Oracle:
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0=None, gamma=5.0 / 3.0,
                  cfl=0.4, rho0=1.0, cs=1.0, seed=1, noise_amp=1e-6, GM=0.01, eps=0.0,
                  L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None, subcycle=0, bcmode=0, visc=0.0,
-                 lib_path=_LIB):
+                 n1=None, lib_path=_LIB):
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         if dx0 is None:
@@ -115,9 +116,13 @@ class Oracle:
             os.environ["OMP_NUM_THREADS"] = str(threads)
             _load(lib_path).dfo_set_threads(int(threads))
         self._lib = _load(lib_path)
+        n1 = tuple(n1) if n1 else (0, 0, 0)
         self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
-                         noise_amp, GM, eps, L, mach, chi, int(subcycle), int(bcmode), float(visc))
+                         noise_amp, GM, eps, L, mach, chi, int(subcycle), int(bcmode), float(visc),
+                         *[int(v) for v in n1])
         self.n = (nx, ny, nz)
+        # cells of each level (levels >= 1 may be half as wide as level 0)
+        self.nl = [self.n] + [(n1 if n1[0] else self.n)] * (nlevels - 1)
         self.nlevels = nlevels
         self.g = [g0] + [gf] * (nlevels - 1)
         self._h = self._lib.dfo_create(ctypes.byref(self.p))
@@ -165,7 +170,7 @@ class Oracle:
 
     def _shape(self, level, ghosts):
         g = self.g[level] if ghosts else 0
-        nx, ny, nz = self.n
+        nx, ny, nz = self.nl[level]
         return (nz + 2 * g, ny + 2 * g, nx + 2 * g)
 
     def field(self, level: int, name: str, ghosts: bool = False) -> np.ndarray:
@@ -183,7 +188,7 @@ class Oracle:
 
     def last_face(self, level: int, name: str) -> np.ndarray:
         """the face-velocity entries with index n along their own axis"""
-        nx, ny, nz = self.n
+        nx, ny, nz = self.nl[level]
         dn = FIELDS[name] - 2
         shp = {0: (nz, ny), 1: (nz, nx), 2: (ny, nx)}[dn]
         out = np.zeros(shp)
@@ -225,7 +230,7 @@ class Oracle:
         self._lib.dfo_commmean(self._h, coarse_level)
 
     def heat_weights(self, level: int) -> np.ndarray:
-        nx, ny, nz = self.n
+        nx, ny, nz = self.nl[level]
         out = np.zeros((nz, ny, nx))
         self._lib.dfo_heat_weights(self._h, level, _dp(out))
         return out
