@@ -12,8 +12,9 @@
  *
  * Conventions (code units G = rho0 = c_s = 1 unless set otherwise):
  *  - the perturber sits at the origin, which is the central vertex of every
- *    level; level l+1 covers the central half of level l in each dimension,
- *    with the same number of cells and half the cell size;
+ *    level; level l+1 has half the cell size of level l and covers its central
+ *    half in each dimension (or, with finer levels of half level 0's cells,
+ *    level 1 covers the central quarter of level 0);
  *  - the gas enters through the x_max face with velocity (-mach c_s, 0, 0);
  *    every other outer face of level 0 is a zero-gradient outflow boundary;
  *  - fields: DF_RHO density, DF_E internal energy per unit volume, and the
@@ -57,8 +58,9 @@ enum { DF_RHO = 0, DF_E = 1, DF_VX = 2, DF_VY = 3, DF_VZ = 4 };
 typedef struct df_run df_run;
 
 /* Mesh description (Sect. 3.4).
- *  nx, ny, nz : active cells per level, each even (the perturber is a vertex),
- *               each a multiple of 4 and >= 16 when nlevels > 1;
+ *  nx, ny, nz : active cells of level 0 (and of every level unless nx1 is
+ *               set), each even (the perturber is a vertex), each a multiple
+ *               of 4 and >= 16 when nlevels > 1;
  *  nlevels    : 1..12;
  *  dx0        : cell size of level 0 (> 0);
  *  gamma      : adiabatic index (> 1); cfl: Courant factor in (0, 1];
@@ -71,7 +73,13 @@ typedef struct df_run df_run;
  *               U uniform in [0,1) from a counter-based SplitMix64 stream;
  *  tile_chunk : cells per column segment of the streaming y and z transport
  *               passes (0 selects 32 for FP64 and 16 for FP32 storage; 2..256),
- *               a launch-shape parameter that does not change results. */
+ *               a launch-shape parameter that does not change results;
+ *  nx1, ny1, nz1 : cells of every level >= 1 (0: those of level 0), each a
+ *               multiple of 4, >= 16 and at most twice level 0's count.  Level
+ *               l+1 covers the central n_{l+1}/2 cells of level l along each
+ *               dimension: the central half when all levels have the same
+ *               cells, the central quarter of level 0 when the finer levels
+ *               have half its cells (the hierarchy of Sects. 4.1.3, 4.2.2). */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t nlevels;
@@ -83,6 +91,7 @@ typedef struct {
   uint64_t seed;
   double noise_amp;
   int32_t tile_chunk;
+  int32_t nx1, ny1, nz1;
 } df_mesh_desc;
 
 /* Validate a mesh description and create a run handle (host memory only; no

@@ -31,6 +31,7 @@ class MeshDesc(ctypes.Structure):
         ("precision", ctypes.c_int32), ("ghost_fine", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("tile_chunk", ctypes.c_int32),
+        ("nx1", ctypes.c_int32), ("ny1", ctypes.c_int32), ("nz1", ctypes.c_int32),
     ]
 
 
@@ -103,16 +104,17 @@ def _dp(a: np.ndarray):
 # ---------------------------------------------------------------- entry points
 
 def mesh_desc(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
-              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0) -> MeshDesc:
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None) -> MeshDesc:
+    n1 = tuple(n1) if n1 else (0, 0, 0)
     return MeshDesc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
-                    tile_chunk)
+                    tile_chunk, *[int(v) for v in n1])
 
 
 def init_mesh(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
-              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0) -> int:
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None) -> int:
     lib = _load()
     d = mesh_desc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
-                  tile_chunk)
+                  tile_chunk, n1)
     h = ctypes.c_void_p()
     _ck(lib.df_init_mesh(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -238,15 +240,17 @@ class Run:
 
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0, gamma=5.0 / 3.0, cfl=0.4,
                  precision=DF_FP64, ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0,
-                 device="cuda"):
+                 n1=None, device="cuda"):
         import torch
 
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         self.n = (nx, ny, nz)
         self.nlevels = nlevels
+        # cells of each level (the finer levels may have their own, n1)
+        self.nl = [self.n] + [tuple(n1) if n1 else self.n] * (nlevels - 1)
         self._h = init_mesh(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed,
-                            noise_amp, tile_chunk)
+                            noise_amp, tile_chunk, n1)
         self.nbytes = required_bytes(self._h)
         self.device = torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
@@ -320,22 +324,22 @@ class Run:
     def stage(self, name, dt):
         debug_stage(self._h, STAGES[name], dt)
 
-    def shape(self, name):
-        nx, ny, nz = self.n
+    def shape(self, name, level=0):
+        nx, ny, nz = self.nl[level]
         e = [nx, ny, nz]
         if name in ("vx", "vy", "vz"):
             e["xyz".index(name[1])] += 1
         return (e[2], e[1], e[0])
 
     def field(self, level, name):
-        out = np.zeros(self.shape(name))
+        out = np.zeros(self.shape(name, level))
         get_field(self._h, level, FIELDS[name], out)
         return out
 
     def set_field(self, level, name, arr):
         a = np.ascontiguousarray(arr, dtype=np.float64)
-        if a.shape != self.shape(name):
-            raise ValueError(f"shape {a.shape} != {self.shape(name)}")
+        if a.shape != self.shape(name, level):
+            raise ValueError(f"shape {a.shape} != {self.shape(name, level)}")
         set_field(self._h, level, FIELDS[name], a)
 
 
@@ -378,7 +382,7 @@ def engine_job_bytes(cfg: dict, precision=DF_FP64, tile_chunk=0) -> int:
 def _desc_of(cfg, precision, tile_chunk):
     return mesh_desc(cfg["nx"], cfg["ny"], cfg["nz"], cfg["nlevels"], cfg["dx0"], cfg.get("gamma", 5.0 / 3.0),
                      cfg.get("cfl", 0.4), precision, cfg.get("ghost_fine", 0), cfg.get("seed", 1),
-                     cfg.get("noise_amp", 1e-6), tile_chunk)
+                     cfg.get("noise_amp", 1e-6), tile_chunk, cfg.get("n1"))
 
 
 class Engine:

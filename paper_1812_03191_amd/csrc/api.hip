@@ -432,6 +432,12 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     if (d->nlevels > 1 && (n[k] % 4 != 0 || n[k] < 16))
       return fail(DF_EINVAL, "nested runs need cell counts that are multiples of 4 and >= 16");
   }
+  // cells of the finer levels (0: those of level 0)
+  const bool own1 = d->nx1 != 0 || d->ny1 != 0 || d->nz1 != 0;
+  const int n1[3] = {own1 ? d->nx1 : d->nx, own1 ? d->ny1 : d->ny, own1 ? d->nz1 : d->nz};
+  for (int k = 0; k < 3 && own1; ++k)
+    if (n1[k] % 4 != 0 || n1[k] < 16 || n1[k] / 2 > n[k] || n1[k] > 4096)
+      return fail(DF_EINVAL, "finer-level cell counts must be multiples of 4, >= 16 and at most twice level 0's");
   if (!(d->dx0 > 0.0) || !std::isfinite(d->dx0)) return fail(DF_EINVAL, "dx0 must be positive");
   if (!(d->gamma > 1.0) || !std::isfinite(d->gamma)) return fail(DF_EINVAL, "gamma must exceed 1");
   if (!(d->cfl > 0.0) || d->cfl > 1.0) return fail(DF_EINVAL, "cfl must be in (0, 1]");
@@ -450,7 +456,7 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
     Geo &G = R->geo[l];
-    for (int k = 0; k < 3; ++k) G.n[k] = n[k];
+    for (int k = 0; k < 3; ++k) G.n[k] = l == 0 ? n[k] : n1[k];
     G.g = (l == 0) ? 0 : gf;
     for (int k = 0; k < 3; ++k) G.s[k] = (l == 0) ? G.n[k] + 1 : G.n[k] + 2 * G.g;
     // x = 0 of each row on a 128-byte boundary (16 doubles)
@@ -462,6 +468,11 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     G.level = l;
     G.bc = (l == 0);
     G.has_fine = (l + 1 < R->nl);
+    // the finer level's cells cover the central n1/2 cells of this one
+    for (int k = 0; k < 3; ++k) {
+      G.cn[k] = G.has_fine ? n1[k] / 2 : 0;
+      G.co[k] = G.has_fine ? (G.n[k] - G.cn[k]) / 2 : 0;
+    }
     R->vol[l] = (size_t)G.sz * G.s[2];
     if (R->vol[l] >= ((size_t)1 << 31)) {
       delete R;

@@ -28,7 +28,9 @@ struct Geo {
   int level;
   int bc;        // level 0 reads its outer boundary conditions: 1 inflow at x_max and outflow elsewhere,
                  // 2 the boundary list of Sect. 3.4 (background at both flow ends, mirror walls); 0 finer levels
-  int has_fine;  // a finer level covers the central half
+  int has_fine;  // a finer level covers a central box of this level
+  int co[3];     // that box: first covered cell and number of covered cells (the
+  int cn[3];     // finer level's cell count / 2), centred on the perturber's vertex
 };
 
 // Gas and perturber parameters (code units).  The fields are stored as

@@ -786,9 +786,9 @@ __global__ void __launch_bounds__(BX * BY) k_xpass(Geo G, Phys P, PassArgs<T> A)
   int side = 0;
   long fbase = 0, fnt = 0;
   if (A.facc) {
-    const int a1 = j - G.n[1] / 4, a2 = k - G.n[2] / 4;
-    const int lo = G.n[0] / 4, hi = (3 * G.n[0]) / 4;
-    if (a1 >= 0 && a2 >= 0 && a1 < G.n[1] / 2 && a2 < G.n[2] / 2 && (x == lo || x == hi)) {
+    const int a1 = j - G.co[1], a2 = k - G.co[2];
+    const int lo = G.co[0], hi = G.co[0] + G.cn[0];
+    if (a1 >= 0 && a2 >= 0 && a1 < G.cn[1] && a2 < G.cn[2] && (x == lo || x == hi)) {
       fine_face = true;
       side = (x == hi);
       fnt = (long)A.fn[1] * A.fn[2];
@@ -1054,11 +1054,10 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
   }
   X.begin(G, P, (T)(A.fac * A.dtp[0]));
   // flux matching on the frontier of the finer level
-  const bool ov = A.facc && j - G.n[1] / 4 >= 0 && k - G.n[2] / 4 >= 0 && j - G.n[1] / 4 < G.n[1] / 2 &&
-                  k - G.n[2] / 4 < G.n[2] / 2;
-  const int flo = n / 4, fhi = (3 * n) / 4;
+  const bool ov = A.facc && j - G.co[1] >= 0 && k - G.co[2] >= 0 && j - G.co[1] < G.cn[1] && k - G.co[2] < G.cn[2];
+  const int flo = G.co[0], fhi = G.co[0] + G.cn[0];
   const long fnt = (long)A.fn[1] * A.fn[2];
-  const long fbase = (long)(2 * (k - G.n[2] / 4)) * A.fn[1] + 2 * (j - G.n[1] / 4);
+  const long fbase = (long)(2 * (k - G.co[2])) * A.fn[1] + 2 * (j - G.co[1]);
   auto finish = [&](int m, const T (&own)[R], T (&FL)[R]) {
     if (ov) {
 #pragma unroll
@@ -1210,13 +1209,13 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   long fbase = 0, fnt = 0;
   int flo = 0, fhi = 0;
   if (FRONT && A.facc) {
-    const int a1 = tv1 - G.n[T1] / 4, a2 = tv2 - G.n[T2] / 4;
-    if (a1 >= 0 && a2 >= 0 && a1 < G.n[T1] / 2 && a2 < G.n[T2] / 2) {
+    const int a1 = tv1 - G.co[T1], a2 = tv2 - G.co[T2];
+    if (a1 >= 0 && a2 >= 0 && a1 < G.cn[T1] && a2 < G.cn[T2]) {
       ov = true;
       fnt = (long)A.fn[T1] * A.fn[T2];
       fbase = (long)(2 * a2) * A.fn[T1] + 2 * a1;
-      flo = G.n[DIR] / 4;
-      fhi = (3 * G.n[DIR]) / 4;
+      flo = G.co[DIR];
+      fhi = G.co[DIR] + G.cn[DIR];
     }
   }
   const bool acc_col = FRONT && A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
@@ -1740,7 +1739,7 @@ __device__ __forceinline__ int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i
 // neighbours and, since the limited slope of a 1-D step does not depend on
 // which half of the host a child takes, every slope is formed once for both
 // children (19 slopes instead of 8 x 13).  A.b counts hosts relative to the
-// covered coarse box (host H = Gc.n/4 + h).
+// covered coarse box (host H = Gc.co + h).
 template <typename T, int CBC>
 __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A) {
   int h[3];
@@ -1754,7 +1753,7 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A)
     if (2 * h[d] < 0 || 2 * h[d] + 1 >= hi) inner = false;
   }
   if (inner) return;
-  const int H0 = Gc.n[0] / 4 + h[0], H1 = Gc.n[1] / 4 + h[1], H2 = Gc.n[2] / 4 + h[2];
+  const int H0 = Gc.co[0] + h[0], H1 = Gc.co[1] + h[1], H2 = Gc.co[2] + h[2];
   auto C = [&](int a, int b, int cc) -> T {
     const int ci = H0 + a, cj = H1 + b, ck = H2 + cc;
     if (CBC) {
@@ -1835,7 +1834,7 @@ __global__ void __launch_bounds__(BX * BY) k_commmean(Geo Gf, Geo Gc, MeanArgs<T
     const idx_t e2 = (A.stag == 2) ? (idx_t)Gf.sy : (idx_t)Gf.sz;
     val = ((q[f] + q[f + e1]) + (q[f + e2] + q[f + e1 + e2])) * T(0.25);
   }
-  A.out[lin(Gc, Gc.n[0] / 4 + I, Gc.n[1] / 4 + J, Gc.n[2] / 4 + K)] = val;
+  A.out[lin(Gc, Gc.co[0] + I, Gc.co[1] + J, Gc.co[2] + K)] = val;
 }
 
 // -------------------------------------------------------------- reductions
@@ -3408,7 +3407,7 @@ static void commmean_t(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, con
     A.out = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
     for (int d = 0; d < 3; ++d) {
       A.b.lo[d] = 0;
-      A.b.hi[d] = Gc.n[d] / 2 + (d == A.stag ? 1 : 0);
+      A.b.hi[d] = Gc.cn[d] + (d == A.stag ? 1 : 0);
     }
     DFK_LAUNCH(k_commmean<T>, grid_of(A.b), dim3(BX, BY), st, Gf, Gc, A);
   }
@@ -3436,8 +3435,8 @@ static RedArgs<T> red_args(const Geo &G, LevBufs &B, int cur, Scal *S) {
   A.spart = B.part + 3 * (size_t)A.npart;
   A.S = S;
   for (int d = 0; d < 3; ++d) {
-    A.cov_lo[d] = G.has_fine ? G.n[d] / 4 : 0;
-    A.cov_hi[d] = G.has_fine ? (3 * G.n[d]) / 4 : 0;
+    A.cov_lo[d] = G.has_fine ? G.co[d] : 0;
+    A.cov_hi[d] = G.has_fine ? G.co[d] + G.cn[d] : 0;
   }
   return A;
 }

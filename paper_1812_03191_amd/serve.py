@@ -22,7 +22,9 @@ from ._lib import DF_FP32, Engine, engine_job_bytes
 def job_cell_updates(cfg: dict, steps: int) -> int:
     """active cells x (sub)steps: level l advances 2^l times per coarse step"""
     n = cfg["nx"] * cfg["ny"] * cfg["nz"]
-    return steps * n * sum(2 ** l for l in range(cfg["nlevels"]))
+    n1 = cfg.get("n1")
+    m = n1[0] * n1[1] * n1[2] if n1 else n
+    return steps * (n + m * sum(2 ** l for l in range(1, cfg["nlevels"])))
 
 
 def serve(arrivals, jobs, steps, *, budget_bytes, precision=DF_FP32, nstreams=4, tune=True,

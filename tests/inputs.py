@@ -20,11 +20,29 @@ def finest_dx(mach, chi=0.1, GM=0.01, gamma=GAMMA, cs=1.0):
 
 
 def job(n, nlevels, mach, GM, chi, L, *, seed=1, noise_amp=1e-6, gamma=GAMMA, cfl=0.4,
-        dx_finest=None, eps_cells=2.0):
+        dx_finest=None, eps_cells=2.0, n1=None):
+    """one run of n^3 cells per level (or n1^3 on the finer levels)"""
     dxf = finest_dx(mach, chi, GM, gamma) if dx_finest is None else dx_finest
-    return dict(nx=n, ny=n, nz=n, nlevels=nlevels, dx0=dxf * 2 ** (nlevels - 1), gamma=gamma,
-                cfl=cfl, seed=seed, noise_amp=noise_amp, GM=GM, eps=eps_cells * dxf, L=L,
-                mach=mach, chi=chi)
+    d = dict(nx=n, ny=n, nz=n, nlevels=nlevels, dx0=dxf * 2 ** (nlevels - 1), gamma=gamma,
+             cfl=cfl, seed=seed, noise_amp=noise_amp, GM=GM, eps=eps_cells * dxf, L=L,
+             mach=mach, chi=chi)
+    if n1:
+        d["n1"] = (n1, n1, n1)
+    return d
+
+
+def paper_mesh(n0, nlevels, mach, chi, *, GM=1e-3, L=0.0, seed=1, noise_amp=0.0, dx_finest=None):
+    """The mesh of the paper's Sects. 4.1.3 and 4.2.2 (its Figs. 8 and 12) with
+    the flow along x and the full box standing for the paper's quadrant (x, y
+    > 0 there, its mirror images here): a ground level of n0^3 cells and
+    finer levels of (n0/2)^3 cells, the first covering the central quarter of
+    the ground level, the next ones the central half of the level before;
+    gamma 1.4, eps 0, the heat split over the 8 cells around the perturber;
+    finest cell lambda / 5 unless given."""
+    d = job(n0, nlevels, mach, GM, chi, L, seed=seed, noise_amp=noise_amp, gamma=1.4,
+            dx_finest=dx_finest, n1=n0 // 2)
+    d["eps"] = 0.0
+    return d
 
 
 def config1():
