@@ -51,6 +51,7 @@ typedef struct {
   int bcmode;         /* level-0 boundaries: 0 inflow/outflow; 1 Sect. 3.4  */
   double visc;        /* artificial-viscosity coefficient C2 (0: off)       */
   int nx1, ny1, nz1;  /* cells of every level >= 1 (0: those of level 0)    */
+  int quadrant;       /* 1: the domain is y > 0, z > 0 (Sect. 3.4's quadrant) */
 } dfo_params;
 
 typedef struct {
@@ -62,6 +63,7 @@ typedef struct {
   double *tmp;
   double *acc[3][2][NQ]; /* fine-level frontier transfers [dir][side][q]   */
   double *hw;            /* heat-release weight per active cell            */
+  double org[3];         /* index of the perturber's vertex along each dimension */
 } lev_t;
 
 typedef struct {
@@ -71,6 +73,8 @@ typedef struct {
   double t, dt_last, bflux, e0, V;
   long nsteps;
   int xi[DFO_MAXLEV];    /* sub-steps of level l+1 per step of level l       */
+  int anch[3];           /* quadrant: the domain starts at the perturber's mirror plane */
+  double mult;           /* copies of the domain in the whole space (mirror images) */
 } run_t;
 
 /* ------------------------------------------------------------------ index */
@@ -80,6 +84,7 @@ typedef struct {
  * levels half as wide as level 0 level 1 covers the central quarter of it
  * (the mesh of Sect. 4.1.3 and 4.2.2).  o: first covered cell, h: count. */
 static void cov_box(const run_t *R, int lc, int o[3], int h[3]);
+static void mirror_fill(run_t *R, int lvl);
 
 static inline size_t IX(const lev_t *L, int i, int j, int k) {
   return ((size_t)(k + L->g) * (size_t)L->s[1] + (size_t)(j + L->g)) * (size_t)L->s[0] +
@@ -88,9 +93,10 @@ static inline size_t IX(const lev_t *L, int i, int j, int k) {
 static inline long STR(const lev_t *L, int d) {
   return d == 0 ? 1L : (d == 1 ? (long)L->s[0] : (long)L->s[0] * (long)L->s[1]);
 }
-/* cell-centre coordinate along dimension d (perturber on the central vertex) */
+/* cell-centre coordinate along dimension d (perturber on the central vertex,
+ * or on the low face of an anchored dimension of the quadrant) */
 static inline double XC(const lev_t *L, int d, int i) {
-  return ((double)i - 0.5 * (double)L->n[d] + 0.5) * L->dx;
+  return ((double)i - L->org[d] + 0.5) * L->dx;
 }
 
 /* -------------------------------------------------------------- potential */
@@ -525,7 +531,9 @@ static void heat_weights(run_t *R, int lvl) {
         L->hw[((size_t)k * L->n[1] + j) * L->n[0] + i] = gw;
         sum += gw;
       }
-  for (size_t a = 0; a < na; ++a) L->hw[a] /= sum;
+  /* quadrant: the cells' mirror images hold the same weights, so the whole
+   * set sums to mult times the domain's */
+  for (size_t a = 0; a < na; ++a) L->hw[a] /= sum * R->mult;
 }
 
 static void heat(run_t *R, int lvl, double dt) {
@@ -539,6 +547,22 @@ static void heat(run_t *R, int lvl, double dt) {
         double w = L->hw[((size_t)k * L->n[1] + j) * L->n[0] + i];
         if (w != 0.0) e[IX(L, i, j, k)] += R->p.L * dt * w / vol;
       }
+  /* quadrant, finer levels: the ghosts beyond a mirror plane are advanced
+   * with the level as the mirror images of its cells (mirror_fill), so the
+   * images of the heated cells are heated too */
+  if (lvl == 0 || !(R->anch[1] || R->anch[2])) return;
+  const int g = L->g;
+  for (int k = -g; k < L->n[2]; ++k)
+    for (int j = -g; j < L->n[1]; ++j) {
+      if (j >= 0 && k >= 0) continue;
+      if ((j < 0 && !R->anch[1]) || (k < 0 && !R->anch[2])) continue;
+      const int jm = j < 0 ? -1 - j : j, km = k < 0 ? -1 - k : k;
+      if (jm >= L->n[1] || km >= L->n[2]) continue;
+      for (int i = 0; i < L->n[0]; ++i) {
+        double w = L->hw[((size_t)km * L->n[1] + jm) * L->n[0] + i];
+        if (w != 0.0) e[IX(L, i, j, k)] += R->p.L * dt * w / vol;
+      }
+    }
 }
 
 /* ------------------------------------------------------------- transport */
@@ -726,12 +750,18 @@ static void rebuild_velocities(run_t *R, int lvl) {
   if (lvl == 0) reset_inflow_face(R);
 }
 
+static void mirror_q(run_t *R, int lvl);
+
 static void transport(run_t *R, int lvl, double dt) {
   lev_t *L = &R->lev[lvl];
   build_momenta(R, lvl);
+  /* quadrant: a finer level with a finer one of its own takes that level's
+   * transfers on its frontier faces, whose mirror images lie in its ghosts */
+  const int mq = lvl > 0 && lvl < R->nl - 1 && (R->anch[1] || R->anch[2]);
   for (int dn = 0; dn < 3; ++dn) {
     if (lvl == 0) bc_q(R);
     transport_pass(R, lvl, dn, dt);
+    if (mq) mirror_q(R, lvl);
   }
   if (lvl == 0) bc_q(R);
   rebuild_velocities(R, lvl);
@@ -789,12 +819,16 @@ static void commup_fill(run_t *R, int lc, int all) {
       for (int j = -g; j < F->n[1] + g; ++j)
         for (int i = -g; i < F->n[0] + g; ++i) {
           int id[3] = {i, j, k};
-          int active = 1;
+          int active = 1, beyond_plane = 0;
           for (int d = 0; d < 3; ++d) {
             int hi = F->n[d] + (d == stag ? 1 : 0);
             if (id[d] < 0 || id[d] >= hi) active = 0;
+            if (id[d] < 0 && R->anch[d]) beyond_plane = 1;
           }
           if (active && !all) continue;
+          /* quadrant: entries beyond a mirror plane take the fine level's own
+           * mirror images instead (mirror_fill) */
+          if (beyond_plane) continue;
           int H[3], odd[3];
           double del[3];
           for (int d = 0; d < 3; ++d) {
@@ -822,7 +856,75 @@ static void commup_fill(run_t *R, int lc, int all) {
   }
 }
 
-static void commup(run_t *R, int lc) { commup_fill(R, lc, 0); }
+/* Quadrant (Sect. 3.4): the mirror planes y = 0 and z = 0 bound every level.
+ * Level 0 reads its wall ghosts as mirror images (bc_state); on a finer level
+ * the ghost entries beyond an anchored face are the mirror images of its own
+ * entries -- centred fields and tangential velocities even, the normal
+ * velocity odd (zero on the plane) -- set after each CommUp (which fills them
+ * from the coarse level first, so that the corners beyond a frontier take
+ * the mirror of their prolonged values), and after each CommMean into the
+ * level (the images of the cells it overwrites are the restricted values
+ * too, as in the full box).  Both sub-cycles then advance these
+ * ghosts with the level (by the scheme's mirror symmetry they stay the mirror
+ * images within the dependency radius of the active cells), as the
+ * full box advances the same entries as active cells.
+ * Pinned by: a quadrant run equals the quarter y, z > 0 of the full box,
+ * bitwise (1 to 3 levels, both hierarchies). */
+static void mirror_fill(run_t *R, int lvl) {
+  lev_t *L = &R->lev[lvl];
+  const int g = L->g;
+  for (int d = 1; d < 3; ++d) {
+    if (!R->anch[d]) continue;
+    for (int fld = 0; fld < NSTATE; ++fld) {
+      const int normal = (fld == S_VX + d);
+      double *a = L->st[fld];
+      const long sd = STR(L, d);
+      for (int k = -g; k < L->n[2] + g; ++k)
+        for (int j = -g; j < L->n[1] + g; ++j)
+          for (int i = -g; i < L->n[0] + g; ++i) {
+            const int id[3] = {i, j, k};
+            if (id[d] >= 0) continue;
+            const size_t c = IX(L, i, j, k);
+            const long m = id[d];
+            if (normal) a[c] = -a[c - 2 * m * sd];      /* face m < 0 <- face -m */
+            else a[c] = a[c + (-1 - 2 * m) * sd];        /* cell m < 0 <- cell -1-m */
+          }
+    }
+  }
+}
+
+/* the transported set beyond the mirror planes of a finer level: the mirror
+ * images of its cells, the momenta normal to a plane swapped and reversed
+ * (P-_d of an image is -P+_d of its cell), after every transport pass of a
+ * level that takes a finer level's frontier transfers (their images are not
+ * matched otherwise) */
+static void mirror_q(run_t *R, int lvl) {
+  lev_t *L = &R->lev[lvl];
+  const int g = L->g;
+  for (int d = 1; d < 3; ++d) {
+    if (!R->anch[d]) continue;
+    const long sd = STR(L, d);
+    for (int iq = 0; iq < NQ; ++iq) {
+      const int pair = (iq == 2 + 2 * d) ? iq + 1 : ((iq == 3 + 2 * d) ? iq - 1 : -1);
+      double *a = L->q[iq];
+      const double *src = pair >= 0 ? L->q[pair] : L->q[iq];
+      const double sgn = pair >= 0 ? -1.0 : 1.0;
+      for (int k = -g; k < L->n[2] + g; ++k)
+        for (int j = -g; j < L->n[1] + g; ++j)
+          for (int i = -g; i < L->n[0] + g; ++i) {
+            const int id[3] = {i, j, k};
+            if (id[d] >= 0) continue;
+            const size_t c = IX(L, i, j, k);
+            a[c] = sgn * src[c + (-1 - 2 * (long)id[d]) * sd];
+          }
+    }
+  }
+}
+
+static void commup(run_t *R, int lc) {
+  commup_fill(R, lc, 0);
+  if (R->anch[1] || R->anch[2]) mirror_fill(R, lc + 1);
+}
 
 /* CommMean / CommDown (Sect. 3.2.2, Figs. 3-4): coarse centred values in the
  * region covered by the fine level are replaced by the mean of their 8 fine
@@ -867,6 +969,7 @@ static void commmean(run_t *R, int lc) {
           out[IX(C, o[0] + I, o[1] + J, o[2] + K)] = val;
         }
   }
+  if ((R->anch[1] || R->anch[2]) && lc > 0) mirror_fill(R, lc);
 }
 
 /* ---------------------------------------------------------------- cycle */
@@ -1022,7 +1125,9 @@ static void force(run_t *R, double out[3]) {
       for (int d = 0; d < 3; ++d) nadd(&tot[d], pl[d].s + pl[d].c);
     }
   }
-  for (int d = 0; d < 3; ++d) out[d] = tot[d].s + tot[d].c;
+  /* quadrant: the force of the whole gas, the domain's mirror images
+   * included (they cancel the components normal to the mirror planes) */
+  for (int d = 0; d < 3; ++d) out[d] = R->anch[d] ? 0.0 : R->mult * (tot[d].s + tot[d].c);
 }
 
 /* composite totals over uncovered active cells: mass, internal energy,
@@ -1049,10 +1154,11 @@ static void totals(run_t *R, double out[4]) {
           nadd(&ek, 0.5 * r * v2 * vol);
         }
   }
-  out[0] = m.s + m.c;
-  out[1] = ei.s + ei.c;
-  out[2] = ek.s + ek.c;
-  out[3] = R->bflux;
+  /* quadrant: the whole gas (the domain and its mirror images) */
+  out[0] = R->mult * (m.s + m.c);
+  out[1] = R->mult * (ei.s + ei.c);
+  out[2] = R->mult * (ek.s + ek.c);
+  out[3] = R->mult * R->bflux;
 }
 
 /* ---------------------------------------------------------- initial state */
@@ -1105,7 +1211,7 @@ static void cov_box(const run_t *R, int lc, int o[3], int h[3]) {
   const lev_t *C = &R->lev[lc], *F = &R->lev[lc + 1];
   for (int d = 0; d < 3; ++d) {
     h[d] = F->n[d] / 2;
-    o[d] = (C->n[d] - h[d]) / 2;
+    o[d] = R->anch[d] ? 0 : (C->n[d] - h[d]) / 2;  /* quadrant: from the mirror plane */
   }
 }
 
@@ -1129,11 +1235,19 @@ void *dfo_create(const dfo_params *p) {
   for (int m = 0; m < DFO_MAXLEV; ++m) R->xi[m] = 2;
   R->V = p->mach * p->cs;
   R->e0 = p->rho0 * p->cs * p->cs / (p->gamma * (p->gamma - 1.0));
+  /* quadrant: y and z start at the perturber's mirror planes (the paper's
+   * x, y > 0 with its flow along z is here y, z > 0 with the flow along x);
+   * its boundaries are those of the boundary list */
+  if (p->quadrant && p->bcmode != 1) { free(R); return NULL; }
+  R->anch[0] = 0;
+  R->anch[1] = R->anch[2] = p->quadrant ? 1 : 0;
+  R->mult = p->quadrant ? 4.0 : 1.0;
   for (int l = 0; l < R->nl; ++l) {
     lev_t *L = &R->lev[l];
     L->n[0] = p->nx; L->n[1] = p->ny; L->n[2] = p->nz;
     if (l > 0 && p->nx1 > 0) { L->n[0] = p->nx1; L->n[1] = p->ny1; L->n[2] = p->nz1; }
     L->g = (l == 0) ? p->g0 : p->gf;
+    for (int d = 0; d < 3; ++d) L->org[d] = R->anch[d] ? 0.0 : 0.5 * (double)L->n[d];
     L->vol = 1;
     for (int d = 0; d < 3; ++d) { L->s[d] = L->n[d] + 2 * L->g; L->vol *= (size_t)L->s[d]; }
     L->dx = p->dx0 / (double)(1L << l);
@@ -1275,7 +1389,11 @@ int dfo_set_lastface(void *h, int l, int f, const double *in) {
 void dfo_sync(void *h) { restrict_prolong_all((run_t *)h); }
 void dfo_commup(void *h, int lc) { commup((run_t *)h, lc); }
 /* test helper: interpolate every entry of level lc+1 (active ones too) */
-void dfo_prolong_all(void *h, int lc) { commup_fill((run_t *)h, lc, 1); }
+void dfo_prolong_all(void *h, int lc) {
+  run_t *R = (run_t *)h;
+  commup_fill(R, lc, 1);
+  if (R->anch[1] || R->anch[2]) mirror_fill(R, lc + 1);
+}
 void dfo_commmean(void *h, int lc) { commmean((run_t *)h, lc); }
 
 /* single-level stage harness (level 0), with the boundary fills the step

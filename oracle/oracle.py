@@ -49,6 +49,7 @@ class _Params(ctypes.Structure):
         ("mach", ctypes.c_double), ("chi", ctypes.c_double),
         ("subcycle", ctypes.c_int), ("bcmode", ctypes.c_int), ("visc", ctypes.c_double),
         ("nx1", ctypes.c_int), ("ny1", ctypes.c_int), ("nz1", ctypes.c_int),
+        ("quadrant", ctypes.c_int),
     ]
 
 
@@ -107,7 +108,7 @@ class Oracle:
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0=None, gamma=5.0 / 3.0,
                  cfl=0.4, rho0=1.0, cs=1.0, seed=1, noise_amp=1e-6, GM=0.01, eps=0.0,
                  L=0.0, mach=0.5, chi=0.1, g0=3, gf=10, threads=None, subcycle=0, bcmode=0, visc=0.0,
-                 n1=None, lib_path=_LIB):
+                 n1=None, quadrant=False, lib_path=_LIB):
         ny = nx if ny is None else ny
         nz = nx if nz is None else nz
         if dx0 is None:
@@ -119,7 +120,7 @@ class Oracle:
         n1 = tuple(n1) if n1 else (0, 0, 0)
         self.p = _Params(nx, ny, nz, nlevels, g0, gf, dx0, gamma, cfl, rho0, cs, seed,
                          noise_amp, GM, eps, L, mach, chi, int(subcycle), int(bcmode), float(visc),
-                         *[int(v) for v in n1])
+                         *[int(v) for v in n1], int(bool(quadrant)))
         self.n = (nx, ny, nz)
         # cells of each level (levels >= 1 may be half as wide as level 0)
         self.nl = [self.n] + [(n1 if n1[0] else self.n)] * (nlevels - 1)
