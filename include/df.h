@@ -79,7 +79,16 @@ typedef struct df_run df_run;
  *               l+1 covers the central n_{l+1}/2 cells of level l along each
  *               dimension: the central half when all levels have the same
  *               cells, the central quarter of level 0 when the finer levels
- *               have half its cells (the hierarchy of Sects. 4.1.3, 4.2.2). */
+ *               have half its cells (the hierarchy of Sects. 4.1.3, 4.2.2);
+ *  quadrant   : 1: the domain is the paper's quadrant (Sect. 3.4) -- with the
+ *               flow along x here, y > 0 and z > 0, the perturber's vertex on
+ *               the low y and z faces, which are its mirror planes; every
+ *               level starts at the planes (nx, ny, nz count the quadrant's
+ *               cells); level 0 takes the boundary list of Sect. 3.4 (its
+ *               mode 1, the only one df_set_boundaries then accepts), the
+ *               entries of the finer levels beyond the planes are their own
+ *               mirror images; the force and totals are those of the whole
+ *               gas (the domain and its three images: Fy = Fz = 0). */
 typedef struct {
   int32_t nx, ny, nz;
   int32_t nlevels;
@@ -92,6 +101,7 @@ typedef struct {
   double noise_amp;
   int32_t tile_chunk;
   int32_t nx1, ny1, nz1;
+  int32_t quadrant;
 } df_mesh_desc;
 
 /* Validate a mesh description and create a run handle (host memory only; no

@@ -32,6 +32,7 @@ class MeshDesc(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("noise_amp", ctypes.c_double),
         ("tile_chunk", ctypes.c_int32),
         ("nx1", ctypes.c_int32), ("ny1", ctypes.c_int32), ("nz1", ctypes.c_int32),
+        ("quadrant", ctypes.c_int32),
     ]
 
 
@@ -104,17 +105,17 @@ def _dp(a: np.ndarray):
 # ---------------------------------------------------------------- entry points
 
 def mesh_desc(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
-              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None) -> MeshDesc:
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None, quadrant=False) -> MeshDesc:
     n1 = tuple(n1) if n1 else (0, 0, 0)
     return MeshDesc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
-                    tile_chunk, *[int(v) for v in n1])
+                    tile_chunk, *[int(v) for v in n1], int(quadrant))
 
 
 def init_mesh(nx, ny, nz, nlevels, dx0, gamma=5.0 / 3.0, cfl=0.4, precision=DF_FP64,
-              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None) -> int:
+              ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0, n1=None, quadrant=False) -> int:
     lib = _load()
     d = mesh_desc(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed, noise_amp,
-                  tile_chunk, n1)
+                  tile_chunk, n1, quadrant)
     h = ctypes.c_void_p()
     _ck(lib.df_init_mesh(ctypes.byref(d), ctypes.byref(h)))
     return h.value
@@ -240,7 +241,7 @@ class Run:
 
     def __init__(self, nx, ny=None, nz=None, *, nlevels=1, dx0, gamma=5.0 / 3.0, cfl=0.4,
                  precision=DF_FP64, ghost_fine=0, seed=1, noise_amp=1e-6, tile_chunk=0,
-                 n1=None, device="cuda"):
+                 n1=None, quadrant=False, device="cuda"):
         import torch
 
         ny = nx if ny is None else ny
@@ -250,7 +251,7 @@ class Run:
         # cells of each level (the finer levels may have their own, n1)
         self.nl = [self.n] + [tuple(n1) if n1 else self.n] * (nlevels - 1)
         self._h = init_mesh(nx, ny, nz, nlevels, dx0, gamma, cfl, precision, ghost_fine, seed,
-                            noise_amp, tile_chunk, n1)
+                            noise_amp, tile_chunk, n1, quadrant)
         self.nbytes = required_bytes(self._h)
         self.device = torch.device(device)
         self.arena = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
@@ -382,7 +383,7 @@ def engine_job_bytes(cfg: dict, precision=DF_FP64, tile_chunk=0) -> int:
 def _desc_of(cfg, precision, tile_chunk):
     return mesh_desc(cfg["nx"], cfg["ny"], cfg["nz"], cfg["nlevels"], cfg["dx0"], cfg.get("gamma", 5.0 / 3.0),
                      cfg.get("cfl", 0.4), precision, cfg.get("ghost_fine", 0), cfg.get("seed", 1),
-                     cfg.get("noise_amp", 1e-6), tile_chunk, cfg.get("n1"))
+                     cfg.get("noise_amp", 1e-6), tile_chunk, cfg.get("n1"), cfg.get("quadrant", False))
 
 
 class Engine:

@@ -79,6 +79,8 @@ struct df_run {
   int xi[MAXLEV];          // sub-steps of level l+1 per step of level l (last coarse step)
   double up[MAXLEV + 1];   // staging of the host-chosen step lengths and time
   double eps = 0.0;
+  bool quad = false;   // the domain is the quadrant y, z > 0 (Sect. 3.4)
+  double mult = 1.0;   // copies of the domain in the whole gas (4 on the quadrant)
   // optional per-kernel-kind timing: event pairs around launches
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -127,19 +129,26 @@ void carve(df_run *R, char *base) {
 // the eight cells around the perturber's vertex; sigma = 0 gives those eight
 // cells 1/8 each (the split of Sect. 3.4).  Stored on the smallest centred box
 // of active cells that holds every non-zero weight.
-void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3]) {
+// On the quadrant the box starts at the mirror planes and the weights are
+// normalised over the cells and their mirror images (mult copies): the
+// domain's cells take a quarter of the release, each its full-box share.
+void heat_table(const Geo &G, double sigma, double mult, std::vector<double> &w, int edge[3]) {
   double dx = G.dx;
-  auto cen = [&](int d, int i) { return ((double)i - 0.5 * (double)G.n[d] + 0.5) * dx; };
+  auto cen = [&](int d, int i) { return ((double)i - G.org[d] + 0.5) * dx; };
   double r2min = 3.0 * (0.5 * dx) * (0.5 * dx);
   double rcut = std::sqrt(r2min) + 8.0 * sigma;
   int half = (sigma == 0.0) ? 1 : (int)std::ceil(rcut / dx) + 1;
-  for (int d = 0; d < 3; ++d) edge[d] = 2 * half < G.n[d] ? 2 * half : G.n[d];
+  for (int d = 0; d < 3; ++d) {
+    const int want = G.anch[d] ? half : 2 * half;
+    edge[d] = want < G.n[d] ? want : G.n[d];
+  }
   w.assign((size_t)edge[0] * edge[1] * edge[2], 0.0);
   double sum = 0.0;
+  auto first = [&](int d) { return G.anch[d] ? 0 : G.n[d] / 2 - edge[d] / 2; };
   for (int c = 0; c < edge[2]; ++c)
     for (int b = 0; b < edge[1]; ++b)
       for (int a = 0; a < edge[0]; ++a) {
-        int i = G.n[0] / 2 - edge[0] / 2 + a, j = G.n[1] / 2 - edge[1] / 2 + b, k = G.n[2] / 2 - edge[2] / 2 + c;
+        int i = first(0) + a, j = first(1) + b, k = first(2) + c;
         double x = cen(0, i), y = cen(1, j), z = cen(2, k);
         double r2 = x * x + y * y + z * z;
         double g = 0.0;
@@ -148,7 +157,7 @@ void heat_table(const Geo &G, double sigma, std::vector<double> &w, int edge[3])
         w[((size_t)c * edge[1] + b) * edge[0] + a] = g;
         sum += g;
       }
-  for (double &x : w) x /= sum;
+  for (double &x : w) x /= sum * mult;
 }
 
 // ---------------------------------------------------------------- timing
@@ -216,8 +225,14 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
     TScope t(R, K_PASSXY);
     dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
   } else {
+    // quadrant: a middle level takes the finer level's frontier transfers,
+    // whose images lie beyond the planes: the transported set's images are
+    // set again after every pass
+    const bool mq = Gf && G.level > 0;
     { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
+    if (mq) dfk::mirror_q(st, G, P, B, 1 - c);
     { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, Bt, 1 - c, dtp, scale, Gf, facc, R->chunk); }
+    if (mq) dfk::mirror_q(st, G, P, B, c);
   }
   // the z pass and the rebuild take the set the y pass wrote (q[c] after
   // separate passes, q[1-c] after the fused ones)
@@ -234,6 +249,7 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
   }
   if (!zf) {
     { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
+    if (Gf && G.level > 0) dfk::mirror_q(st, G, P, B, 1 - cy);
     { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, post); }
   }
   R->cur[l] = 1 - cy;
@@ -248,10 +264,14 @@ void cycle(df_run *R, int l) {
   if (l + 1 < R->nl) {
     { TScope t(R, K_COMMUP);
       dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
-                  R->cur[l + 1]); }
+                  R->cur[l + 1]);
+      // quadrant: the finer level's entries beyond the planes are its images
+      dfk::mirror_state(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1]); }
     { TScope t(R, K_COMMMEAN);
       dfk::commmean(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
-                    R->cur[l]); }
+                    R->cur[l]);
+      // and so are the images of the cells the restriction overwrote
+      dfk::mirror_state(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l]); }
   }
 }
 
@@ -275,12 +295,16 @@ void force_reduce(df_run *R, int slot) {
 }
 
 void sync_levels(df_run *R) {
-  for (int l = R->nl - 2; l >= 0; --l)
+  for (int l = R->nl - 2; l >= 0; --l) {
     dfk::commmean(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1], R->geo[l], R->buf[l],
                   R->cur[l]);
-  for (int l = 0; l + 1 < R->nl; ++l)
+    dfk::mirror_state(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l]);
+  }
+  for (int l = 0; l + 1 < R->nl; ++l) {
     dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
                 R->cur[l + 1]);
+    dfk::mirror_state(R->stream, R->geo[l + 1], R->phys, R->buf[l + 1], R->cur[l + 1]);
+  }
 }
 
 void *field_ptr(df_run *R, int l, int f) {
@@ -432,6 +456,7 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     if (d->nlevels > 1 && (n[k] % 4 != 0 || n[k] < 16))
       return fail(DF_EINVAL, "nested runs need cell counts that are multiples of 4 and >= 16");
   }
+  if (d->quadrant != 0 && d->quadrant != 1) return fail(DF_EINVAL, "quadrant must be 0 or 1");
   // cells of the finer levels (0: those of level 0)
   const bool own1 = d->nx1 != 0 || d->ny1 != 0 || d->nz1 != 0;
   const int n1[3] = {own1 ? d->nx1 : d->nx, own1 ? d->ny1 : d->ny, own1 ? d->nz1 : d->nz};
@@ -452,6 +477,8 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
   R->nl = d->nlevels;
   R->esz = d->precision == DF_FP32 ? 4 : 8;
   R->chunk = d->tile_chunk ? d->tile_chunk : (d->precision == DF_FP32 ? 16 : 32);
+  R->quad = d->quadrant == 1;
+  R->mult = R->quad ? 4.0 : 1.0;
   for (int m = 0; m < MAXLEV; ++m) R->xi[m] = 2;
   R->phys.fp32 = d->precision == DF_FP32;
   for (int l = 0; l < R->nl; ++l) {
@@ -466,12 +493,16 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     G.off = px + G.g * G.sy + G.g * G.sz;
     G.dx = std::ldexp(d->dx0, -l);
     G.level = l;
-    G.bc = (l == 0);
+    // the quadrant's level 0 takes the boundary list of Sect. 3.4
+    G.bc = (l == 0) ? (R->quad ? 2 : 1) : 0;
     G.has_fine = (l + 1 < R->nl);
-    // the finer level's cells cover the central n1/2 cells of this one
+    // the finer level's cells cover the central n1/2 cells of this one (on
+    // the quadrant: from the mirror planes along y and z)
     for (int k = 0; k < 3; ++k) {
+      G.anch[k] = R->quad && k > 0;
+      G.org[k] = G.anch[k] ? 0.0 : 0.5 * (double)G.n[k];
       G.cn[k] = G.has_fine ? n1[k] / 2 : 0;
-      G.co[k] = G.has_fine ? (G.n[k] - G.cn[k]) / 2 : 0;
+      G.co[k] = G.has_fine ? (G.anch[k] ? 0 : (G.n[k] - G.cn[k]) / 2) : 0;
     }
     R->vol[l] = (size_t)G.sz * G.s[2];
     if (R->vol[l] >= ((size_t)1 << 31)) {
@@ -539,7 +570,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
   for (int l = 0; l < R->nl; ++l) {
     std::vector<double> w;
     int edge[3] = {0, 0, 0};
-    heat_table(R->geo[l], eps, w, edge);
+    heat_table(R->geo[l], eps, R->mult, w, edge);
     for (int d = 0; d < 3; ++d) R->buf[l].hw_n[d] = edge[d];
     rc = hip_check(hipMemcpyAsync(R->buf[l].hw, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, st),
                    "heat table upload");
@@ -563,6 +594,8 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
       if (B.vk[k]) dfk::zero(st, B.vk[k], R->vol[l] * R->esz);
   }
   Scal zero{};
+  for (int q = 0; q < 3; ++q) zero.fmul[q] = (q > 0 && R->quad) ? 0.0 : R->mult;
+  zero.tmul = R->mult;
   rc = hip_check(hipMemcpyAsync(R->scal, &zero, sizeof(Scal), hipMemcpyHostToDevice, st), "scalars");
   if (rc) return rc;
   sync_levels(R);
@@ -636,6 +669,7 @@ int df_set_boundaries(df_run *R, int32_t mode) {
   int rc = check_run(R, false);
   if (rc) return rc;
   if (mode != 0 && mode != 1) return fail(DF_EINVAL, "boundary mode must be 0 or 1");
+  if (R->quad && mode != 1) return fail(DF_EINVAL, "the quadrant takes the boundary list of Sect. 3.4 (mode 1)");
   R->geo[0].bc = mode == 1 ? 2 : 1;
   R->sig_valid = false;
   return DF_OK;

@@ -31,6 +31,8 @@ struct Geo {
   int has_fine;  // a finer level covers a central box of this level
   int co[3];     // that box: first covered cell and number of covered cells (the
   int cn[3];     // finer level's cell count / 2), centred on the perturber's vertex
+  int anch[3];   // quadrant: the dimension starts at the perturber's mirror plane
+  double org[3]; // index of the perturber's vertex along each dimension (n/2, or 0 when anchored)
 };
 
 // Gas and perturber parameters (code units).  The fields are stored as
@@ -62,6 +64,11 @@ struct Scal {
   unsigned long long smax[NSLOT];
   double tlog;               // time of the state whose force partials await the log
   int pending;               // 1: the end-of-step force partials are not logged yet
+  // the whole gas from the domain's sums: 1 for the full box; on the quadrant
+  // 4 (the domain and its three mirror images) for Fx and the totals, 0 for
+  // the force components normal to the mirror planes
+  double fmul[3];
+  double tmul;
 };
 
 constexpr int FLOG = 4096;   // force-log ring: (Fx, Fy, Fz, t) per coarse step
@@ -141,6 +148,12 @@ void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc,
             LevBufs &Bf, int curf);
 void commmean(hipStream_t st, const Geo &Gf, const Phys &P, LevBufs &Bf, int curf, const Geo &Gc,
               LevBufs &Bc, int curc);
+// quadrant, finer levels: the entries beyond the mirror planes as the images
+// of the level's own (rho, e of q[cur] and the face velocities; or the
+// transported set q[set], the momenta normal to a plane swapped and reversed);
+// nothing on level 0 or off the quadrant
+void mirror_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur);
+void mirror_q(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int set);
 // per-block maxima of the signal speed of one level into the signal region of
 // B.part; health flag
 void signal_speed(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S);

@@ -147,7 +147,7 @@ __device__ __forceinline__ void from_lanes(V v, T (&a)[W]) {
 // cell-centre coordinate: the perturber is the central vertex of the level
 template <typename T>
 __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
-  return (T)(((double)i - 0.5 * (double)G.n[d] + 0.5) * G.dx);
+  return (T)(((double)i - G.org[d] + 0.5) * G.dx);
 }
 
 // Quotient and square root in the storage type, from the hardware reciprocal
@@ -584,9 +584,12 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
     en = dec + qdiv(dt * (T)(P.chi * P.rho0) * lap, (T)(G.dx * G.dx));
   }
   if (A.do_heat && A.hw_n[0] > 0) {
-    const int a = i - A.hw_lo[0], b = j - A.hw_lo[1], d = k - A.hw_lo[2];
-    if (a >= 0 && b >= 0 && d >= 0 && a < A.hw_n[0] && b < A.hw_n[1] && d < A.hw_n[2] && i >= 0 && j >= 0 &&
-        k >= 0 && i < G.n[0] && j < G.n[1] && k < G.n[2]) {
+    // quadrant: the entries beyond a mirror plane are the images of the
+    // level's cells and are heated as their cells are
+    const int jj = (G.anch[1] && j < 0) ? -1 - j : j, kk = (G.anch[2] && k < 0) ? -1 - k : k;
+    const int a = i - A.hw_lo[0], b = jj - A.hw_lo[1], d = kk - A.hw_lo[2];
+    if (a >= 0 && b >= 0 && d >= 0 && a < A.hw_n[0] && b < A.hw_n[1] && d < A.hw_n[2] && i >= 0 && jj >= 0 &&
+        kk >= 0 && i < G.n[0] && jj < G.n[1] && kk < G.n[2]) {
       const double w = A.hw[((long)d * A.hw_n[1] + b) * A.hw_n[0] + a];
       if (w != 0.0) en += (T)(P.L * (A.fac * A.dtp[0]) * w / (G.dx * G.dx * G.dx));
     }
@@ -1806,6 +1809,36 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A)
     }
 }
 
+// ------------------------------------------------------ quadrant images
+// The entries of a finer level beyond an anchored face (the perturber's mirror
+// plane, Sect. 3.4) as the mirror images of the level's own entries:
+// dst = sgn src at the mirror position -- cell j < 0 takes cell -1-j, a face
+// normal to the plane j < 0 takes face -j.  One launch per plane, every
+// listed field at each position.
+template <typename T>
+struct MirArgs {
+  T *dst[NQ];
+  const T *src[NQ];
+  T sgn[NQ];
+  int face[NQ];  // the field lives on the faces normal to the plane
+  int nf;
+  int d;         // the plane's normal (1 or 2)
+  Box b;         // the entries beyond the plane
+};
+
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_mirror(Geo G, MirArgs<T> A) {
+  int i, j, k;
+  if (!thread_cell(A.b, i, j, k)) return;
+  const int id[3] = {i, j, k};
+  const int m = id[A.d];  // < 0
+  const idx_t c = lin(G, i, j, k), sd = dstride(G, A.d);
+  for (int f = 0; f < A.nf; ++f) {
+    const idx_t src = A.face[f] ? c - 2 * m * sd : c + (-1 - 2 * m) * sd;
+    A.dst[f][c] = A.sgn[f] * A.src[f][src];
+  }
+}
+
 // ------------------------------------------------------------ CommMean
 
 template <typename T>
@@ -1962,7 +1995,7 @@ __device__ void final3_finish(const FinalArgs &A, const double (*sh)[FW]) {
   for (int q = 0; q < 3; ++q) {
     double t = 0.0;
     for (int v = 0; v < FW; ++v) t += sh[q][v];
-    A.out[q] = t;
+    A.out[q] = t * (A.out == A.S->totals ? A.S->tmul : A.S->fmul[q]);
   }
   if (A.flog) {
     const unsigned int n = A.S->nlog;
@@ -2060,6 +2093,7 @@ __device__ void log_pending_body(const double *part, int n, Scal *S, double *flo
     for (int q = 0; q < 3; ++q) {
       double t = 0.0;
       for (int v = 0; v < NW; ++v) t += sh[q][v];
+      t *= S->fmul[q];
       S->force[q] = t;
       e[q] = t;
     }
@@ -3123,7 +3157,7 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.hw = B.hw;
   for (int d = 0; d < 3; ++d) {
     A.hw_n[d] = B.hw_n[d];
-    A.hw_lo[d] = G.n[d] / 2 - B.hw_n[d] / 2;
+    A.hw_lo[d] = G.anch[d] ? 0 : G.n[d] / 2 - B.hw_n[d] / 2;
   }
   A.dtp = dtp;
   A.fac = fac;
@@ -3381,9 +3415,11 @@ static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const
     A.stag = f >= 2 ? f - 2 : -1;
     A.Q = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
     A.out = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
-    // hosts of the stored fine entries [-g, n+g) along each axis
+    // hosts of the stored fine entries [-g, n+g) along each axis (from the
+    // mirror plane along an anchored one: the entries beyond it are the fine
+    // level's own images, set after the fill)
     for (int d = 0; d < 3; ++d) {
-      A.b.lo[d] = fdiv2_host(-Gf.g);
+      A.b.lo[d] = Gf.anch[d] ? 0 : fdiv2_host(-Gf.g);
       A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
     }
     if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
@@ -3395,6 +3431,65 @@ void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc,
             int curf) {
   if (P.fp32) commup_t<float>(st, Gc, Bc, curc, Gf, Bf, curf);
   else commup_t<double>(st, Gc, Bc, curc, Gf, Bf, curf);
+}
+
+template <typename T>
+static void mirror_state_t(hipStream_t st, const Geo &G, LevBufs &B, int cur) {
+  for (int d = 1; d < 3; ++d) {
+    if (!G.anch[d]) continue;
+    MirArgs<T> A{};
+    A.nf = 5;
+    for (int f = 0; f < 5; ++f) {
+      T *a = tp<T>(f < 2 ? B.q[cur][f] : B.v[f - 2]);
+      A.dst[f] = a;
+      A.src[f] = a;
+      A.sgn[f] = (f == 2 + d) ? T(-1) : T(1);  // the velocity normal to the plane is odd
+      A.face[f] = 0;
+    }
+    A.face[2 + d] = 1;
+    A.d = d;
+    for (int e = 0; e < 3; ++e) {
+      A.b.lo[e] = -G.g;
+      A.b.hi[e] = e == d ? 0 : G.s[e] - G.g;
+    }
+    DFK_LAUNCH(k_mirror<T>, grid_of(A.b), dim3(BX, BY), st, G, A);
+  }
+}
+
+template <typename T>
+static void mirror_q_t(hipStream_t st, const Geo &G, LevBufs &B, int set) {
+  for (int d = 1; d < 3; ++d) {
+    if (!G.anch[d]) continue;
+    MirArgs<T> A{};
+    A.nf = NQ;
+    for (int m = 0; m < NQ; ++m) {
+      // the momenta normal to the plane swap and change sign: P-_d of an
+      // image is -P+_d of its cell
+      const int pair = (m == 2 + 2 * d) ? m + 1 : ((m == 3 + 2 * d) ? m - 1 : m);
+      A.dst[m] = tp<T>(B.q[set][m]);
+      A.src[m] = tp<T>(B.q[set][pair]);
+      A.sgn[m] = pair != m ? T(-1) : T(1);
+      A.face[m] = 0;
+    }
+    A.d = d;
+    for (int e = 0; e < 3; ++e) {
+      A.b.lo[e] = -G.g;
+      A.b.hi[e] = e == d ? 0 : G.s[e] - G.g;
+    }
+    DFK_LAUNCH(k_mirror<T>, grid_of(A.b), dim3(BX, BY), st, G, A);
+  }
+}
+
+void mirror_state(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {
+  if (G.bc || !(G.anch[1] || G.anch[2])) return;
+  if (P.fp32) mirror_state_t<float>(st, G, B, cur);
+  else mirror_state_t<double>(st, G, B, cur);
+}
+
+void mirror_q(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int set) {
+  if (G.bc || !(G.anch[1] || G.anch[2])) return;
+  if (P.fp32) mirror_q_t<float>(st, G, B, set);
+  else mirror_q_t<double>(st, G, B, set);
 }
 
 template <typename T>

@@ -32,6 +32,7 @@ def test_library_exports_every_declared_symbol():
     dict(nx=33), dict(nlevels=0), dict(nlevels=13), dict(dx0=0.0), dict(gamma=1.0),
     dict(cfl=0.0), dict(cfl=1.5), dict(precision=7), dict(nlevels=2, nx=18),
     dict(nlevels=2, nx=12, ny=12, nz=12), dict(nlevels=2, ghost_fine=6), dict(noise_amp=0.7),
+    dict(quadrant=2),
 ])
 def test_init_mesh_rejects_bad_descriptions(bad):
     import paper_1812_03191_amd as dfm
