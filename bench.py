@@ -92,7 +92,8 @@ def step_traffic_from_profiles():
         d = json.load(fh)
     if d.get("source_hash") != dfk_hash():
         return None
-    return sum(k["bytes_per_launch"] for k in d.get("kernels", {}).values())
+    # the end-of-run partials (post) are taken once per run, not per step
+    return sum(v["bytes_per_launch"] for k, v in d.get("kernels", {}).items() if k != "post")
 
 
 def host_threads():
