@@ -231,6 +231,18 @@ int df_set_kick_fusion(df_run *run, int32_t on);
  * DF_EINVAL for other values. */
 int df_set_finish_fusion(df_run *run, int32_t on);
 
+/* Launch form of df_step on nested runs (the recursion of Sects. 3.1 and 3.3:
+ * a few hundred short launches per coarse step): on (1, default) the launches
+ * of two coarse steps are captured once into a HIP graph on a private stream
+ * and df_step replays it on the bound stream (n / 2 replays; an odd last step
+ * and runs with kernel timing enabled are launched directly); a graph is kept
+ * per pattern of the levels' current buffer sets and captured again after any
+ * call that changes the launches (perturber, boundaries, viscosity, launch
+ * switches, sub-cycling, bind).  off (0): every launch is made directly.  The
+ * results are bitwise the same either way; DF_EINVAL for other values.
+ * Single-level runs are always launched directly. */
+int df_set_step_graphs(df_run *run, int32_t on);
+
 /* Outer boundary conditions of level 0 (Sect. 3.4).  mode 0 (default): the
  * gas enters through x_max with the unperturbed state (rho0, -V, 0, 0, e0) and
  * every other boundary is zero-gradient outflow.  mode 1: the paper's list,
@@ -286,9 +298,14 @@ int df_destroy(df_run *run);
  * budget, and a stream.  Each admitted job is a run carved from a free range of
  * the arena.  df_engine_step advances every active job by 2 coarse steps per
  * call of its count: the launches of all active jobs are captured into one HIP
- * graph, spread over nstreams worker streams so that jobs overlap on the
- * device, and replayed on the caller's stream; the graph is captured again
- * when the set of jobs changes.  A job's results are bitwise those of the same
+ * graph and replayed on the caller's stream; the graph is captured again when
+ * the set of jobs changes.  Single-level jobs whose step takes the fused
+ * launches (at most 128 cells along x, the default boundaries) advance
+ * together: one launch per stage carries the blocks of all of them, each
+ * block reading its job's launch arguments from a device table (allocated by
+ * the engine outside the arena, a few hundred bytes per job and stage); the
+ * other jobs' own launches are spread over nstreams worker streams so that
+ * they overlap on the device.  A job's results are bitwise those of the same
  * job run alone.  Jobs run a multiple of 2 coarse steps (nsteps rounded up). */
 typedef struct df_engine df_engine;
 
@@ -324,8 +341,10 @@ int df_engine_get_field(df_engine *eng, int32_t slot, int32_t level, int32_t fie
 /* Free a job's slot and arena range (synchronises). */
 int df_engine_release(df_engine *eng, int32_t slot);
 
-/* out[0] graph replays, out[1] graph captures since creation. */
-int df_engine_stats(df_engine *eng, int64_t out[2]);
+/* out[0] graph replays, out[1] graph captures since creation, out[2] jobs
+ * advanced by the batched launches of the current graph (one launch per stage
+ * for all of them). */
+int df_engine_stats(df_engine *eng, int64_t out[3]);
 
 int df_engine_destroy(df_engine *eng);
 

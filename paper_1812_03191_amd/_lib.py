@@ -77,6 +77,7 @@ def _load():
         "df_set_transport_fusion": [vp, i32],
         "df_set_kick_fusion": [vp, i32],
         "df_set_finish_fusion": [vp, i32],
+        "df_set_step_graphs": [vp, i32],
         "df_set_viscosity": [vp, ctypes.c_double],
         "df_get_schedule": [vp, ctypes.POINTER(i32), i32],
         "df_force_density": [vp, i32, i32, i32] + [ctypes.c_double] * 4 + [vp, vp],
@@ -309,6 +310,10 @@ class Run:
         """fuse a single-level step's z pass with the rebuild and kick where it qualifies (default on)"""
         _ck(_load().df_set_finish_fusion(self._h, int(bool(on))))
 
+    def set_step_graphs(self, on: bool) -> None:
+        """replay HIP graphs of two coarse steps in step() on nested runs (default on)"""
+        _ck(_load().df_set_step_graphs(self._h, int(bool(on))))
+
     def schedule(self) -> list:
         """sub-steps of level l+1 per step of level l in the last coarse step"""
         n = max(1, self.nlevels - 1)
@@ -452,6 +457,6 @@ class Engine:
         _ck(_load().df_engine_release(self._h, int(slot)))
 
     def stats(self):
-        out = (ctypes.c_int64 * 2)()
+        out = (ctypes.c_int64 * 3)()
         _ck(_load().df_engine_stats(self._h, out))
-        return {"replays": out[0], "captures": out[1]}
+        return {"replays": out[0], "captures": out[1], "batched": out[2]}

@@ -2,15 +2,20 @@
 
 The streaming y and z transport passes walk column segments of ``tile_chunk``
 cells: short segments give more waves but reload more halo cells, long ones the
-reverse, and the best length depends on the mesh and the storage type.  The
-choice changes only the launch shape, never the results (each face transfer is
-computed the same way whichever segment holds it).  ``best_chunk`` times a few
-steps of a scratch run for each candidate and caches the winner per
-(mesh, levels, precision) in a JSON file (``DFMESH_TUNE_CACHE`` or
-``~/.cache/dfmesh/autotune.json``).  The winner is the longest segment whose
-lone-run time is within ``SLACK`` of the fastest: jobs of the batching engine
-share the GPU, where the halo rows a short segment recomputes cost throughput
-that a lone run hides behind its extra waves.
+reverse, and the best length depends on the mesh, the storage type and how
+full the GPU is.  The choice changes only the launch shape, never the results
+(each face transfer is computed the same way whichever segment holds it).
+``best_chunk`` times each candidate and caches the winner per (mesh,
+precision, context) in a JSON file (``DFMESH_TUNE_CACHE`` or
+``~/.cache/dfmesh/autotune.json``):
+
+* batched (the default, for the engine): copies of the job advanced together
+  by an engine, enough of them to fill the GPU (about 16 M cells, at most 64
+  copies), as the engine's batched launches run them; the winner is the fastest
+  per job-step.
+* alone: a scratch run by itself; the winner is the longest segment within
+  ``SLACK`` of the fastest (a lone run hides a short segment's halo rows behind
+  its extra waves, which a shared GPU does not).
 """
 from __future__ import annotations
 
@@ -74,8 +79,38 @@ def time_chunk(cfg: dict, precision: int, chunk: int, *, steps=6, warmup=2) -> f
     return e0.elapsed_time(e1) / steps
 
 
-def best_chunk(cfg: dict, precision: int, *, use_cache=True) -> int:
-    k = key(cfg, precision)
+BATCH_CELLS = 16 << 20
+MAX_COPIES = 64
+
+
+def time_chunk_batched(cfg: dict, precision: int, chunk: int, *, steps=6, warmup=2) -> float:
+    """milliseconds per job-step of copies of a single-level run of this mesh
+    advanced together by an engine with this segment length"""
+    import torch
+
+    from ._lib import Engine, engine_job_bytes
+
+    one = dict(cfg, nlevels=1)
+    one.pop("n1", None)
+    copies = max(1, min(MAX_COPIES, -(-BATCH_CELLS // (cfg["nx"] * cfg["ny"] * cfg["nz"]))))
+    eng = Engine(copies * engine_job_bytes(one, precision) + (64 << 20))
+    for _ in range(copies):
+        if eng.admit(one, steps + warmup, precision=precision, tile_chunk=chunk) is None:
+            raise RuntimeError("autotune: engine budget too small")
+    eng.step(warmup // 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(eng.stream)
+    eng.step(steps // 2)
+    e1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (steps * copies)
+    del eng
+    return ms
+
+
+def best_chunk(cfg: dict, precision: int, *, use_cache=True, batched=True) -> int:
+    k = key(cfg, precision) + (":batched" if batched else "")
     with _lock:
         if k in _mem:
             return _mem[k]
@@ -84,9 +119,13 @@ def best_chunk(cfg: dict, precision: int, *, use_cache=True) -> int:
             if k in d:
                 _mem[k] = int(d[k]["chunk"])
                 return _mem[k]
-    times = {c: time_chunk(cfg, precision, c) for c in CANDIDATES}
-    fastest = min(times.values())
-    best = max(c for c in CANDIDATES if times[c] <= (1.0 + SLACK) * fastest)
+    if batched:
+        times = {c: time_chunk_batched(cfg, precision, c) for c in CANDIDATES}
+        best = min(CANDIDATES, key=lambda c: times[c])
+    else:
+        times = {c: time_chunk(cfg, precision, c) for c in CANDIDATES}
+        fastest = min(times.values())
+        best = max(c for c in CANDIDATES if times[c] <= (1.0 + SLACK) * fastest)
     with _lock:
         _mem[k] = best
         if use_cache:

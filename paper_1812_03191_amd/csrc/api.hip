@@ -81,6 +81,15 @@ struct df_run {
   double eps = 0.0;
   bool quad = false;   // the domain is the quadrant y, z > 0 (Sect. 3.4)
   double mult = 1.0;   // copies of the domain in the whole gas (4 on the quadrant)
+  // nested runs: df_step replays a HIP graph of two coarse steps (which bring
+  // every buffer back to its role), one per pattern of the levels' current
+  // sets, captured on a private stream; any call that changes a launch's
+  // arguments or form marks them stale
+  bool use_graphs = true;
+  bool graphs_stale = false;
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  unsigned gpat[2] = {0, 0};
   // optional per-kernel-kind timing: event pairs around launches
   bool timing = false;
   std::vector<hipEvent_t> ev;
@@ -425,6 +434,68 @@ void enqueue_steps(df_run *R, int n) {
   R->sig_valid = true;
 }
 
+unsigned cur_pattern(const df_run *R) {
+  unsigned p = 0;
+  for (int l = 0; l < R->nl; ++l) p |= (unsigned)R->cur[l] << l;
+  return p;
+}
+
+// destroy the step graphs (after the stream has run every replay)
+int drop_graphs(df_run *R) {
+  int rc = DF_OK;
+  if (R->gexec[0] || R->gexec[1]) rc = hip_check(hipStreamSynchronize(R->stream), "graph release");
+  for (int s = 0; s < 2; ++s) {
+    if (R->gexec[s]) (void)hipGraphExecDestroy(R->gexec[s]);
+    R->gexec[s] = nullptr;
+  }
+  R->graphs_stale = false;
+  return rc;
+}
+
+// k replays of two coarse steps each: the arithmetic of enqueue_steps(R, 2k)
+// (the step length of each replay's first step is taken from the same
+// partials by the replay's opening reduction), so the results are bitwise
+// those of the eager steps
+int graph_steps(df_run *R, int k) {
+  int rc = DF_OK;
+  if (R->graphs_stale) rc = drop_graphs(R);
+  if (rc) return rc;
+  if (!R->sig_valid) post_reduce(R);  // eagerly: the graph starts from valid partials
+  const unsigned pat = cur_pattern(R);
+  int s = -1;
+  for (int q = 0; q < 2; ++q)
+    if (R->gexec[q] && R->gpat[q] == pat) s = q;
+  if (s < 0) {
+    s = R->gexec[0] ? 1 : 0;
+    if (R->gexec[s]) {
+      rc = hip_check(hipStreamSynchronize(R->stream), "graph release");
+      if (rc) return rc;
+      (void)hipGraphExecDestroy(R->gexec[s]);
+      R->gexec[s] = nullptr;
+    }
+    if (!R->gstream) {
+      rc = hip_check(hipStreamCreateWithFlags(&R->gstream, hipStreamNonBlocking), "graph stream");
+      if (rc) return rc;
+    }
+    rc = hip_check(hipStreamBeginCapture(R->gstream, hipStreamCaptureModeRelaxed), "graph capture");
+    if (rc) return rc;
+    hipStream_t user = R->stream;
+    R->stream = R->gstream;
+    enqueue_steps(R, 2);
+    R->stream = user;
+    hipGraph_t g = nullptr;
+    rc = hip_check(hipStreamEndCapture(R->gstream, &g), "graph capture end");
+    if (rc) return rc;
+    rc = hip_check(hipGraphInstantiate(&R->gexec[s], g, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(g);
+    if (rc) return rc;
+    R->gpat[s] = pat;
+    if (cur_pattern(R) != pat) return fail(DF_ESTATE, "two coarse steps did not restore the buffer roles");
+  }
+  for (int i = 0; i < k && !rc; ++i) rc = hip_check(hipGraphLaunch(R->gexec[s], R->stream), "graph launch");
+  return rc;
+}
+
 }  // namespace
 
 // ================================================================== ABI
@@ -540,6 +611,7 @@ int df_bind(df_run *R, void *dev_ptr, size_t bytes, void *stream) {
   if (rc) return rc;
   R->bound = true;
   R->ready = false;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -605,6 +677,7 @@ int df_set_perturber(df_run *R, double GM, double eps, double L, double mach, do
   rc = hip_check(hipStreamSynchronize(st), "df_set_perturber");
   if (rc) return rc;
   R->ready = true;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -619,8 +692,24 @@ int df_step(df_run *R, int32_t n) {
     }
     return DF_OK;
   }
+  // nested runs replay graphs of two coarse steps (one per-step launch
+  // sequence has a few hundred short kernels); timing runs stay eager
+  if (R->nl > 1 && R->use_graphs && !R->timing && n >= 2) {
+    rc = graph_steps(R, n / 2);
+    if (rc) return rc;
+    n %= 2;
+  }
   enqueue_steps(R, n);
   return launch_check("df_step");
+}
+
+int df_set_step_graphs(df_run *R, int32_t on) {
+  int rc = check_run(R, false);
+  if (rc) return rc;
+  if (on != 0 && on != 1) return fail(DF_EINVAL, "step graphs must be 0 or 1");
+  R->use_graphs = on == 1;
+  R->graphs_stale = true;
+  return DF_OK;
 }
 
 int df_set_subcycling(df_run *R, int32_t mode) {
@@ -629,6 +718,7 @@ int df_set_subcycling(df_run *R, int32_t mode) {
   if (mode != 0 && mode != 1) return fail(DF_EINVAL, "sub-cycling mode must be 0 or 1");
   R->subcycle = mode;
   for (int m = 0; m < MAXLEV; ++m) R->xi[m] = 2;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -638,6 +728,7 @@ int df_set_viscosity(df_run *R, double c2) {
   if (!std::isfinite(c2) || c2 < 0.0) return fail(DF_EINVAL, "viscosity coefficient must be finite and >= 0");
   R->visc = c2;
   R->phys.visc = c2;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -646,6 +737,7 @@ int df_set_transport_fusion(df_run *R, int32_t on) {
   if (rc) return rc;
   if (on != 0 && on != 1) return fail(DF_EINVAL, "transport fusion must be 0 or 1");
   R->fuse_xy = on == 1;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -654,6 +746,7 @@ int df_set_kick_fusion(df_run *R, int32_t on) {
   if (rc) return rc;
   if (on != 0 && on != 1) return fail(DF_EINVAL, "kick fusion must be 0 or 1");
   R->fuse_kc = on == 1;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -662,6 +755,7 @@ int df_set_finish_fusion(df_run *R, int32_t on) {
   if (rc) return rc;
   if (on != 0 && on != 1) return fail(DF_EINVAL, "finish fusion must be 0 or 1");
   R->fuse_zf = on == 1;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -672,6 +766,7 @@ int df_set_boundaries(df_run *R, int32_t mode) {
   if (R->quad && mode != 1) return fail(DF_EINVAL, "the quadrant takes the boundary list of Sect. 3.4 (mode 1)");
   R->geo[0].bc = mode == 1 ? 2 : 1;
   R->sig_valid = false;
+  R->graphs_stale = true;
   return DF_OK;
 }
 
@@ -924,6 +1019,8 @@ int df_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {
 
 int df_destroy(df_run *R) {
   if (!R) return fail(DF_EINVAL, "null run handle");
+  if (R->gexec[0] || R->gexec[1]) (void)drop_graphs(R);
+  if (R->gstream) (void)hipStreamDestroy(R->gstream);
   for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);  // released once any pending record completes
   delete R;
   return DF_OK;
@@ -979,9 +1076,25 @@ struct df_engine {
   std::vector<EngineJob> jobs;
   std::vector<std::pair<size_t, size_t>> freel;  // (offset, length), sorted, coalesced
   hipGraphExec_t exec = nullptr;
+  int exec_tab = -1;  // the job table of the current graph's batched launches
   // replaced graphs whose launches may still run on the device: each is
-  // destroyed once the event recorded after its last launch has completed
-  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> retired;
+  // destroyed (and its job table freed for reuse) once the event recorded
+  // after its last launch has completed
+  struct Retired {
+    hipGraphExec_t exec;
+    hipEvent_t ev;
+    int tab;
+  };
+  std::vector<Retired> retired;
+  // device job tables of the batched launches (allocated outside the arena,
+  // reused once their graph is retired)
+  struct Tab {
+    void *dev = nullptr;
+    size_t cap = 0;
+    bool busy = false;
+  };
+  std::vector<Tab> tabs;
+  long batched = 0;  // jobs in the batched launches of the current graph
   bool dirty = true;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -1041,13 +1154,14 @@ hipEvent_t engine_event(df_engine *E) {
 void engine_reap(df_engine *E, bool wait) {
   size_t k = 0;
   for (auto &r : E->retired) {
-    hipError_t q = wait ? hipEventSynchronize(r.second) : hipEventQuery(r.second);
+    hipError_t q = wait ? hipEventSynchronize(r.ev) : hipEventQuery(r.ev);
     if (q != hipSuccess) {
       E->retired[k++] = r;
       continue;
     }
-    (void)hipGraphExecDestroy(r.first);  // its last launch has completed
-    E->ev_pool.push_back(r.second);
+    (void)hipGraphExecDestroy(r.exec);  // its last launch has completed
+    E->ev_pool.push_back(r.ev);
+    if (r.tab >= 0) E->tabs[r.tab].busy = false;
   }
   E->retired.resize(k);
 }
@@ -1059,16 +1173,109 @@ int engine_capture(df_engine *E) {
     if (!ev) return DF_EDEVICE;
     int rc = hip_check(hipEventRecord(ev, E->main), "event record");
     if (rc) return rc;
-    E->retired.push_back({E->exec, ev});
+    E->retired.push_back({E->exec, ev, E->exec_tab});
     E->exec = nullptr;
+    E->exec_tab = -1;
   }
   engine_reap(E, false);
   std::vector<int> act;
   for (int s = 0; s < (int)E->jobs.size(); ++s)
     if (E->jobs[s].used && E->jobs[s].active) act.push_back(s);
   E->dirty = false;
+  E->batched = 0;
   if (act.empty()) return DF_OK;
-  int rc = hip_check(hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed), "graph capture");
+  // A dry run of every job's two steps with a recorder: the jobs whose every
+  // launch is a batched stage, in the same sequence of stages, advance together,
+  // one launch per stage; the others keep launches of their own.
+  std::vector<dfk::Recorder> rec(act.size());
+  std::vector<char> bat(act.size(), 0);
+  std::vector<int> seq;  // stage sequence (kind classes) of the batched jobs
+  auto cls = [](int kind) {
+    return kind <= dfk::JK_KC_F2 ? 0 : kind <= dfk::JK_DF_F2 ? 1 : kind <= dfk::JK_XY_F2F ? 2 : kind <= dfk::JK_ZF_F ? 3 : 4;
+  };
+  for (size_t q = 0; q < act.size(); ++q) {
+    df_run *R = E->jobs[act[q]].run;
+    int cur0[MAXLEV];
+    std::copy(R->cur, R->cur + R->nl, cur0);
+    const bool sig0 = R->sig_valid, timing = R->timing;
+    R->timing = false;
+    dfk::set_recorder(&rec[q]);
+    enqueue_steps(R, ENGINE_STEPS_PER_REPLAY);
+    dfk::set_recorder(nullptr);
+    R->timing = timing;
+    bool ok = !rec[q].failed && !rec[q].recs.empty();
+    if (ok) {
+      std::vector<int> c;
+      for (const auto &r : rec[q].recs) c.push_back(cls(r.kind));
+      if (seq.empty()) seq = c;
+      ok = c == seq;
+    }
+    if (ok) {
+      bat[q] = 1;
+      E->batched++;
+    } else {
+      // launched by the job itself below
+      std::copy(cur0, cur0 + R->nl, R->cur);
+      R->sig_valid = sig0;
+    }
+  }
+  // the job tables: per stage of the sequence and per kind, the entries of
+  // the jobs (256-byte aligned) and their block offsets
+  struct Group {
+    int kind, n;
+    size_t off_e, off_s;
+    unsigned nblocks;
+  };
+  std::vector<Group> groups;
+  std::vector<unsigned char> host;
+  auto grow = [&](size_t bytes) {
+    const size_t off = align_up(host.size());
+    host.resize(off + bytes);
+    return off;
+  };
+  for (size_t p = 0; p < seq.size() && E->batched; ++p) {
+    for (int kind = 0; kind < dfk::JK_N; ++kind) {
+      std::vector<size_t> qs;
+      for (size_t q = 0; q < act.size(); ++q)
+        if (bat[q] && rec[q].recs[p].kind == kind) qs.push_back(q);
+      if (qs.empty()) continue;
+      const size_t esz = dfk::job_entry_size(kind);
+      Group g{kind, (int)qs.size(), grow(esz * qs.size()), 0, 0};
+      std::vector<unsigned> start(qs.size() + 1, 0);
+      for (size_t u = 0; u < qs.size(); ++u) {
+        const dfk::JobRec &r = rec[qs[u]].recs[p];
+        std::memcpy(host.data() + g.off_e + u * esz, r.bytes.data(), esz);
+        // one block per job for the force log; else the job's blocks, padded
+        // to a multiple of 8 (XCD placement)
+        const unsigned nb = kind == dfk::JK_LOG ? 1u : (r.nblk + 7u) / 8u * 8u;
+        start[u + 1] = start[u] + nb;
+      }
+      g.nblocks = start.back();
+      g.off_s = grow(start.size() * sizeof(unsigned));
+      std::memcpy(host.data() + g.off_s, start.data(), start.size() * sizeof(unsigned));
+      groups.push_back(g);
+    }
+  }
+  int tab = -1;
+  int rc = DF_OK;
+  if (!groups.empty()) {
+    for (size_t u = 0; u < E->tabs.size() && tab < 0; ++u)
+      if (!E->tabs[u].busy && E->tabs[u].cap >= host.size()) tab = (int)u;
+    if (tab < 0) {
+      df_engine::Tab t;
+      t.cap = (host.size() + (1u << 20) - 1) / (1u << 20) * (1u << 20);
+      rc = hip_check(hipMalloc(&t.dev, t.cap), "job table");
+      if (rc) return rc;
+      E->tabs.push_back(t);
+      tab = (int)E->tabs.size() - 1;
+    }
+    rc = hip_check(hipMemcpyAsync(E->tabs[tab].dev, host.data(), host.size(), hipMemcpyHostToDevice, E->admin),
+                   "job table upload");
+    if (!rc) rc = hip_check(hipStreamSynchronize(E->admin), "job table upload");
+    if (rc) return rc;
+    E->tabs[tab].busy = true;
+  }
+  rc = hip_check(hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed), "graph capture");
   if (rc) return rc;
   // a failed fork or join leaves the capture unusable: end it and report
   auto abandon = [&](int code) {
@@ -1080,15 +1287,23 @@ int engine_capture(df_engine *E) {
   for (size_t w = 0; !rc && w < E->workers.size(); ++w)
     rc = hip_check(hipStreamWaitEvent(E->workers[w], E->fork, 0), "graph fork");
   if (rc) return abandon(rc);
+  size_t nw = 0;
   for (size_t q = 0; q < act.size(); ++q) {
+    if (bat[q]) continue;
     EngineJob &J = E->jobs[act[q]];
-    J.worker = (int)(q % E->workers.size());
+    J.worker = (int)(nw++ % E->workers.size());
     df_run *R = J.run;
     R->stream = E->workers[J.worker];
     const bool timing = R->timing;
     R->timing = false;
     enqueue_steps(R, ENGINE_STEPS_PER_REPLAY);
     R->timing = timing;
+  }
+  // the batched jobs, one launch per stage, on the capture stream
+  for (const Group &g : groups) {
+    const char *base = static_cast<const char *>(E->tabs[tab].dev);
+    dfk::launch_jobs(E->cap, g.kind, base + g.off_e, reinterpret_cast<const unsigned *>(base + g.off_s), g.n,
+                     g.nblocks);
   }
   for (size_t w = 0; !rc && w < E->workers.size(); ++w) {
     rc = hip_check(hipEventRecord(E->join[w], E->workers[w]), "graph join");
@@ -1100,6 +1315,7 @@ int engine_capture(df_engine *E) {
   if (rc) return rc;
   rc = hip_check(hipGraphInstantiate(&E->exec, g, nullptr, nullptr, 0), "graph instantiate");
   (void)hipGraphDestroy(g);  // the instantiated graph does not need it
+  E->exec_tab = tab;
   E->captures++;
   return rc;
 }
@@ -1326,12 +1542,13 @@ int df_engine_release(df_engine *E, int32_t slot) {
   return DF_OK;
 }
 
-int df_engine_stats(df_engine *E, int64_t out[2]) {
+int df_engine_stats(df_engine *E, int64_t out[3]) {
   int rc = check_engine(E);
   if (rc) return rc;
   if (!out) return fail(DF_EINVAL, "null output");
   out[0] = E->replays;
   out[1] = E->captures;
+  out[2] = E->batched;
   return DF_OK;
 }
 
@@ -1342,6 +1559,8 @@ int df_engine_destroy(df_engine *E) {
   const int rc = E->main ? hip_check(hipStreamSynchronize(E->main), "engine destroy") : DF_OK;
   engine_reap(E, true);
   if (E->exec) (void)hipGraphExecDestroy(E->exec);
+  for (auto &t : E->tabs)
+    if (t.dev) (void)hipFree(t.dev);
   for (auto &J : E->jobs)
     if (J.used) delete J.run;
   for (auto &p : E->pending) (void)hipEventDestroy(p.ev);

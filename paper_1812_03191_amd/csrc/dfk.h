@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace dfk {
 
 constexpr int NQ = 8;       // transported set: rho, e, P-x, P+x, P-y, P+y, P-z, P+z
@@ -180,5 +182,37 @@ size_t part_count(const Geo &G);
 void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16);
 // logs a pending force of a single-level run (as compress with log does)
 void log_pending(hipStream_t st, const Geo &G, LevBufs &B, Scal *S, double *flog);
+
+// Batched stages (the engine): while a recorder is set on the calling thread,
+// the launchers of the single-level fused step (the fused kick and
+// compression, the diffusion with heat release, the fused x + y pass, the
+// fused z pass and step end, the force log) record their launch arguments
+// instead of launching; any other launch marks the recording failed and is
+// not made.  launch_jobs then makes one launch for one stage of several runs
+// from a device table of their records.
+enum JobKind {
+  JK_KC_D1, JK_KC_D2, JK_KC_F1, JK_KC_F2,      // kick + compression: FP64/FP32, boundary mode 1/2
+  JK_DF_D1, JK_DF_D2, JK_DF_F1, JK_DF_F2,      // diffusion + heat release
+  JK_XY_D1P, JK_XY_D1F, JK_XY_D2P, JK_XY_D2F,  // fused x + y: cells per lane 1/2, rows partial/full
+  JK_XY_F1P, JK_XY_F1F, JK_XY_F2P, JK_XY_F2F,
+  JK_ZF_D, JK_ZF_F,                            // fused z pass and step end
+  JK_LOG,                                      // force log after the last step
+  JK_N
+};
+struct JobRec {
+  int kind;
+  unsigned nblk;                     // blocks of the run's own launch
+  std::vector<unsigned char> bytes;  // the launch's table entry (job_entry_size(kind) bytes)
+};
+struct Recorder {
+  std::vector<JobRec> recs;
+  bool failed = false;
+};
+void set_recorder(Recorder *r);
+size_t job_entry_size(int kind);
+// one launch of stage `kind` for n runs: `entries` a device array of their
+// records' bytes, `start` n + 1 device block offsets (multiples of 8),
+// nblocks = start[n]
+void launch_jobs(hipStream_t st, int kind, const void *entries, const unsigned *start, int n, unsigned nblocks);
 
 }  // namespace dfk

@@ -19,6 +19,8 @@
 // levels advance their whole ghost shell, filled once per parent step.
 #include "dfk.h"
 
+#include <cstring>
+
 namespace dfk {
 
 namespace {
@@ -44,10 +46,18 @@ inline dim3 grid_of(const Box &b) {
   return dim3((unsigned)n, 1, 1);
 }
 
-__device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k) {
+// A block's place in its launch: the hardware's, or, in a launch that
+// carries the blocks of several runs (the engine's batched stages), its place
+// among its own run's blocks.
+struct Blk {
+  unsigned id, n;
+};
+__device__ __forceinline__ Blk grid_blk() { return Blk{blockIdx.x, gridDim.x}; }
+
+__device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k, Blk bk = grid_blk()) {
   const unsigned nbx = (unsigned)(b.hi[0] - b.lo[0] + BX - 1) / BX;
   const unsigned nby = (unsigned)(b.hi[1] - b.lo[1] + BY - 1) / BY;
-  const unsigned N = gridDim.x, h = blockIdx.x;
+  const unsigned N = bk.n, h = bk.id;
   const unsigned nbz = N / (nbx * nby);
   const unsigned q = N / 8, r = N % 8, x = h % 8, s = h / 8;
   unsigned L = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
@@ -603,11 +613,11 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArg
 // as 8- or 16-byte accesses, the x neighbours of the pair are the other cell
 // of the pair and one cell on each side.
 template <typename T, int BC>
-__global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffArgs<T> A) {
+__device__ __forceinline__ void diffuse_heat2_body(Geo G, Phys P, DiffArgs<T> A, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  const bool ok = thread_cell(A.b, p, j, k);
-  if (A.clear && blockIdx.x == 0) {
+  const bool ok = thread_cell(A.b, p, j, k, bk);
+  if (A.clear && bk.id == 0) {
     // the kick of this step has read the slots: clear them for this step's
     // end-of-step pass
     for (int q = threadIdx.y * BX + threadIdx.x; q < NSLOT; q += BX * BY) A.clear->smax[q] = 0ull;
@@ -658,6 +668,11 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffAr
     }
   }
   gstv<V>(A.eo, c, en);
+}
+
+template <typename T, int BC>
+__global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffArgs<T> A) {
+  diffuse_heat2_body<T, BC>(G, P, A, grid_blk());
 }
 
 // -------------------------------------------------------------- transport
@@ -1691,14 +1706,13 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
 // of the separate passes up to the pairing of products and sums into fused
 // multiply-adds.
 template <typename T, int W, bool FULL>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
+__device__ __forceinline__ void xyshared_body(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M, Blk bk) {
   constexpr int NG = 4;
   __shared__ T rows[XY_RS * 3 * W * 64];
   __shared__ T faces[XY_FS * W * 64];
   const int lane = threadIdx.x;
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.y);
-  const int t = (int)(blockIdx.x % (unsigned)G.n[2]), ch = (int)(blockIdx.x / (unsigned)G.n[2]);
+  const int t = (int)(bk.id % (unsigned)G.n[2]), ch = (int)(bk.id / (unsigned)G.n[2]);
   const int c0 = ch * M.chunk;
   const int c1 = min(c0 + M.chunk, G.n[1]);
   if (c0 >= c1) return;  // the whole block
@@ -1710,6 +1724,12 @@ k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
   else if (grp == 1) xy_shared_group<T, W, 1, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
   else if (grp == 2) xy_shared_group<T, W, 2, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
   else xy_shared_group<T, W, 3, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+}
+
+template <typename T, int W, bool FULL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
+  xyshared_body<T, W, FULL>(G, P, A, M, grid_blk());
 }
 
 // ------------------------------------------------------------ CommUp
@@ -1901,7 +1921,7 @@ __device__ __forceinline__ bool is_covered(const RedArgs<T> &A, int i, int j, in
 }
 
 // block sum of three values into part[q * blocks + block]; fixed order for a fixed grid
-__device__ void block_sum3(double a, double b, double c, double *part, int npart) {
+__device__ void block_sum3(double a, double b, double c, double *part, int npart, Blk bk = grid_blk()) {
   __shared__ double sh[3][BX * BY / 64];
   a = wave_sum(a);
   b = wave_sum(b);
@@ -1915,7 +1935,7 @@ __device__ void block_sum3(double a, double b, double c, double *part, int npart
   }
   __syncthreads();
   if (t == 0) {
-    const long blk = blockIdx.x;
+    const long blk = bk.id;
     double s0 = 0, s1 = 0, s2 = 0;
     for (int q = 0; q < BX * BY / 64; ++q) {
       s0 += sh[0][q];
@@ -2129,7 +2149,7 @@ __device__ __forceinline__ double cell_signal(const Geo &G, const Phys &P, const
 
 // block maximum of the signal speeds into spart[block]; a bad cell raises
 // the health flag
-__device__ void block_signal(double sig, int bad, double *spart, Scal *S) {
+__device__ void block_signal(double sig, int bad, double *spart, Scal *S, Blk bk = grid_blk()) {
   sig = wave_max(bad ? 0.0 : sig);
   const bool anybad = __any(bad);
   __shared__ double sh[BX * BY / 64];
@@ -2142,11 +2162,11 @@ __device__ void block_signal(double sig, int bad, double *spart, Scal *S) {
   if (t == 0) {
     double m = sh[0];
     for (int q = 1; q < BX * BY / 64; ++q) m = fmax(m, sh[q]);
-    spart[blockIdx.x] = m;
+    spart[bk.id] = m;
     // the same maximum into this block's slot (m >= 0, so the order of the
     // bits is that of the values)
     if (S)
-      __hip_atomic_fetch_max(&S->smax[blockIdx.x & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
+      __hip_atomic_fetch_max(&S->smax[bk.id & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
@@ -2211,12 +2231,11 @@ __global__ void __launch_bounds__(BX * BY) k_post(Geo G, Phys P, RedArgs<T> A) {
 // compressed energy goes to A.eo.
 // (five waves per SIMD: the FP64 end-of-step form fits 93 registers with no
 // spill, against 104 and four waves unconstrained)
-template <typename T, int BCM, bool REBUILD, bool KICK, bool POST, bool COMP = false>
-__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(5)))
-k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
+template <typename T, int BCM, bool REBUILD, bool KICK, bool POST, bool COMP>
+__device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  const bool ok = thread_cell(A.b, p, j, k);
+  const bool ok = thread_cell(A.b, p, j, k, bk);
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
@@ -2237,13 +2256,13 @@ k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
     double dtl = G.dx / smax;
     if (P.chi > 0.0) dtl = fmin(dtl, G.dx * G.dx / (6.0 * P.chi));
     dtk = P.cfl * dtl;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    if (bk.id == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
       A.slots->dtl[0] = P.cfl * dtl;
       A.slots->dt[0] = dtk;
       A.slots->t += dtk;
     }
   }
-  if (POST && blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+  if (POST && bk.id == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
     R.S->tlog = R.S->t;  // the force partials of this state await the log
     R.S->pending = 1;
   }
@@ -2442,11 +2461,11 @@ k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
       if (!isfinite(sig)) bad = 1;
     }
   }
-  if (COMP && A.log && blockIdx.x == 0) log_pending_body<BX * BY>(A.part, A.npart, A.log, A.flog);
+  if (COMP && A.log && bk.id == 0) log_pending_body<BX * BY>(A.part, A.npart, A.log, A.flog);
   if (POST) {
-    block_sum3(fx, fy, fz, R.part, R.npart);
-    block_signal((double)sig, bad, R.spart, R.S);
-    const unsigned z = gridDim.x + blockIdx.x;
+    block_sum3(fx, fy, fz, R.part, R.npart, bk);
+    block_signal((double)sig, bad, R.spart, R.S, bk);
+    const unsigned z = bk.n + bk.id;
     if (threadIdx.x == 0 && threadIdx.y == 0 && z < (unsigned)R.npart) {
       R.part[z] = 0.0;
       R.part[R.npart + z] = 0.0;
@@ -2454,6 +2473,12 @@ k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
       R.spart[z] = 0.0;
     }
   }
+}
+
+template <typename T, int BCM, bool REBUILD, bool KICK, bool POST, bool COMP = false>
+__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(5)))
+k_kick0p(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R) {
+  kick0p_body<T, BCM, REBUILD, KICK, POST, COMP>(G, P, A, R, grid_blk());
 }
 
 // ------------------------------------------ z pass fused with the step's end
@@ -2531,8 +2556,7 @@ __device__ __forceinline__ void zf_walk(const Geo &G, const Phys &P, const March
 }
 
 template <typename T>
-__global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchArgs<T> M, KickArgs<T> K,
-                                                            RedArgs<T> R) {
+__device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, KickArgs<T> K, RedArgs<T> R, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
   __shared__ __align__(16) T zl[2 * (ZF_TY + 1) * NQ * 128];
   __shared__ double sh[5][ZF_WAVES];
@@ -2542,7 +2566,7 @@ __global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchA
   // block -> (row band, z segment): each XCD (block h runs on XCD h % 8)
   // takes one contiguous range of bands through all segments
   const int nch = (G.n[2] + M.chunk - 1) / M.chunk;
-  const unsigned N = gridDim.x, h = blockIdx.x;
+  const unsigned N = bk.n, h = bk.id;
   const unsigned q8 = N / 8, r8 = N % 8, xcd = h % 8, s8 = h / 8;
   const unsigned Lg = (xcd < r8) ? xcd * (q8 + 1) + s8 : r8 * (q8 + 1) + (xcd - r8) * q8 + s8;
   const int band = (int)(Lg / (unsigned)nch), ch = (int)(Lg % (unsigned)nch);
@@ -2554,7 +2578,7 @@ __global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchA
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
-  if (blockIdx.x == 0 && lane == 0 && wv == 0) {
+  if (bk.id == 0 && lane == 0 && wv == 0) {
     R.S->tlog = R.S->t;  // the force partials of this state await the log
     R.S->pending = 1;
   }
@@ -2722,7 +2746,7 @@ __global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchA
     if (!isfinite(sig)) bad = 1;
   }
   // block sums of the force partials and maximum of the signal speeds (every
-  // wave takes part; walkers contribute zeros), written to slot blockIdx.x;
+  // wave takes part; walkers contribute zeros), written to the block's slot;
   // the slots of the one-cell-per-thread grid past the launch are zeroed
   fx = wave_sum(fx);
   fy = wave_sum(fy);
@@ -2746,20 +2770,26 @@ __global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchA
       m = fmax(m, sh[3][w]);
     }
     const long nb = R.npart;
-    R.part[blockIdx.x] = s0;
-    R.part[nb + blockIdx.x] = s1;
-    R.part[2 * nb + blockIdx.x] = s2;
-    R.spart[blockIdx.x] = m;
-    __hip_atomic_fetch_max(&R.S->smax[blockIdx.x & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
+    R.part[bk.id] = s0;
+    R.part[nb + bk.id] = s1;
+    R.part[2 * nb + bk.id] = s2;
+    R.spart[bk.id] = m;
+    __hip_atomic_fetch_max(&R.S->smax[bk.id & (NSLOT - 1)], (unsigned long long)__double_as_longlong(m),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  for (unsigned z = gridDim.x + blockIdx.x + (unsigned)(wv * 64 + lane) * gridDim.x; z < (unsigned)R.npart;
-       z += gridDim.x * 64u * ZF_WAVES) {
+  for (unsigned z = bk.n + bk.id + (unsigned)(wv * 64 + lane) * bk.n; z < (unsigned)R.npart;
+       z += bk.n * 64u * ZF_WAVES) {
     R.part[z] = 0.0;
     R.part[R.npart + z] = 0.0;
     R.part[2 * (size_t)R.npart + z] = 0.0;
     R.spart[z] = 0.0;
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish(Geo G, Phys P, MarchArgs<T> M, KickArgs<T> K,
+                                                            RedArgs<T> R) {
+  zfinish_body<T>(G, P, M, K, R, grid_blk());
 }
 
 struct DtArgs {
@@ -2927,11 +2957,164 @@ inline T *tp(void *p) {
 }  // namespace
 
 // launch only non-empty grids
+// While a recorder is set (the engine's dry run of a step), every launch that
+// is not one of the batched stages marks the recording failed and is not made.
 #define DFK_LAUNCH(K, GR, BL, ST, ...)                                      \
   do {                                                                      \
+    if (g_rec) {                                                            \
+      g_rec->failed = true;                                                 \
+      break;                                                                \
+    }                                                                       \
     dim3 g_ = (GR);                                                         \
     if (!empty_grid(g_)) hipLaunchKernelGGL(K, g_, BL, 0, ST, __VA_ARGS__); \
   } while (0)
+
+thread_local Recorder *g_rec = nullptr;
+
+// in a recording: add the launch of stage kind `kind` with its arguments
+template <typename E>
+bool record(int kind, const E &e) {
+  if (!g_rec) return false;
+  if (e.nblk == 0) return true;  // an empty launch is no launch
+  JobRec r;
+  r.kind = kind;
+  r.nblk = e.nblk;
+  r.bytes.resize(sizeof(E));
+  std::memcpy(r.bytes.data(), &e, sizeof(E));
+  g_rec->recs.push_back(std::move(r));
+  return true;
+}
+
+// ============================================================ batched jobs
+// One launch for one stage of several single-level runs (the engine's batched
+// step): run r owns the blocks [start[r], start[r+1]) of the launch, each
+// run's count padded to a multiple of 8 so that its blocks keep their XCD
+// placement (block h on XCD h % 8), and its launch arguments are entry r of
+// the table; block b runs as block b - start[r] of the run's own launch.  The
+// bodies are those of the single-run kernels, so a run's results do not
+// depend on the other runs in the launch.
+template <typename T>
+struct KcJob {
+  Geo G;
+  Phys P;
+  KickArgs<T> A;
+  RedArgs<T> R;
+  unsigned nblk;
+};
+template <typename T>
+struct DiffJob {
+  Geo G;
+  Phys P;
+  DiffArgs<T> A;
+  unsigned nblk;
+};
+template <typename T>
+struct XyJob {
+  Geo G;
+  Phys P;
+  PassArgs<T> A;
+  MarchArgs<T> M;
+  unsigned nblk;
+};
+template <typename T>
+struct ZfJob {
+  Geo G;
+  Phys P;
+  MarchArgs<T> M;
+  KickArgs<T> K;
+  RedArgs<T> R;
+  unsigned nblk;
+};
+struct LogJob {
+  const double *part;
+  int npart;
+  Scal *S;
+  double *flog;
+  unsigned nblk;
+};
+
+// stage kinds of the batched launches (dfk.h), per storage type and form
+template <typename T>
+constexpr int jk_kc(int bc) {
+  return (sizeof(T) == 4 ? JK_KC_F1 : JK_KC_D1) + (bc == 2 ? 1 : 0);
+}
+template <typename T>
+constexpr int jk_df(int bc) {
+  return (sizeof(T) == 4 ? JK_DF_F1 : JK_DF_D1) + (bc == 2 ? 1 : 0);
+}
+template <typename T>
+constexpr int jk_xy(int n) {  // the k_xyshared form transport_xy_t takes for rows of n cells
+  return (sizeof(T) == 4 ? JK_XY_F1P : JK_XY_D1P) + (n > BX ? 2 : 0) + ((n == BX || n == 2 * BX) ? 1 : 0);
+}
+template <typename T>
+constexpr int jk_zf() {
+  return sizeof(T) == 4 ? JK_ZF_F : JK_ZF_D;
+}
+
+template <typename E>
+struct JobTab {
+  const E *__restrict__ e;
+  const unsigned *__restrict__ start;  // n + 1 block offsets
+  int n;
+};
+
+// the run of block b and the block's place in the run's launch; false for a
+// padding block
+template <typename E>
+__device__ __forceinline__ bool job_of(const JobTab<E> &t, unsigned b, int &r, Blk &bk) {
+  int lo = 0, hi = t.n;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (t.start[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  r = lo;
+  bk.id = b - t.start[lo];
+  bk.n = t.e[lo].nblk;
+  return bk.id < bk.n;
+}
+
+template <typename T, int BCM>
+__global__ void __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(5)))
+k_kick_compress_jobs(JobTab<KcJob<T>> t) {
+  int r;
+  Blk bk;
+  if (!job_of(t, blockIdx.x, r, bk)) return;
+  const KcJob<T> &J = t.e[r];
+  kick0p_body<T, BCM, false, true, false, true>(J.G, J.P, J.A, J.R, bk);
+}
+
+template <typename T, int BC>
+__global__ void __launch_bounds__(BX * BY) k_diffuse_heat2_jobs(JobTab<DiffJob<T>> t) {
+  int r;
+  Blk bk;
+  if (!job_of(t, blockIdx.x, r, bk)) return;
+  const DiffJob<T> &J = t.e[r];
+  diffuse_heat2_body<T, BC>(J.G, J.P, J.A, bk);
+}
+
+template <typename T, int W, bool FULL>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_xyshared_jobs(JobTab<XyJob<T>> t) {
+  int r;
+  Blk bk;
+  if (!job_of(t, blockIdx.x, r, bk)) return;
+  const XyJob<T> &J = t.e[r];
+  xyshared_body<T, W, FULL>(J.G, J.P, J.A, J.M, bk);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * ZF_WAVES) k_zfinish_jobs(JobTab<ZfJob<T>> t) {
+  int r;
+  Blk bk;
+  if (!job_of(t, blockIdx.x, r, bk)) return;
+  const ZfJob<T> &J = t.e[r];
+  zfinish_body<T>(J.G, J.P, J.M, J.K, J.R, bk);
+}
+
+__global__ void __launch_bounds__(FT) k_log_pending_jobs(JobTab<LogJob> t) {
+  const LogJob &J = t.e[blockIdx.x];
+  log_pending_body<FT>(J.part, J.npart, J.S, J.flog);
+}
 
 // ======================================================================
 // launchers (templated on the storage type, dispatched on P.fp32)
@@ -3048,6 +3231,7 @@ static void kick_compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs
   A.flog = flog;
   RedArgs<T> R{};
   const dim3 gr = grid_of(A.b), bl(BX, BY);
+  if (record(jk_kc<T>(G.bc), KcJob<T>{G, P, A, R, gr.x})) return;
   if (G.bc == 2) DFK_LAUNCH((k_kick0p<T, 2, false, true, false, true>), gr, bl, st, G, P, A, R);
   else DFK_LAUNCH((k_kick0p<T, 1, false, true, false, true>), gr, bl, st, G, P, A, R);
 }
@@ -3165,6 +3349,7 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.do_heat = do_heat && P.L != 0.0;
   if (G.bc) {
     A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
+    if (record(jk_df<T>(G.bc), DiffJob<T>{G, P, A, grid_of(A.b).x})) return;
     if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
     else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
   } else {
@@ -3308,6 +3493,7 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   // one block of four waves per (plane, y segment)
   const long nch = (G.n[1] + M.chunk - 1) / M.chunk;
   const dim3 gr((unsigned)(G.n[2] * nch)), bl(64, 4);
+  if (record(jk_xy<T>(n), XyJob<T>{G, P, A, M, gr.x})) return true;
   if (n == BX) DFK_LAUNCH((k_xyshared<T, 1, true>), gr, bl, st, G, P, A, M);
   else if (n < BX) DFK_LAUNCH((k_xyshared<T, 1, false>), gr, bl, st, G, P, A, M);
   else if (n == 2 * BX) DFK_LAUNCH((k_xyshared<T, 2, true>), gr, bl, st, G, P, A, M);
@@ -3358,6 +3544,7 @@ static bool transport_z_finish_t(hipStream_t st, const Geo &G, const Phys &P, Le
   const long nch = (G.n[2] + M.chunk - 1) / M.chunk;
   const long nblk = (long)(G.n[1] / ZF_TY) * nch;
   if (nblk > R.npart) return false;  // every block needs a partial slot (never the case for a fitting mesh)
+  if (record(jk_zf<T>(), ZfJob<T>{G, P, M, K, R, (unsigned)nblk})) return true;
   DFK_LAUNCH(k_zfinish<T>, dim3((unsigned)nblk), dim3(64, ZF_WAVES), st, G, P, M, K, R);
   return true;
 }
@@ -3387,13 +3574,63 @@ __global__ void __launch_bounds__(256) k_copy16(uint4 *dst, const uint4 *src, si
 }
 
 void log_pending(hipStream_t st, const Geo &G, LevBufs &B, Scal *S, double *flog) {
-  hipLaunchKernelGGL(k_log_pending, dim3(1), dim3(FT), 0, st, (const double *)B.part, (int)part_count(G), S, flog);
+  const LogJob J{(const double *)B.part, (int)part_count(G), S, flog, 1u};
+  if (record(JK_LOG, J)) return;
+  DFK_LAUNCH(k_log_pending, dim3(1), dim3(FT), st, J.part, J.npart, S, flog);
+}
+
+void set_recorder(Recorder *r) { g_rec = r; }
+
+size_t job_entry_size(int kind) {
+  switch (kind) {
+    case JK_KC_D1: case JK_KC_D2: return sizeof(KcJob<double>);
+    case JK_KC_F1: case JK_KC_F2: return sizeof(KcJob<float>);
+    case JK_DF_D1: case JK_DF_D2: return sizeof(DiffJob<double>);
+    case JK_DF_F1: case JK_DF_F2: return sizeof(DiffJob<float>);
+    case JK_XY_D1P: case JK_XY_D1F: case JK_XY_D2P: case JK_XY_D2F: return sizeof(XyJob<double>);
+    case JK_XY_F1P: case JK_XY_F1F: case JK_XY_F2P: case JK_XY_F2F: return sizeof(XyJob<float>);
+    case JK_ZF_D: return sizeof(ZfJob<double>);
+    case JK_ZF_F: return sizeof(ZfJob<float>);
+    case JK_LOG: return sizeof(LogJob);
+    default: return 0;
+  }
+}
+
+template <typename E>
+static JobTab<E> tab_of(const void *entries, const unsigned *start, int n) {
+  return JobTab<E>{reinterpret_cast<const E *>(entries), start, n};
+}
+
+void launch_jobs(hipStream_t st, int kind, const void *entries, const unsigned *start, int n, unsigned nblocks) {
+  const dim3 gr(nblocks), bl(BX, BY), xb(64, 4), zb(64, ZF_WAVES);
+  switch (kind) {
+    case JK_KC_D1: DFK_LAUNCH((k_kick_compress_jobs<double, 1>), gr, bl, st, tab_of<KcJob<double>>(entries, start, n)); break;
+    case JK_KC_D2: DFK_LAUNCH((k_kick_compress_jobs<double, 2>), gr, bl, st, tab_of<KcJob<double>>(entries, start, n)); break;
+    case JK_KC_F1: DFK_LAUNCH((k_kick_compress_jobs<float, 1>), gr, bl, st, tab_of<KcJob<float>>(entries, start, n)); break;
+    case JK_KC_F2: DFK_LAUNCH((k_kick_compress_jobs<float, 2>), gr, bl, st, tab_of<KcJob<float>>(entries, start, n)); break;
+    case JK_DF_D1: DFK_LAUNCH((k_diffuse_heat2_jobs<double, 1>), gr, bl, st, tab_of<DiffJob<double>>(entries, start, n)); break;
+    case JK_DF_D2: DFK_LAUNCH((k_diffuse_heat2_jobs<double, 2>), gr, bl, st, tab_of<DiffJob<double>>(entries, start, n)); break;
+    case JK_DF_F1: DFK_LAUNCH((k_diffuse_heat2_jobs<float, 1>), gr, bl, st, tab_of<DiffJob<float>>(entries, start, n)); break;
+    case JK_DF_F2: DFK_LAUNCH((k_diffuse_heat2_jobs<float, 2>), gr, bl, st, tab_of<DiffJob<float>>(entries, start, n)); break;
+    case JK_XY_D1P: DFK_LAUNCH((k_xyshared_jobs<double, 1, false>), gr, xb, st, tab_of<XyJob<double>>(entries, start, n)); break;
+    case JK_XY_D1F: DFK_LAUNCH((k_xyshared_jobs<double, 1, true>), gr, xb, st, tab_of<XyJob<double>>(entries, start, n)); break;
+    case JK_XY_D2P: DFK_LAUNCH((k_xyshared_jobs<double, 2, false>), gr, xb, st, tab_of<XyJob<double>>(entries, start, n)); break;
+    case JK_XY_D2F: DFK_LAUNCH((k_xyshared_jobs<double, 2, true>), gr, xb, st, tab_of<XyJob<double>>(entries, start, n)); break;
+    case JK_XY_F1P: DFK_LAUNCH((k_xyshared_jobs<float, 1, false>), gr, xb, st, tab_of<XyJob<float>>(entries, start, n)); break;
+    case JK_XY_F1F: DFK_LAUNCH((k_xyshared_jobs<float, 1, true>), gr, xb, st, tab_of<XyJob<float>>(entries, start, n)); break;
+    case JK_XY_F2P: DFK_LAUNCH((k_xyshared_jobs<float, 2, false>), gr, xb, st, tab_of<XyJob<float>>(entries, start, n)); break;
+    case JK_XY_F2F: DFK_LAUNCH((k_xyshared_jobs<float, 2, true>), gr, xb, st, tab_of<XyJob<float>>(entries, start, n)); break;
+    case JK_ZF_D: DFK_LAUNCH(k_zfinish_jobs<double>, gr, zb, st, tab_of<ZfJob<double>>(entries, start, n)); break;
+    case JK_ZF_F: DFK_LAUNCH(k_zfinish_jobs<float>, gr, zb, st, tab_of<ZfJob<float>>(entries, start, n)); break;
+    case JK_LOG: DFK_LAUNCH(k_log_pending_jobs, gr, dim3(FT), st, tab_of<LogJob>(entries, start, n)); break;
+    default: break;
+  }
 }
 
 void stream_copy(hipStream_t st, void *dst, const void *src, size_t n16) {
   if (n16 == 0) return;
   const size_t blocks = (n16 + 1023) / 1024;
-  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<uint4 *>(dst),
+  DFK_LAUNCH(k_copy16, dim3((unsigned)blocks), dim3(256), st, reinterpret_cast<uint4 *>(dst),
                      reinterpret_cast<const uint4 *>(src), n16);
 }
 
@@ -3402,7 +3639,7 @@ void zero(hipStream_t st, void *p, size_t bytes) {
   if (n == 0 || !p) return;
   size_t blocks = (n + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, reinterpret_cast<unsigned int *>(p), n);
+  DFK_LAUNCH(k_zero, dim3((unsigned)blocks), dim3(256), st, reinterpret_cast<unsigned int *>(p), n);
 }
 
 // floor(i / 2)
@@ -3559,7 +3796,7 @@ static DtArgs dt_args(const Geo *G, const LevBufs *B, int nl, int advance) {
 }
 
 void dt_final(hipStream_t st, const Geo *G, const LevBufs *B, int nl, const Phys &P, Scal *S, int advance) {
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(FT), 0, st, P, dt_args(G, B, nl, advance), S);
+  DFK_LAUNCH(k_dt_final, dim3(1), dim3(FT), st, P, dt_args(G, B, nl, advance), S);
 }
 
 void post_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, Scal *S) {
@@ -3595,9 +3832,9 @@ void step_final(hipStream_t st, const Geo *G, LevBufs *B, int nl, const Phys &P,
   }
   const FinalArgs F = final_args(parts, np, nl, S, 2, flog);
   const DtArgs D = dt_args(G, B, nl, do_dt == 2 ? 2 : 1);
-  if (do_force && do_dt) hipLaunchKernelGGL((k_step_final<true, true>), dim3(1), dim3(FT), 0, st, P, F, D, S);
-  else if (do_force) hipLaunchKernelGGL((k_step_final<true, false>), dim3(1), dim3(FT), 0, st, P, F, D, S);
-  else if (do_dt) hipLaunchKernelGGL((k_step_final<false, true>), dim3(1), dim3(FT), 0, st, P, F, D, S);
+  if (do_force && do_dt) DFK_LAUNCH((k_step_final<true, true>), dim3(1), dim3(FT), st, P, F, D, S);
+  else if (do_force) DFK_LAUNCH((k_step_final<true, false>), dim3(1), dim3(FT), st, P, F, D, S);
+  else if (do_dt) DFK_LAUNCH((k_step_final<false, true>), dim3(1), dim3(FT), st, P, F, D, S);
 }
 
 int force_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur) {
@@ -3624,7 +3861,7 @@ int totals_partials(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int
 
 void force_final(hipStream_t st, double *const *parts, const int *nparts, int nl, Scal *S, int slot,
                  double *flog) {
-  hipLaunchKernelGGL(k_final3, dim3(1), dim3(FT), 0, st, final_args(parts, nparts, nl, S, slot, flog));
+  DFK_LAUNCH(k_final3, dim3(1), dim3(FT), st, final_args(parts, nparts, nl, S, slot, flog));
 }
 
 }  // namespace dfk

@@ -39,9 +39,11 @@ def serve(arrivals, jobs, steps, *, budget_bytes, precision=DF_FP32, nstreams=4,
     for cfg in jobs:
         if engine_job_bytes(cfg, precision) > budget_bytes:
             raise ValueError("a job does not fit the HBM budget")
-        k = (cfg["nx"], cfg["ny"], cfg["nz"])
+        # single-level jobs advance in the engine's batched launches (a full
+        # GPU); nested ones launch by themselves, beside the others
+        k = (cfg["nx"], cfg["ny"], cfg["nz"], cfg["nlevels"] == 1)
         if tune and k not in chunks:
-            chunks[k] = best_chunk(cfg, precision)
+            chunks[k] = best_chunk(cfg, precision, batched=k[3])
     eng = Engine(budget_bytes, nstreams=nstreams)
     stream = eng.stream
     torch.cuda.synchronize()
@@ -59,7 +61,7 @@ def serve(arrivals, jobs, steps, *, budget_bytes, precision=DF_FP32, nstreams=4,
         while queue:
             j = queue[0]
             cfg = jobs[j]
-            k = (cfg["nx"], cfg["ny"], cfg["nz"])
+            k = (cfg["nx"], cfg["ny"], cfg["nz"], cfg["nlevels"] == 1)
             slot = eng.admit(cfg, steps, precision=precision, tile_chunk=chunks.get(k, 0))
             if slot is None:
                 break

@@ -1,6 +1,8 @@
 """The batched engine (df_engine_*) through the C ABI: a job run in the engine,
-alone or among others of different sizes, nesting depths and precisions, gives
-bitwise the results of the same job stepped eagerly; graph replays stay equal to
+alone or among others of different sizes, nesting depths and precisions (the
+single-level ones advancing together in one launch per stage, the nested ones
+with launches of their own), gives bitwise the results of the same job stepped
+eagerly; graph replays stay equal to
 the eager run with other GPU work and synchronisations between them; admission
 is bound by the HBM budget; completions are reported once."""
 import sys
@@ -74,6 +76,7 @@ def test_engine_job_equals_eager_run(dfm, precision):
     eng = dfm.Engine(1 << 30)
     s = eng.admit(cfg, 12, precision=precision)
     eng.step(6)
+    assert eng.stats()["batched"] == 1  # the single-level job took the batched launches
     assert s in _wait_done(eng, [s])
     ref = _eager(dfm, cfg, 12, precision)
     for name in FIELDS:
@@ -109,6 +112,7 @@ def test_engine_solo_equals_mix(dfm, precision):
     assert np.array_equal(solo.force(a), mix.force(b))
     st = mix.stats()
     assert st["captures"] >= 2  # the set of jobs changed while running
+    assert solo.stats()["batched"] == 0  # a nested job keeps launches of its own
 
 
 def test_graph_replays_match_eager_between_replays(dfm):

@@ -247,7 +247,8 @@ def test_fusion_switches_reject_other_values(dfm):
 
     g = dfm.Run(16, dx0=0.1)
     lib = _lib._load()
-    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion, lib.df_set_finish_fusion):
+    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion, lib.df_set_finish_fusion,
+               lib.df_set_step_graphs):
         assert fn(g._h, 0) == 0 and fn(g._h, 1) == 0
         assert fn(g._h, 2) == -1 and fn(g._h, -1) == -1
 

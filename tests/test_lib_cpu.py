@@ -95,7 +95,8 @@ def test_launch_switches_need_a_bound_run():
 
     h = dfm.init_mesh(16, 16, 16, 1, 0.1)
     lib = _lib._load()
-    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion, lib.df_set_finish_fusion):
+    for fn in (lib.df_set_kick_fusion, lib.df_set_transport_fusion, lib.df_set_finish_fusion,
+               lib.df_set_step_graphs):
         assert fn(h, 1) == -2
         assert fn(None, 1) == -1
     dfm.destroy(h)
