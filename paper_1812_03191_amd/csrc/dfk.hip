@@ -78,6 +78,43 @@ __device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k
   return i < b.hi[0] && j < b.hi[1];
 }
 
+// Flat tiles for the level-0 kernels that give each thread a pair of cells:
+// the (pair, row) entries of a plane are numbered row by row and each wave
+// takes 64 consecutive ones, so that rows of fewer than 64 pairs share a wave
+// (a row of 64 pairs is one wave, and the tiles are those of thread_cell);
+// blocks of four waves go to the XCDs in bands through all planes as there.
+// A lane's previous lane then holds the previous pair of its row unless the
+// lane is the first of its wave or its pair the first of its row.
+inline dim3 grid_of_flat(const Box &b) {
+  const long ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
+  if (ex <= 0 || ey <= 0 || ez <= 0) return dim3(0, 1, 1);
+  return dim3((unsigned)((ex * ey + BX * BY - 1) / (BX * BY) * ez), 1, 1);
+}
+
+__device__ __forceinline__ bool thread_cell_flat(const Box &b, int &i, int &j, int &k, Blk bk) {
+  const unsigned ex = (unsigned)(b.hi[0] - b.lo[0]), ey = (unsigned)(b.hi[1] - b.lo[1]);
+  const unsigned nby = (ex * ey + BX * BY - 1) / (BX * BY);  // blocks per plane
+  const unsigned N = bk.n, h = bk.id;
+  const unsigned nbz = N / nby;
+  const unsigned q = N / 8, r = N % 8, x = h % 8, s = h / 8;
+  unsigned L = (x < r) ? x * (q + 1) + s : r * (q + 1) + (x - r) * q + s;
+  const unsigned hq = nby / 8, hr = nby % 8;
+  unsigned y0 = 0, hb = hq + (hr > 0);
+  for (unsigned bb = 0; bb < 8; ++bb) {
+    hb = hq + (bb < hr ? 1u : 0u);
+    unsigned nt = hb * nbz;
+    if (L < nt || bb == 7) break;
+    L -= nt;
+    y0 += hb;
+  }
+  const unsigned by = y0 + L % hb, bz = L / hb;
+  const unsigned f = by * (BX * BY) + threadIdx.y * BX + threadIdx.x;
+  i = b.lo[0] + (int)(f % ex);
+  j = b.lo[1] + (int)(f / ex);
+  k = b.lo[2] + (int)bz;
+  return f < ex * ey;
+}
+
 // Element indices are 32-bit (a field holds fewer than 2^31 entries, checked
 // when a mesh is created): with a uniform 64-bit base in scalar registers the
 // loads and stores then take a 32-bit per-lane offset, with no 64-bit address
@@ -616,7 +653,7 @@ template <typename T, int BC>
 __device__ __forceinline__ void diffuse_heat2_body(Geo G, Phys P, DiffArgs<T> A, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  const bool ok = thread_cell(A.b, p, j, k, bk);
+  const bool ok = thread_cell_flat(A.b, p, j, k, bk);
   if (A.clear && bk.id == 0) {
     // the kick of this step has read the slots: clear them for this step's
     // end-of-step pass
@@ -2235,7 +2272,7 @@ template <typename T, int BCM, bool REBUILD, bool KICK, bool POST, bool COMP>
 __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArgs<T> R, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  const bool ok = thread_cell(A.b, p, j, k, bk);
+  const bool ok = thread_cell_flat(A.b, p, j, k, bk);
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
@@ -2284,7 +2321,9 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
     const V r2c = r2of(xcx, yc, zc);
     const V dcen = qsqrtv(r2c);
     const T gg = (T)(P.gamma * P.gm1), e0 = (T)P.e0;
-    const int lane = threadIdx.x;  // pair p-1 is the lane before (BX is the wave width)
+    // pair p-1 is the lane before, unless this is the wave's first lane (BX is
+    // the wave width) or p the row's first pair (flat tiles)
+    const int lane = threadIdx.x;
     auto sound1 = [&](T dr, T de) -> T {
       const T r = rho0 + dr, en = e0 + de;
       if (!(r > T(0)) || !(en > T(0)) || !isfinite(r) || !isfinite(en)) bad = 1;
@@ -2465,13 +2504,13 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
   if (POST) {
     block_sum3(fx, fy, fz, R.part, R.npart, bk);
     block_signal((double)sig, bad, R.spart, R.S, bk);
-    const unsigned z = bk.n + bk.id;
-    if (threadIdx.x == 0 && threadIdx.y == 0 && z < (unsigned)R.npart) {
-      R.part[z] = 0.0;
-      R.part[R.npart + z] = 0.0;
-      R.part[2 * (size_t)R.npart + z] = 0.0;
-      R.spart[z] = 0.0;
-    }
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+      for (unsigned z = bk.n + bk.id; z < (unsigned)R.npart; z += bk.n) {
+        R.part[z] = 0.0;
+        R.part[R.npart + z] = 0.0;
+        R.part[2 * (size_t)R.npart + z] = 0.0;
+        R.spart[z] = 0.0;
+      }
   }
 }
 
@@ -3180,7 +3219,7 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
     if (post) R = red_args<T>(G, *post, 0, S);
     A.b.hi[0] = G.n[0] / 2;  // level-0 rows have an even length
     A.slots = slots;
-    const dim3 gr = grid_of(A.b);
+    const dim3 gr = grid_of_flat(A.b);
     if (G.bc == 2) {
       if (rebuild && do_kick && post) DFK_LAUNCH((k_kick0p<T, 2, true, true, true>), gr, bl, st, G, P, A, R);
       else if (rebuild && do_kick) DFK_LAUNCH((k_kick0p<T, 2, true, true, false>), gr, bl, st, G, P, A, R);
@@ -3230,7 +3269,7 @@ static void kick_compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs
   A.npart = (int)part_count(G);
   A.flog = flog;
   RedArgs<T> R{};
-  const dim3 gr = grid_of(A.b), bl(BX, BY);
+  const dim3 gr = grid_of_flat(A.b), bl(BX, BY);
   if (record(jk_kc<T>(G.bc), KcJob<T>{G, P, A, R, gr.x})) return;
   if (G.bc == 2) DFK_LAUNCH((k_kick0p<T, 2, false, true, false, true>), gr, bl, st, G, P, A, R);
   else DFK_LAUNCH((k_kick0p<T, 1, false, true, false, true>), gr, bl, st, G, P, A, R);
@@ -3349,9 +3388,9 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   A.do_heat = do_heat && P.L != 0.0;
   if (G.bc) {
     A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
-    if (record(jk_df<T>(G.bc), DiffJob<T>{G, P, A, grid_of(A.b).x})) return;
-    if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
-    else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of(A.b), dim3(BX, BY), st, G, P, A);
+    if (record(jk_df<T>(G.bc), DiffJob<T>{G, P, A, grid_of_flat(A.b).x})) return;
+    if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
+    else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
   } else {
     DFK_LAUNCH(k_diffuse_heat<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
   }
