@@ -59,6 +59,9 @@ struct df_run {
   size_t vol[MAXLEV]{};
   size_t acc_n[MAXLEV]{};
   size_t npart[MAXLEV]{};
+  // finer levels: cells beyond the active range along each dimension that
+  // CommUp into the next finer level reads after a step (0 for the finest)
+  int mobs[MAXLEV][3]{};
   size_t need = 0;
   char *base = nullptr;
   size_t bytes = 0;
@@ -110,6 +113,9 @@ struct Carver {
     return p;
   }
 };
+
+// floor(i / 2)
+int fdiv2_i(int i) { return (i >= 0) ? i / 2 : -((1 - i) / 2); }
 
 void carve(df_run *R, char *base) {
   Carver c{base};
@@ -195,12 +201,38 @@ struct TScope {
 };
 
 // ------------------------------------------------------------- scheduler
-void level_step(df_run *R, int l, const double *dtp, double scale) {
+// A finer level's step computes, in each stage, only the entries that later
+// stages, later sub-steps before the next ghost fill (rem of them) and CommUp
+// into the next finer level read: with the step's output needed to a margin m
+// beyond the active range, the rebuild and kick needs the z pass's cells to
+// m + 1, the z pass the y pass's to m + 1 (m + 3 along z), the y pass the x
+// pass's to m + 1 (m + 3 along y and z), the x pass the diffused energy and the
+// kicked faces to m + 3, the diffusion the compressed energy to m + 4, the
+// compression (and the viscosity) the kicked faces to m + 4, and the first kick
+// the state's cells to m + 5 (one more with viscosity): a step reaches 5 (6)
+// cells.  Every stage keeps its own bounds (the ghost shell) as well, so the
+// entries computed are those of the whole-shell update within the margins.
+void level_step(df_run *R, int l, const double *dtp, double scale, int rem) {
   hipStream_t st = R->stream;
-  const Geo &G = R->geo[l];
+  const Geo &G0 = R->geo[l];
   LevBufs &B = R->buf[l];
   const Phys &P = R->phys;
   int c = R->cur[l];
+  const int vs = P.visc > 0.0 ? 1 : 0;
+  int mo[3];
+  for (int d = 0; d < 3; ++d) mo[d] = R->mobs[l][d] + rem * (5 + vs);
+  auto stage = [&](int a, int b, int cc) {
+    Geo g = G0;
+    if (!g.bc) {
+      g.mg[0] = mo[0] + a;
+      g.mg[1] = mo[1] + b;
+      g.mg[2] = mo[2] + cc;
+    }
+    return g;
+  };
+  const Geo Gk = stage(4 + vs, 4 + vs, 4 + vs), Gc = stage(4, 4, 4), Gd = stage(3, 3, 3);
+  const Geo Gx = stage(1, 3, 3), Gy = stage(1, 1, 3), Gz = stage(1, 1, 1), Grk = stage(0, 0, 0);
+  const Geo &G = G0;
   const Geo *Gf = (l + 1 < R->nl) ? &R->geo[l + 1] : nullptr;
   const void *facc = Gf ? R->buf[l + 1].acc : nullptr;
   // single level: the kick sets this step's length from the last end-of-step
@@ -219,10 +251,10 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
     { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, Bd, c, dtp, scale, true, true, slots); }
     for (int d = 0; d < 3; ++d) Bt.v[d] = B.vk[d];
   } else {
-    { TScope t(R, K_KICK); dfk::kick(st, G, P, B, c, dtp, 0.5 * scale, slots); }
-    if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, G, P, B, c, dtp, scale); }
-    { TScope t(R, K_COMPRESS); dfk::compress(st, G, P, B, c, dtp, scale, slots, R->flog); }
-    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, B, c, dtp, scale, true, true); }
+    { TScope t(R, K_KICK); dfk::kick(st, Gk, P, B, c, dtp, 0.5 * scale, slots); }
+    if (P.visc > 0.0) { TScope t(R, K_VISC); dfk::viscosity(st, Gc, P, B, c, dtp, scale); }
+    { TScope t(R, K_COMPRESS); dfk::compress(st, Gc, P, B, c, dtp, scale, slots, R->flog); }
+    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, Gd, P, B, c, dtp, scale, true, true); }
   }
   // the x pass reads the new energy from the diffusion output; every buffer
   // keeps its role, so the launches of two consecutive steps repeat exactly
@@ -238,9 +270,9 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
     // whose images lie beyond the planes: the transported set's images are
     // set again after every pass
     const bool mq = Gf && G.level > 0;
-    { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, G, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_PASSX); dfk::transport_pass(st, 0, Gx, P, Bx, c, dtp, scale, Gf, facc, R->chunk); }
     if (mq) dfk::mirror_q(st, G, P, B, 1 - c);
-    { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, G, P, Bt, 1 - c, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_PASSY); dfk::transport_pass(st, 1, Gy, P, Bt, 1 - c, dtp, scale, Gf, facc, R->chunk); }
     if (mq) dfk::mirror_q(st, G, P, B, c);
   }
   // the z pass and the rebuild take the set the y pass wrote (q[c] after
@@ -257,19 +289,22 @@ void level_step(df_run *R, int l, const double *dtp, double scale) {
     zf = dfk::transport_z_finish(st, G, P, B, Bt.v, cy, dtp, scale, 0.5 * scale, post, R->chunk);
   }
   if (!zf) {
-    { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, G, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
+    { TScope t(R, K_PASSZ); dfk::transport_pass(st, 2, Gz, P, Bt, cy, dtp, scale, Gf, facc, R->chunk); }
     if (Gf && G.level > 0) dfk::mirror_q(st, G, P, B, 1 - cy);
-    { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, G, P, B, 1 - cy, dtp, 0.5 * scale, true, post); }
+    { TScope t(R, K_REBUILD); dfk::rebuild_kick(st, Grk, P, B, 1 - cy, dtp, 0.5 * scale, true, post); }
   }
   R->cur[l] = 1 - cy;
 }
 
-void cycle(df_run *R, int l) {
+// one step of level l and, first, the xi[l] sub-steps of the finer levels
+// under it; rem: sub-steps of level l that follow this one before its next
+// ghost fill
+void cycle(df_run *R, int l, int rem = 0) {
   if (l + 1 < R->nl) {
     { TScope t(R, K_ZERO); dfk::zero(R->stream, R->buf[l + 1].acc, R->acc_n[l + 1] * R->esz); }
-    for (int sub = 0; sub < R->xi[l]; ++sub) cycle(R, l + 1);
+    for (int sub = 0; sub < R->xi[l]; ++sub) cycle(R, l + 1, R->xi[l] - 1 - sub);
   }
-  level_step(R, l, &R->scal->dt[l], 1.0);
+  level_step(R, l, &R->scal->dt[l], 1.0, rem);
   if (l + 1 < R->nl) {
     { TScope t(R, K_COMMUP);
       dfk::commup(R->stream, R->geo[l], R->phys, R->buf[l], R->cur[l], R->geo[l + 1], R->buf[l + 1],
@@ -574,6 +609,7 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
       G.org[k] = G.anch[k] ? 0.0 : 0.5 * (double)G.n[k];
       G.cn[k] = G.has_fine ? n1[k] / 2 : 0;
       G.co[k] = G.has_fine ? (G.anch[k] ? 0 : (G.n[k] - G.cn[k]) / 2) : 0;
+      G.mg[k] = 1 << 20;  // no margin: the whole stored box
     }
     R->vol[l] = (size_t)G.sz * G.s[2];
     if (R->vol[l] >= ((size_t)1 << 31)) {
@@ -586,6 +622,18 @@ int df_init_mesh(const df_mesh_desc *d, df_run **out) {
     // frontier accumulators of a fine level: [dir][side][quantity][face]
     R->acc_n[l] = (l > 0) ? (size_t)3 * 2 * NQ * face_max : 0;
     R->npart[l] = dfk::part_count(G);
+  }
+  // CommUp from a finer level l into l + 1 reads the coarse hosts of the
+  // stored fine entries and one neighbour on each side (two above, for the
+  // faces): the cells of l it reaches beyond its active range, plus one
+  for (int l = 1; l + 1 < R->nl; ++l) {
+    const Geo &Gc = R->geo[l], &Gf = R->geo[l + 1];
+    for (int k = 0; k < 3; ++k) {
+      const int hmin = Gc.co[k] + (Gf.anch[k] ? 0 : fdiv2_i(-Gf.g));
+      const int hmax = Gc.co[k] + fdiv2_i(Gf.s[k] - Gf.g - 1);
+      const int lo = 1 - hmin, hi = hmax + 2 - (Gc.n[k] - 1);
+      R->mobs[l][k] = std::max(0, std::max(lo, hi)) + 1;
+    }
   }
   carve(R, nullptr);
   *out = R;
@@ -929,7 +977,7 @@ int df_debug_stage(df_run *R, int32_t stage, double dt) {
       dfk::diffuse_heat(st, G, P, B, c, dtp, 1.0, true, true);
       std::swap(B.etmp, B.q[c][1]);
       break;
-    case 7: level_step(R, 0, dtp, 1.0); break;
+    case 7: level_step(R, 0, dtp, 1.0, 0); break;
     case 8: dfk::viscosity(st, G, P, B, c, dtp, 1.0); break;
     default: return fail(DF_EINVAL, "unknown stage");
   }

@@ -33,6 +33,8 @@ struct Geo {
   int has_fine;  // a finer level covers a central box of this level
   int co[3];     // that box: first covered cell and number of covered cells (the
   int cn[3];     // finer level's cell count / 2), centred on the perturber's vertex
+  int mg[3];     // finer levels: a launch computes entries at most mg[d] cells beyond the active range
+                 // along d (faces up to face n + mg[d]), set per stage by the scheduler; large: no limit
   int anch[3];   // quadrant: the dimension starts at the perturber's mirror plane
   double org[3]; // index of the perturber's vertex along each dimension (n/2, or 0 when anchored)
 };

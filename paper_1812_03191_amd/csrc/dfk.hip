@@ -2988,6 +2988,19 @@ Box uniform_box(const Geo &G, int lo_off, int hi_off) {
   return b;
 }
 
+// A finer level's launch computes only the entries within its stage's margin
+// G.mg of the active range (the entries later stages and the level's
+// observers need); the range [lo, hi) along d, of cells or (face) of faces
+// normal to d, is cut to it.
+inline void clip_margin(const Geo &G, int d, bool face, int &lo, int &hi) {
+  lo = max(lo, -G.mg[d]);
+  hi = min(hi, G.n[d] + G.mg[d] + (face ? 1 : 0));
+}
+inline Box clip_cells(const Geo &G, Box b) {
+  for (int d = 0; d < 3; ++d) clip_margin(G, d, false, b.lo[d], b.hi[d]);
+  return b;
+}
+
 template <typename T>
 inline T *tp(void *p) {
   return reinterpret_cast<T *>(p);
@@ -3198,6 +3211,7 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
         A.flo[d][e] = -G.g + (d == e ? 3 : 2);
         A.fhi[d][e] = G.n[e] + G.g - 3;
       }
+      if (!G.bc) clip_margin(G, e, d == e, A.flo[d][e], A.fhi[d][e]);
     }
   for (int e = 0; e < 3; ++e) {
     A.b.lo[e] = min(A.flo[0][e], min(A.flo[1][e], A.flo[2][e]));
@@ -3291,7 +3305,7 @@ template <typename T>
 static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
                        double fac, Scal *log, double *flog) {
   CellArgs<T> A;
-  A.b = G.bc ? active_box(G) : uniform_box(G, 0, 1);
+  A.b = G.bc ? active_box(G) : clip_cells(G, uniform_box(G, 0, 1));
   A.e = tp<T>(B.q[cur][1]);
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.dtp = dtp;
@@ -3321,6 +3335,7 @@ static void viscosity_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B,
   for (int e = 0; e < 3; ++e) {
     A.elo[e] = G.bc ? 0 : -G.g;
     A.ehi[e] = G.bc ? G.n[e] : G.n[e] + G.g - 1;
+    if (!G.bc) clip_margin(G, e, false, A.elo[e], A.ehi[e]);
   }
   for (int d = 0; d < 3; ++d)
     for (int e = 0; e < 3; ++e) {
@@ -3330,6 +3345,7 @@ static void viscosity_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B,
       } else {
         A.flo[d][e] = -G.g + (d == e ? 1 : 0);
         A.fhi[d][e] = G.n[e] + G.g - 1;
+        clip_margin(G, e, d == e, A.flo[d][e], A.fhi[d][e]);
       }
     }
   for (int e = 0; e < 3; ++e) {
@@ -3373,7 +3389,7 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
                            double fac, bool do_diff, bool do_heat, Scal *clear) {
   DiffArgs<T> A;
   A.clear = G.bc ? clear : nullptr;
-  A.b = G.bc ? active_box(G) : uniform_box(G, 1, 1);
+  A.b = G.bc ? active_box(G) : clip_cells(G, uniform_box(G, 1, 1));
   A.rho = tp<T>(B.q[cur][0]);
   A.e = tp<T>(B.q[cur][1]);
   A.eo = tp<T>(B.etmp);
@@ -3425,6 +3441,7 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
         A.b.hi[d] = G.n[d] + G.g - 1;
       }
     }
+    A.b = clip_cells(G, A.b);
   }
   for (int m = 0; m < NQ; ++m) {
     A.qi[m] = tp<T>(B.q[src][m]);
