@@ -1418,16 +1418,31 @@ __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
   // from the first lane makes the quantity group, and so every field pointer,
   // a scalar
   const int grp = __builtin_amdgcn_readfirstlane(ty) & 1;
-  const int nbx = (A.hi[0] - A.lo[0] + 64 * W - 1) / (64 * W);
-  const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
-  const unsigned h = blockIdx.x;
-  const int bx = (int)(h % (unsigned)nbx);
-  const unsigned r1 = h / (unsigned)nbx;
-  const int tb = (int)(r1 % (unsigned)ntb);
-  const int ch = (int)(r1 / (unsigned)ntb);
-  const int i = A.lo[0] + (bx * 64 + lane) * W;  // the lane's first column (W divides the extent)
-  const int t = A.lo[TD] + tb * 2 + (ty >> 1);
-  if (i >= A.hi[0] || t >= A.hi[TD]) return;
+  int i, t, ch;
+  if (W == 1) {
+    // one column per lane: the (x, transverse) columns of the box numbered x
+    // fastest, each wave taking 64 consecutive ones (rows that are not a
+    // multiple of 64 long share waves), two waves' worth per block
+    const unsigned ex = (unsigned)(A.hi[0] - A.lo[0]), et = (unsigned)(A.hi[TD] - A.lo[TD]);
+    const unsigned nt2 = (ex * et + 127) / 128;
+    const unsigned h = blockIdx.x;
+    ch = (int)(h / nt2);
+    const unsigned f = (h % nt2) * 128 + (unsigned)(ty >> 1) * 64 + (unsigned)lane;
+    if (f >= ex * et) return;
+    i = A.lo[0] + (int)(f % ex);
+    t = A.lo[TD] + (int)(f / ex);
+  } else {
+    const int nbx = (A.hi[0] - A.lo[0] + 64 * W - 1) / (64 * W);
+    const int ntb = (A.hi[TD] - A.lo[TD] + 1) / 2;
+    const unsigned h = blockIdx.x;
+    const int bx = (int)(h % (unsigned)nbx);
+    const unsigned r1 = h / (unsigned)nbx;
+    const int tb = (int)(r1 % (unsigned)ntb);
+    ch = (int)(r1 / (unsigned)ntb);
+    i = A.lo[0] + (bx * 64 + lane) * W;  // the lane's first column (W divides the extent)
+    t = A.lo[TD] + tb * 2 + (ty >> 1);
+    if (i >= A.hi[0] || t >= A.hi[TD]) return;
+  }
   const int c0 = A.lo[DIR] + ch * A.chunk;
   const int c1 = min(c0 + A.chunk, A.hi[DIR]);
   if (c0 >= c1) return;
@@ -3485,6 +3500,7 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
   const int td = (dir == 1) ? 2 : 1;
   const long ntb = (M.hi[td] - M.lo[td] + 1) / 2;
   const long nch = (ext + M.chunk - 1) / M.chunk;
+  const long ncol = (long)(M.hi[0] - M.lo[0]) * (M.hi[td] - M.lo[td]);
   const bool front = M.acc || M.facc;
   // level 0 without frontier transfers: two adjacent columns per lane (its
   // rows start 128-byte aligned and the x extent is even) in FP32, and in FP64
@@ -3495,7 +3511,8 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
                     ? 2
                     : 1;
   const long nbx = (M.hi[0] - M.lo[0] + 64 * w - 1) / (64 * w);
-  const dim3 gr((unsigned)(nbx * ntb * nch)), bl(64, 4);
+  // one column per lane: blocks of 128 consecutive columns (k_march)
+  const dim3 gr((unsigned)(w == 1 ? (ncol + 127) / 128 * nch : nbx * ntb * nch)), bl(64, 4);
   if (!G.bc) {
     march_launch<T, 0, true, 1>(st, dir, G, P, M, gr, bl);  // finer levels always carry frontier transfers
   } else if (G.bc == 2) {
