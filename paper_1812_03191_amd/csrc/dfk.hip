@@ -1786,13 +1786,22 @@ k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
 
 // ------------------------------------------------------------ CommUp
 
+// The five state fields of one CommUp or CommMean in one launch: field f
+// takes blocks [start[f], start[f+1]).
 template <typename T>
 struct UpArgs {
-  const T *Q;   // coarse field
-  T *out;       // fine field
-  int stag;     // -1 centred, else the face normal
-  Box b;        // fine entries
+  const T *Q[NSTATE];  // coarse fields: rho, e, vx, vy, vz
+  T *out[NSTATE];      // fine fields
+  Box b;               // coarse hosts of the fine entries (every field)
+  unsigned nb;         // blocks per field
 };
+
+// element f of a five-entry argument array, for a wave-uniform f (a select
+// chain rather than an indexed load of the kernel's arguments)
+template <typename P>
+__device__ __forceinline__ P pick5(const P (&a)[NSTATE], int f) {
+  return f == 0 ? a[0] : f == 1 ? a[1] : f == 2 ? a[2] : f == 3 ? a[3] : a[4];
+}
 
 // One 1-D step of the prolongation: the value at the fine position from three
 // consecutive coarse values around the host.  Centred axes: a quarter coarse
@@ -1816,9 +1825,15 @@ __device__ __forceinline__ int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i
 // children (19 slopes instead of 8 x 13).  A.b counts hosts relative to the
 // covered coarse box (host H = Gc.co + h).
 template <typename T, int CBC>
-__global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> A) {
+__global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> UA) {
+  const int fld = (int)(blockIdx.x / UA.nb);
+  struct {
+    const T *Q;
+    T *out;
+    int stag;
+  } A{pick5(UA.Q, fld), pick5(UA.out, fld), fld >= 2 ? fld - 2 : -1};
   int h[3];
-  if (!thread_cell(A.b, h[0], h[1], h[2])) return;
+  if (!thread_cell(UA.b, h[0], h[1], h[2], Blk{blockIdx.x % UA.nb, UA.nb})) return;
   // children 2h, 2h+1 along each axis; the host is skipped when all eight are
   // active entries (which the fine level owns)
   bool inner = true;
@@ -1915,18 +1930,33 @@ __global__ void __launch_bounds__(BX * BY) k_mirror(Geo G, MirArgs<T> A) {
 
 template <typename T>
 struct MeanArgs {
-  const T *Q;   // fine field
-  T *out;       // coarse field
-  int stag;
-  Box b;        // coarse covered entries, relative to the covered box
+  const T *Q[NSTATE];      // fine fields
+  T *out[NSTATE];          // coarse fields
+  Box b;                   // covered coarse cells, relative to the covered box (faces: one more
+                           // along their normal)
+  unsigned start[NSTATE + 1];
 };
 
 // CommMean (Sect. 3.2.2): covered coarse cells take the mean of their 8 fine
 // cells, covered coarse faces the mean of their 4 coincident fine faces.
 template <typename T>
-__global__ void __launch_bounds__(BX * BY) k_commmean(Geo Gf, Geo Gc, MeanArgs<T> A) {
+__global__ void __launch_bounds__(BX * BY) k_commmean(Geo Gf, Geo Gc, MeanArgs<T> MA) {
+  const unsigned h = blockIdx.x;
+  const int fld = h < MA.start[1] ? 0 : h < MA.start[2] ? 1 : h < MA.start[3] ? 2 : h < MA.start[4] ? 3 : 4;
+  const unsigned s0 = fld == 0 ? 0u : fld == 1 ? MA.start[1] : fld == 2 ? MA.start[2] : fld == 3 ? MA.start[3] : MA.start[4];
+  const unsigned s1 = fld == 0 ? MA.start[1] : fld == 1 ? MA.start[2] : fld == 2 ? MA.start[3] : fld == 3 ? MA.start[4]
+                                                                                                 : MA.start[5];
+  struct {
+    const T *Q;
+    T *out;
+    int stag;
+  } A{pick5(MA.Q, fld), pick5(MA.out, fld), fld >= 2 ? fld - 2 : -1};
+  Box bb = MA.b;
+  bb.hi[0] += A.stag == 0 ? 1 : 0;
+  bb.hi[1] += A.stag == 1 ? 1 : 0;
+  bb.hi[2] += A.stag == 2 ? 1 : 0;
   int I, J, K;
-  if (!thread_cell(A.b, I, J, K)) return;
+  if (!thread_cell(bb, I, J, K, Blk{h - s0, s1 - s0})) return;
   const idx_t f = lin(Gf, 2 * I, 2 * J, 2 * K);
   const T *q = A.Q;
   T val;
@@ -3720,22 +3750,23 @@ static int fdiv2_host(int i) { return (i >= 0) ? i / 2 : -((1 - i) / 2); }
 
 template <typename T>
 static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const Geo &Gf, LevBufs &Bf, int curf) {
+  UpArgs<T> A;
   for (int f = 0; f < NSTATE; ++f) {
-    UpArgs<T> A;
-    A.stag = f >= 2 ? f - 2 : -1;
-    A.Q = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
-    A.out = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
-    // hosts of the stored fine entries [-g, n+g) along each axis (from the
-    // mirror plane along an anchored one: the entries beyond it are the fine
-    // level's own images, set after the fill)
-    for (int d = 0; d < 3; ++d) {
-      A.b.lo[d] = Gf.anch[d] ? 0 : fdiv2_host(-Gf.g);
-      A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
-    }
-    if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
-    else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
-    else DFK_LAUNCH((k_commup<T, 0>), grid_of(A.b), dim3(BX, BY), st, Gc, Gf, A);
+    A.Q[f] = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
+    A.out[f] = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
   }
+  // hosts of the stored fine entries [-g, n+g) along each axis (from the
+  // mirror plane along an anchored one: the entries beyond it are the fine
+  // level's own images, set after the fill)
+  for (int d = 0; d < 3; ++d) {
+    A.b.lo[d] = Gf.anch[d] ? 0 : fdiv2_host(-Gf.g);
+    A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
+  }
+  A.nb = grid_of(A.b).x;
+  const dim3 gr(A.nb * NSTATE);
+  if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), gr, dim3(BX, BY), st, Gc, Gf, A);
+  else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), gr, dim3(BX, BY), st, Gc, Gf, A);
+  else DFK_LAUNCH((k_commup<T, 0>), gr, dim3(BX, BY), st, Gc, Gf, A);
 }
 void commup(hipStream_t st, const Geo &Gc, const Phys &P, LevBufs &Bc, int curc, const Geo &Gf, LevBufs &Bf,
             int curf) {
@@ -3805,17 +3836,21 @@ void mirror_q(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int set) 
 template <typename T>
 static void commmean_t(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, const Geo &Gc, LevBufs &Bc,
                        int curc) {
+  MeanArgs<T> A;
+  A.start[0] = 0;
   for (int f = 0; f < NSTATE; ++f) {
-    MeanArgs<T> A;
-    A.stag = f >= 2 ? f - 2 : -1;
-    A.Q = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
-    A.out = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
+    const int stag = f >= 2 ? f - 2 : -1;
+    A.Q[f] = tp<T>(f == 0 ? Bf.q[curf][0] : (f == 1 ? Bf.q[curf][1] : Bf.v[f - 2]));
+    A.out[f] = tp<T>(f == 0 ? Bc.q[curc][0] : (f == 1 ? Bc.q[curc][1] : Bc.v[f - 2]));
+    Box b;
     for (int d = 0; d < 3; ++d) {
-      A.b.lo[d] = 0;
-      A.b.hi[d] = Gc.cn[d] + (d == A.stag ? 1 : 0);
+      A.b.lo[d] = b.lo[d] = 0;
+      A.b.hi[d] = Gc.cn[d];
+      b.hi[d] = Gc.cn[d] + (d == stag ? 1 : 0);
     }
-    DFK_LAUNCH(k_commmean<T>, grid_of(A.b), dim3(BX, BY), st, Gf, Gc, A);
+    A.start[f + 1] = A.start[f] + grid_of(b).x;
   }
+  DFK_LAUNCH(k_commmean<T>, dim3(A.start[NSTATE]), dim3(BX, BY), st, Gf, Gc, A);
 }
 void commmean(hipStream_t st, const Geo &Gf, const Phys &P, LevBufs &Bf, int curf, const Geo &Gc, LevBufs &Bc,
               int curc) {
