@@ -2590,12 +2590,14 @@ constexpr int ZF_TY = 2;
 constexpr int ZF_WAVES = 3 * ZF_TY + 1;
 
 // LDS planes: [2 buffers][ZF_TY + 1 row slots (slot 0: the row below the
-// band)][NQ quantities][2 * 64 cells]
+// band)][NQ quantities, then the cells' sound speeds and distances from the
+// perturber][2 * 64 cells]
+constexpr int ZF_CS = NQ, ZF_DIST = NQ + 1, ZF_NQ = NQ + 2;
 template <typename T>
 struct ZfLds {
   T *base;
   __device__ __forceinline__ T *at(int buf, int r, int m) const {
-    return base + ((buf * (ZF_TY + 1) + r) * NQ + m) * 128;
+    return base + ((buf * (ZF_TY + 1) + r) * ZF_NQ + m) * 128;
   }
 };
 
@@ -2605,6 +2607,30 @@ struct ZfLds {
 // belongs to the segment below, whose block writes it (its value there may
 // differ in the last bit, its first face transfer being formed by the walk's
 // first step rather than its loop); done() hands the plane over.
+// In FP64 the walkers also take a share of the finisher's work on their
+// plane (the finisher's work per plane is about twice a walker's, and every
+// plane ends in a barrier): the first group the cells' sound speeds (from the
+// new density and energy), the second group (and the walker of the row below)
+// the cells' distances from the perturber, and the second group the force
+// partials of the segment's planes -- with the finisher's expressions, into
+// LDS for the finisher of the row and of the row above.  (In FP32 the extra
+// registers this costs the walkers lower the occupancy from four waves per
+// SIMD to three, which costs more than the balance gains: the finisher keeps
+// that work.)
+template <typename T>
+constexpr bool zf_share() {
+  return sizeof(T) == 8;
+}
+template <typename T>
+struct ZfWork {
+  const Geo *G;
+  const Phys *P;
+  typename lanes_of<T, 2>::type xcx;  // x of the lane's two cells
+  T yc;                               // y of the row
+  double *fx, *fy, *fz;
+  int *bad;
+};
+
 template <typename T, int GRP, int NG, bool OUT>
 struct ZfSink {
   using V = typename lanes_of<T, 2>::type;
@@ -2612,11 +2638,45 @@ struct ZfSink {
   T *rho_out, *e_out;
   int r, x0, buf, plane, c0;
   bool live;
+  ZfWork<T> W;
+  V drc;
   __device__ __forceinline__ void put(int u, idx_t ic, V val) {
+    if (zf_share<T>() && u == 0 && (GRP == 1 || NG == 3)) {
+      // distances of the plane's cells (and, second group, their force terms)
+      const T zcen = xcen<T>(*W.G, 2, plane);
+      const T eps2 = (T)W.P->eps2;
+      const V r2c = W.xcx * W.xcx + W.yc * W.yc + zcen * zcen + eps2;
+      const V dcen = qsqrtv(r2c);
+      *reinterpret_cast<V *>(L.at(buf, r, ZF_DIST) + x0) = dcen;
+      if (GRP == 1 && live && plane >= c0) {
+        const T GM = (T)W.P->GM, dx = (T)W.G->dx;
+        const V w = qdiv(GM * val * (dx * dx * dx), r2c * dcen);
+        *W.fx += (double)(w.x * W.xcx.x) + (double)(w.y * W.xcx.y);
+        *W.fy += (double)(w.x * W.yc) + (double)(w.y * W.yc);
+        *W.fz += (double)(w.x * zcen) + (double)(w.y * zcen);
+      }
+    }
     if (u == 0 && GRP != 0) return;  // the first group holds the density
     const int m = u == 0 ? 0 : group_q(NG, GRP, u - 1);
     *reinterpret_cast<V *>(L.at(buf, r, m) + x0) = val;
     if (OUT && m <= 1 && live && plane >= c0) gstv<V>(m == 0 ? rho_out : e_out, ic, val);
+    if (zf_share<T>() && GRP == 0 && m == 0) drc = val;
+    if (zf_share<T>() && GRP == 0 && m == 1) {
+      // sound speeds of the plane's cells (the health check on live lanes)
+      const T rho0 = (T)W.P->rho0, e0 = (T)W.P->e0, gg = (T)(W.P->gamma * W.P->gm1);
+      V cs;
+      {
+        const T rr = rho0 + drc.x, en = e0 + val.x;
+        if (live && (!(rr > T(0)) || !(en > T(0)) || !isfinite(rr) || !isfinite(en))) *W.bad = 1;
+        cs.x = qsqrt(qdiv(gg * en, rr));
+      }
+      {
+        const T rr = rho0 + drc.y, en = e0 + val.y;
+        if (live && (!(rr > T(0)) || !(en > T(0)) || !isfinite(rr) || !isfinite(en))) *W.bad = 1;
+        cs.y = qsqrt(qdiv(gg * en, rr));
+      }
+      *reinterpret_cast<V *>(L.at(buf, r, ZF_CS) + x0) = cs;
+    }
   }
   __device__ __forceinline__ void done(int) {
     __syncthreads();
@@ -2627,7 +2687,7 @@ struct ZfSink {
 
 template <typename T, int GRP, int NG, bool OUT>
 __device__ __forceinline__ void zf_walk(const Geo &G, const Phys &P, const MarchArgs<T> &M, ZfLds<T> L, int r,
-                                        int row, int x0, bool live, int cs, int c0, int c1) {
+                                        int row, int x0, bool live, int cs, int c0, int c1, ZfWork<T> W) {
   using V = typename lanes_of<T, 2>::type;
   // lanes past the row end read the row's first cells (in bounds, unused)
   const idx_t base = lin(G, live ? x0 : 0, row, 0);
@@ -2635,14 +2695,14 @@ __device__ __forceinline__ void zf_walk(const Geo &G, const Phys &P, const March
   ColSrc<T, V, 2, 1, GRP, NG> src{qi, {M.qi[group_q(NG, GRP, 0)], M.qi[group_q(NG, GRP, 1)],
                                        M.qi[group_q(NG, GRP, 2)], M.qi[group_q(NG, GRP, 3)]},
                                   base, (idx_t)G.sz, G.n[2]};
-  ZfSink<T, GRP, NG, OUT> snk{L, M.qo[0], M.qo[1], r, x0, 0, cs, c0, live};
+  ZfSink<T, GRP, NG, OUT> snk{L, M.qo[0], M.qo[1], r, x0, 0, cs, c0, live, W, V(0)};
   march_column<T, 2, 1, GRP, false, 2, NG>(G, P, M, live ? x0 : 0, row, cs, c1, src, snk, live);
 }
 
 template <typename T>
 __device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, KickArgs<T> K, RedArgs<T> R, Blk bk) {
   using V = typename lanes_of<T, 2>::type;
-  __shared__ __align__(16) T zl[2 * (ZF_TY + 1) * NQ * 128];
+  __shared__ __align__(16) T zl[2 * (ZF_TY + 1) * ZF_NQ * 128];
   __shared__ double sh[5][ZF_WAVES];
   const ZfLds<T> L{zl};
   const int lane = threadIdx.x;
@@ -2666,13 +2726,22 @@ __device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, Kick
     R.S->tlog = R.S->t;  // the force partials of this state await the log
     R.S->pending = 1;
   }
-  if (wv == 0) {
-    // the row below the band (row 0 again for the first band: not used)
-    zf_walk<T, 0, 3, false>(G, P, M, L, 0, max(j0 - 1, 0), x0, live, cs, c0, c1);
-  } else if (wv <= 2 * ZF_TY) {
-    const int y = (wv - 1) >> 1;
-    if ((wv - 1) & 1) zf_walk<T, 1, 2, false>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1);
-    else zf_walk<T, 0, 2, true>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1);
+  if (wv <= 2 * ZF_TY) {
+    V xw;
+    xw.x = xcen<T>(G, 0, x0);
+    xw.y = xcen<T>(G, 0, x0 + 1);
+    if (wv == 0) {
+      // the row below the band (row 0 again for the first band: its sound
+      // speeds and distances are not used there)
+      const int jb = max(j0 - 1, 0);
+      zf_walk<T, 0, 3, false>(G, P, M, L, 0, jb, x0, live, cs, c0, c1,
+                              ZfWork<T>{&G, &P, xw, xcen<T>(G, 1, jb), &fx, &fy, &fz, &bad});
+    } else {
+      const int y = (wv - 1) >> 1;
+      const ZfWork<T> W{&G, &P, xw, xcen<T>(G, 1, j0 + y), &fx, &fy, &fz, &bad};
+      if ((wv - 1) & 1) zf_walk<T, 1, 2, false>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1, W);
+      else zf_walk<T, 0, 2, true>(G, P, M, L, 1 + y, j0 + y, x0, live, cs, c0, c1, W);
+    }
   } else {
     // finisher of band row y, cells x0, x0 + 1 of row j
     const int y = wv - 1 - 2 * ZF_TY, j = j0 + y, r = 1 + y;
@@ -2724,9 +2793,15 @@ __device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, Kick
       if (!live) continue;
       const V drc = ldv(buf, r, 0), dec = ldv(buf, r, 1);
       const T zcen = xcen<T>(G, 2, k);
-      const V r2c = r2of(xcx, yc, zcen);
-      const V dcen = qsqrtv(r2c);
-      const V cs_own = sound(drc, dec);
+      V dcen, cs_own, r2c;
+      if (zf_share<T>()) {
+        dcen = ldv(buf, r, ZF_DIST);  // the walkers' distances and sound speeds
+        cs_own = ldv(buf, r, ZF_CS);
+      } else {
+        r2c = r2of(xcx, yc, zcen);
+        dcen = qsqrtv(r2c);
+        cs_own = sound(drc, dec);
+      }
       const V ppz = ldv(buf, r, 7);
       if (k >= c0) {
         const idx_t c = lin(G, i, j, k);
@@ -2777,12 +2852,15 @@ __device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, Kick
           const bool lo = j > 0;
           const V drm = lo ? ldv(buf, r - 1, 0) : drc, dem = lo ? ldv(buf, r - 1, 1) : dec;
           V vf = rebuild(1, lo ? ldv(buf, r - 1, 5) : ppy, pmy, drm, drc);
-          const V dmb = qsqrtv(r2of(xcx, xcen<T>(G, 1, j - 1), zcen));
+          // the row below: its walkers' distances and sound speeds (the ghost
+          // row's distance at y = 0)
+          const V dmb = zf_share<T>() && lo ? ldv(buf, r - 1, ZF_DIST)
+                                            : qsqrtv(r2of(xcx, xcen<T>(G, 1, j - 1), zcen));
           vf = kickv(vf, drm, dem, drc, dec, V(yc), dmb, dcen);
           gstv<V>(K.v[1], c, vf);
           const V a = vabs(vf);
           vmax(a + cs_own);
-          if (lo) vmax(a + sound(drm, dem));
+          if (lo) vmax(a + (zf_share<T>() ? ldv(buf, r - 1, ZF_CS) : sound(drm, dem)));
           if (j == G.n[1] - 1) {
             const T xr = xcen<T>(G, 1, j + 1);
             const V dr_ = qsqrtv(r2of(xcx, xr, zcen));
@@ -2815,11 +2893,14 @@ __device__ __forceinline__ void zfinish_body(Geo G, Phys P, MarchArgs<T> M, Kick
           }
         }
         // force of the gas in these cells on the perturber, eq. 18: each
-        // cell's term in the storage type, the sum in FP64
-        const V w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
-        fx += (double)(w.x * xcx.x) + (double)(w.y * xcx.y);
-        fy += (double)(w.x * yc) + (double)(w.y * yc);
-        fz += (double)(w.x * zcen) + (double)(w.y * zcen);
+        // cell's term in the storage type, the sum in FP64 (in FP64 formed by
+        // the second group's walker)
+        if (!zf_share<T>()) {
+          const V w = qdiv(GM * drc * (dx * dx * dx), r2c * dcen);
+          fx += (double)(w.x * xcx.x) + (double)(w.y * xcx.y);
+          fy += (double)(w.x * yc) + (double)(w.y * yc);
+          fz += (double)(w.x * zcen) + (double)(w.y * zcen);
+        }
       }
       zr = drc;
       ze = dec;
