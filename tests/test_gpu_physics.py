@@ -301,3 +301,37 @@ def test_fig12_cold_thermal_force_chi_sweep(dfm):
     for chi in (0.1, 0.05):
         assert abs(got[chi] - 1.0) < 0.05, chi
     assert abs(got[0.01] - 1.0) < 0.08
+
+
+def test_fig12_on_the_papers_quadrant_mesh(dfm):
+    # Sect. 4.2.2's mesh itself: the quadrant bounded by the mirror planes
+    # (here y, z > 0 with the flow along x), a ground level of 64 x 64 x 128
+    # cells (128 along the flow) and finer levels of 32 x 32 x 64, the first
+    # covering the quarter next to the planes, at reduced depth (6 levels,
+    # finest cell lambda / 5); chi 0.1, Mach 0.2, 40 tau: the cold thermal
+    # force of the whole gas against eq. 51 x h, the range running to the
+    # ground level's extent from the planes
+    mach, nl, chi = 0.2, 6, 0.1
+    lam = chi / (PG * mach)
+    dxf = lam / 5.0
+    tau = T.response_time(chi, PG, mach)
+
+    def run(c):
+        r = dfm.Run(128, 64, 64, nlevels=nl, dx0=dxf * 2 ** (nl - 1), gamma=PG, noise_amp=0.0,
+                    precision=dfm.DF_FP32, n1=(64, 32, 32), quadrant=True)
+        r.set_boundaries(1)
+        r.set_perturber(GM, 0.0, 0.0, mach, c)
+        while r.force()[3] < 40 * tau:
+            r.step(50)
+        log = r.force_log()
+        return log[min(int(np.searchsorted(log[:, 3], 40 * tau)), len(log) - 1)]
+
+    diff, adi = run(chi), run(0.0)
+    assert diff[1] == 0.0 and diff[2] == 0.0  # the mirror images cancel them
+    rmax = 64 * dxf * 2 ** (nl - 1) / (2 * lam)
+    h = float(T.h_fraction(rmax) - T.h_fraction(dxf / (2 * lam)))
+    want = T.cold_thermal_force(PG, 1.0, GM) * h
+    ratio = (diff[0] - adi[0]) / want
+    _say(f"[fig12] paper's quadrant mesh, chi {chi}: {(diff[0] - adi[0]) / T.F0(1.0, GM):.4f} F0, "
+         f"{ratio:.4f} of eq. 51 x h (h = {h:.4f})")
+    assert abs(ratio - 1.0) < 0.05

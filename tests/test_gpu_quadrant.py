@@ -86,6 +86,24 @@ def test_quadrant_parity_with_oracle(dfm, n, nl, n1, steps, dx0):
     assert np.max(np.abs(tg[:3] - to) / np.abs(to)) < 1e-12, (tg, to)
 
 
+def test_quadrant_parity_on_the_papers_level_shapes(dfm):
+    # the level shapes of Sect. 4.2.2 as the quadrant: ground 64 x 64 x 128 (128
+    # along the flow, here x), finer levels 32 x 32 x 64 (3 levels)
+    _say("[quadrant] 128x64x64 + 2 levels of 64x32x32 vs oracle, 2 steps")
+    g = _gpu(dfm, 128, 3, 64, 0.16, quadrant=True, noise=1e-4)
+    o = _oracle(128, 3, 64, 0.16, 1e-4)
+    g.step(2)
+    o.step(2)
+    e0 = 1.0 / (BASE["gamma"] * (BASE["gamma"] - 1.0))
+    for lev in range(3):
+        for name in NAMES:
+            a, b = g.field(lev, name), o.full_field(lev, name)
+            assert a.shape == b.shape, (lev, name)
+            assert float(np.max(np.abs(a - b))) / (e0 if name == "e" else 1.0) < 1e-11, (lev, name)
+    fg, fo = g.force()[0], o.force()[0]
+    assert abs(fg - fo) <= 1e-9 * abs(fo), (fg, fo)
+
+
 @pytest.mark.parametrize("n,nl,n1,steps,dx0", [(32, 2, None, 4, 0.16), (64, 3, 32, 3, 0.16)])
 def test_quadrant_is_a_quarter_of_the_full_box(dfm, n, nl, n1, steps, dx0):
     # no noise: the full box then holds the quadrant's mirror images
