@@ -514,18 +514,31 @@ int graph_steps(df_run *R, int k) {
     }
     rc = hip_check(hipStreamBeginCapture(R->gstream, hipStreamCaptureModeRelaxed), "graph capture");
     if (rc) return rc;
+    // the capture records the launches without running them: the levels'
+    // buffer roles it advances are put back if it fails
+    int cur0[MAXLEV];
+    std::copy(R->cur, R->cur + R->nl, cur0);
     hipStream_t user = R->stream;
     R->stream = R->gstream;
     enqueue_steps(R, 2);
     R->stream = user;
     hipGraph_t g = nullptr;
     rc = hip_check(hipStreamEndCapture(R->gstream, &g), "graph capture end");
-    if (rc) return rc;
-    rc = hip_check(hipGraphInstantiate(&R->gexec[s], g, nullptr, nullptr, 0), "graph instantiate");
-    (void)hipGraphDestroy(g);
-    if (rc) return rc;
+    if (!rc) {
+      rc = hip_check(hipGraphInstantiate(&R->gexec[s], g, nullptr, nullptr, 0), "graph instantiate");
+      if (rc) R->gexec[s] = nullptr;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (!rc && cur_pattern(R) != pat) {
+      (void)hipGraphExecDestroy(R->gexec[s]);
+      R->gexec[s] = nullptr;
+      rc = fail(DF_ESTATE, "two coarse steps did not restore the buffer roles");
+    }
+    if (rc) {
+      std::copy(cur0, cur0 + R->nl, R->cur);
+      return rc;
+    }
     R->gpat[s] = pat;
-    if (cur_pattern(R) != pat) return fail(DF_ESTATE, "two coarse steps did not restore the buffer roles");
   }
   for (int i = 0; i < k && !rc; ++i) rc = hip_check(hipGraphLaunch(R->gexec[s], R->stream), "graph launch");
   return rc;
@@ -1241,11 +1254,28 @@ int engine_capture(df_engine *E) {
   auto cls = [](int kind) {
     return kind <= dfk::JK_KC_F2 ? 0 : kind <= dfk::JK_DF_F2 ? 1 : kind <= dfk::JK_XY_F2F ? 2 : kind <= dfk::JK_ZF_F ? 3 : 4;
   };
+  // every job's buffer roles and signal state before the capture: a capture
+  // that fails leaves the jobs where they were
+  std::vector<std::vector<int>> cur_save(act.size());
+  std::vector<char> sig_save(act.size());
   for (size_t q = 0; q < act.size(); ++q) {
     df_run *R = E->jobs[act[q]].run;
-    int cur0[MAXLEV];
-    std::copy(R->cur, R->cur + R->nl, cur0);
-    const bool sig0 = R->sig_valid, timing = R->timing;
+    cur_save[q].assign(R->cur, R->cur + R->nl);
+    sig_save[q] = R->sig_valid;
+  }
+  auto restore = [&](int code) {
+    for (size_t q = 0; q < act.size(); ++q) {
+      df_run *R = E->jobs[act[q]].run;
+      std::copy(cur_save[q].begin(), cur_save[q].end(), R->cur);
+      R->sig_valid = sig_save[q];
+    }
+    E->batched = 0;
+    E->dirty = true;
+    return code;
+  };
+  for (size_t q = 0; q < act.size(); ++q) {
+    df_run *R = E->jobs[act[q]].run;
+    const bool timing = R->timing;
     R->timing = false;
     dfk::set_recorder(&rec[q]);
     enqueue_steps(R, ENGINE_STEPS_PER_REPLAY);
@@ -1263,8 +1293,8 @@ int engine_capture(df_engine *E) {
       E->batched++;
     } else {
       // launched by the job itself below
-      std::copy(cur0, cur0 + R->nl, R->cur);
-      R->sig_valid = sig0;
+      std::copy(cur_save[q].begin(), cur_save[q].end(), R->cur);
+      R->sig_valid = sig_save[q];
     }
   }
   // the job tables: per stage of the sequence and per kind, the entries of
@@ -1313,23 +1343,22 @@ int engine_capture(df_engine *E) {
       df_engine::Tab t;
       t.cap = (host.size() + (1u << 20) - 1) / (1u << 20) * (1u << 20);
       rc = hip_check(hipMalloc(&t.dev, t.cap), "job table");
-      if (rc) return rc;
+      if (rc) return restore(rc);
       E->tabs.push_back(t);
       tab = (int)E->tabs.size() - 1;
     }
     rc = hip_check(hipMemcpyAsync(E->tabs[tab].dev, host.data(), host.size(), hipMemcpyHostToDevice, E->admin),
                    "job table upload");
     if (!rc) rc = hip_check(hipStreamSynchronize(E->admin), "job table upload");
-    if (rc) return rc;
-    E->tabs[tab].busy = true;
+    if (rc) return restore(rc);
   }
   rc = hip_check(hipStreamBeginCapture(E->cap, hipStreamCaptureModeRelaxed), "graph capture");
-  if (rc) return rc;
+  if (rc) return restore(rc);
   // a failed fork or join leaves the capture unusable: end it and report
   auto abandon = [&](int code) {
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(E->cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-    return code;
+    return restore(code);
   };
   rc = hip_check(hipEventRecord(E->fork, E->cap), "graph fork");
   for (size_t w = 0; !rc && w < E->workers.size(); ++w)
@@ -1360,9 +1389,14 @@ int engine_capture(df_engine *E) {
   if (rc) return abandon(rc);
   hipGraph_t g = nullptr;
   rc = hip_check(hipStreamEndCapture(E->cap, &g), "graph capture end");
-  if (rc) return rc;
+  if (rc) return restore(rc);
   rc = hip_check(hipGraphInstantiate(&E->exec, g, nullptr, nullptr, 0), "graph instantiate");
   (void)hipGraphDestroy(g);  // the instantiated graph does not need it
+  if (rc) {
+    E->exec = nullptr;
+    return restore(rc);
+  }
+  if (tab >= 0) E->tabs[tab].busy = true;
   E->exec_tab = tab;
   E->captures++;
   return rc;
