@@ -78,20 +78,22 @@ __device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k
   return i < b.hi[0] && j < b.hi[1];
 }
 
-// Flat tiles for the level-0 kernels that give each thread a pair of cells:
-// the (pair, row) entries of a plane are numbered row by row and each wave
-// takes 64 consecutive ones, so that rows of fewer than 64 pairs share a wave
-// (a row of 64 pairs is one wave, and the tiles are those of thread_cell);
-// blocks of four waves go to the XCDs in bands through all planes as there.
-// A lane's previous lane then holds the previous pair of its row unless the
-// lane is the first of its wave or its pair the first of its row.
+// Flat tiles, for the box kernels whose lanes do not exchange values along x
+// (and for the level-0 pair kernels, whose lanes check for it): the (x, row)
+// entries of a plane are numbered row by row and each wave takes 64
+// consecutive ones, so that rows whose length is not a multiple of 64 share
+// waves (a row of 64 entries is one wave, and the tiles are those of
+// thread_cell); blocks of four waves go to the XCDs in bands through all
+// planes as there.  A lane's previous lane then holds the previous entry of
+// its row unless the lane is the first of its wave or its entry the first of
+// its row.
 inline dim3 grid_of_flat(const Box &b) {
   const long ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return dim3(0, 1, 1);
   return dim3((unsigned)((ex * ey + BX * BY - 1) / (BX * BY) * ez), 1, 1);
 }
 
-__device__ __forceinline__ bool thread_cell_flat(const Box &b, int &i, int &j, int &k, Blk bk) {
+__device__ __forceinline__ bool thread_cell_flat(const Box &b, int &i, int &j, int &k, Blk bk = grid_blk()) {
   const unsigned ex = (unsigned)(b.hi[0] - b.lo[0]), ey = (unsigned)(b.hi[1] - b.lo[1]);
   const unsigned nby = (ex * ey + BX * BY - 1) / (BX * BY);  // blocks per plane
   const unsigned N = bk.n, h = bk.id;
@@ -396,7 +398,7 @@ struct KickArgs {
 template <typename T, bool REBUILD, bool KICK>
 __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) {
   int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
+  if (!thread_cell_flat(A.b, i, j, k)) return;
   bool need = false;
 #pragma unroll
   for (int d = 0; d < 3; ++d)
@@ -465,7 +467,7 @@ struct ViscArgs {
 template <typename T, int BC>
 __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) {
   int id[3];
-  if (!thread_cell(Box{{A.lo[0], A.lo[1], A.lo[2]}, {A.hi[0], A.hi[1], A.hi[2]}}, id[0], id[1], id[2])) return;
+  if (!thread_cell_flat(Box{{A.lo[0], A.lo[1], A.lo[2]}, {A.hi[0], A.hi[1], A.hi[2]}}, id[0], id[1], id[2])) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const T c2 = (T)P.visc, rho0 = (T)P.rho0, dx = (T)G.dx;
   auto rho_at = [&](int i, int j, int k) -> T { return BC ? cread<BC>(A.rho, G, i, j, k) : A.rho[lin(G, i, j, k)]; };
@@ -517,7 +519,7 @@ __global__ void __launch_bounds__(BX * BY) k_visc(Geo G, Phys P, ViscArgs<T> A) 
 template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_copy_faces(Geo G, Box b, T *dst, const T *src) {
   int i, j, k;
-  if (!thread_cell(b, i, j, k)) return;
+  if (!thread_cell_flat(b, i, j, k)) return;
   const idx_t c = lin(G, i, j, k);
   dst[c] = src[c];
 }
@@ -543,7 +545,7 @@ struct CellArgs {
 template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_compress(Geo G, Phys P, CellArgs<T> A) {
   int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
+  if (!thread_cell_flat(A.b, i, j, k)) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const idx_t c = lin(G, i, j, k);
   const T divv = qdiv((A.v[0][c + 1] - A.v[0][c]) + (A.v[1][c + G.sy] - A.v[1][c]) +
@@ -563,7 +565,7 @@ template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_compress2(Geo G, Phys P, CellArgs<T> A) {
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
-  if (thread_cell(A.b, p, j, k)) {
+  if (thread_cell_flat(A.b, p, j, k)) {
     const T dt = (T)(A.fac * A.dtp[0]);
     const idx_t c = lin(G, 2 * p, j, k);
     const V vx0 = gldv<V>(A.v[0], c);
@@ -612,7 +614,7 @@ __device__ __forceinline__ T dtemp(T dr, T de, T rho0, T e0) {
 template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_diffuse_heat(Geo G, Phys P, DiffArgs<T> A) {
   int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
+  if (!thread_cell_flat(A.b, i, j, k)) return;
   const T dt = (T)(A.fac * A.dtp[0]);
   const T rho0 = (T)P.rho0, e0 = (T)P.e0;
   const idx_t c = lin(G, i, j, k);
@@ -1833,7 +1835,7 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> UA
     int stag;
   } A{pick5(UA.Q, fld), pick5(UA.out, fld), fld >= 2 ? fld - 2 : -1};
   int h[3];
-  if (!thread_cell(UA.b, h[0], h[1], h[2], Blk{blockIdx.x % UA.nb, UA.nb})) return;
+  if (!thread_cell_flat(UA.b, h[0], h[1], h[2], Blk{blockIdx.x % UA.nb, UA.nb})) return;
   // children 2h, 2h+1 along each axis; the host is skipped when all eight are
   // active entries (which the fine level owns)
   bool inner = true;
@@ -1916,7 +1918,7 @@ struct MirArgs {
 template <typename T>
 __global__ void __launch_bounds__(BX * BY) k_mirror(Geo G, MirArgs<T> A) {
   int i, j, k;
-  if (!thread_cell(A.b, i, j, k)) return;
+  if (!thread_cell_flat(A.b, i, j, k)) return;
   const int id[3] = {i, j, k};
   const int m = id[A.d];  // < 0
   const idx_t c = lin(G, i, j, k), sd = dstride(G, A.d);
@@ -1956,7 +1958,7 @@ __global__ void __launch_bounds__(BX * BY) k_commmean(Geo Gf, Geo Gc, MeanArgs<T
   bb.hi[1] += A.stag == 1 ? 1 : 0;
   bb.hi[2] += A.stag == 2 ? 1 : 0;
   int I, J, K;
-  if (!thread_cell(bb, I, J, K, Blk{h - s0, s1 - s0})) return;
+  if (!thread_cell_flat(bb, I, J, K, Blk{h - s0, s1 - s0})) return;
   const idx_t f = lin(Gf, 2 * I, 2 * J, 2 * K);
   const T *q = A.Q;
   T val;
@@ -3373,7 +3375,7 @@ static void kick_t(hipStream_t st, const Geo &G, const Phys &P, void *const *q, 
     }
     return;
   }
-  const dim3 gr = grid_of(A.b);
+  const dim3 gr = grid_of_flat(A.b);
   {
     if (rebuild && do_kick) DFK_LAUNCH((k_kick<T, true, true>), gr, bl, st, G, P, A);
     else if (rebuild) DFK_LAUNCH((k_kick<T, true, false>), gr, bl, st, G, P, A);
@@ -3442,10 +3444,10 @@ static void compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, 
   A.flog = flog;
   if (G.bc) {
     A.b.hi[0] = G.n[0] / 2;  // cell pairs: level-0 rows have an even length
-    DFK_LAUNCH(k_compress2<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+    DFK_LAUNCH(k_compress2<T>, grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
     return;
   }
-  DFK_LAUNCH(k_compress<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+  DFK_LAUNCH(k_compress<T>, grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
 }
 void compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double fac,
               Scal *log, double *flog) {
@@ -3491,16 +3493,16 @@ static void viscosity_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B,
     ub.lo[e] = A.lo[e];
     ub.hi[e] = A.hi[e];
   }
-  if (G.bc == 2) DFK_LAUNCH((k_visc<T, 2>), grid_of(ub), dim3(BX, BY), st, G, P, A);
-  else if (G.bc) DFK_LAUNCH((k_visc<T, 1>), grid_of(ub), dim3(BX, BY), st, G, P, A);
-  else DFK_LAUNCH((k_visc<T, 0>), grid_of(ub), dim3(BX, BY), st, G, P, A);
+  if (G.bc == 2) DFK_LAUNCH((k_visc<T, 2>), grid_of_flat(ub), dim3(BX, BY), st, G, P, A);
+  else if (G.bc) DFK_LAUNCH((k_visc<T, 1>), grid_of_flat(ub), dim3(BX, BY), st, G, P, A);
+  else DFK_LAUNCH((k_visc<T, 0>), grid_of_flat(ub), dim3(BX, BY), st, G, P, A);
   for (int d = 0; d < 3; ++d) {
     Box fb;
     for (int e = 0; e < 3; ++e) {
       fb.lo[e] = A.flo[d][e];
       fb.hi[e] = A.fhi[d][e];
     }
-    DFK_LAUNCH((k_copy_faces<T>), grid_of(fb), dim3(BX, BY), st, G, fb, tp<T>(B.v[d]), A.vn[d]);
+    DFK_LAUNCH((k_copy_faces<T>), grid_of_flat(fb), dim3(BX, BY), st, G, fb, tp<T>(B.v[d]), A.vn[d]);
   }
 }
 
@@ -3534,7 +3536,7 @@ static void diffuse_heat_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
     if (G.bc == 2) DFK_LAUNCH((k_diffuse_heat2<T, 2>), grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
     else DFK_LAUNCH((k_diffuse_heat2<T, 1>), grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
   } else {
-    DFK_LAUNCH(k_diffuse_heat<T>, grid_of(A.b), dim3(BX, BY), st, G, P, A);
+    DFK_LAUNCH(k_diffuse_heat<T>, grid_of_flat(A.b), dim3(BX, BY), st, G, P, A);
   }
 }
 void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
@@ -3843,7 +3845,7 @@ static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const
     A.b.lo[d] = Gf.anch[d] ? 0 : fdiv2_host(-Gf.g);
     A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
   }
-  A.nb = grid_of(A.b).x;
+  A.nb = grid_of_flat(A.b).x;
   const dim3 gr(A.nb * NSTATE);
   if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), gr, dim3(BX, BY), st, Gc, Gf, A);
   else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), gr, dim3(BX, BY), st, Gc, Gf, A);
@@ -3874,7 +3876,7 @@ static void mirror_state_t(hipStream_t st, const Geo &G, LevBufs &B, int cur) {
       A.b.lo[e] = -G.g;
       A.b.hi[e] = e == d ? 0 : G.s[e] - G.g;
     }
-    DFK_LAUNCH(k_mirror<T>, grid_of(A.b), dim3(BX, BY), st, G, A);
+    DFK_LAUNCH(k_mirror<T>, grid_of_flat(A.b), dim3(BX, BY), st, G, A);
   }
 }
 
@@ -3898,7 +3900,7 @@ static void mirror_q_t(hipStream_t st, const Geo &G, LevBufs &B, int set) {
       A.b.lo[e] = -G.g;
       A.b.hi[e] = e == d ? 0 : G.s[e] - G.g;
     }
-    DFK_LAUNCH(k_mirror<T>, grid_of(A.b), dim3(BX, BY), st, G, A);
+    DFK_LAUNCH(k_mirror<T>, grid_of_flat(A.b), dim3(BX, BY), st, G, A);
   }
 }
 
@@ -3929,7 +3931,7 @@ static void commmean_t(hipStream_t st, const Geo &Gf, LevBufs &Bf, int curf, con
       A.b.hi[d] = Gc.cn[d];
       b.hi[d] = Gc.cn[d] + (d == stag ? 1 : 0);
     }
-    A.start[f + 1] = A.start[f] + grid_of(b).x;
+    A.start[f + 1] = A.start[f] + grid_of_flat(b).x;
   }
   DFK_LAUNCH(k_commmean<T>, dim3(A.start[NSTATE]), dim3(BX, BY), st, Gf, Gc, A);
 }
