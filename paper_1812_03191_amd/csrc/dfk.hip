@@ -1147,6 +1147,82 @@ __global__ void __launch_bounds__(BX * BY) k_xrow(Geo G, Phys P, PassArgs<T> A) 
   }
 }
 
+// Row form of the x pass on a finer level (no boundary conditions: the
+// stored row holds the ghost cells): one wave per row, lane l the R cells
+// xs + R l .. xs + R l + R - 1 from the R-aligned start xs <= lo - 2, so that
+// the wave covers the cells [lo - 2, hi + 2) every update of [lo, hi) reads.
+// The arithmetic is XRow's (that of k_xpass); the cells outside [lo, hi) are
+// computed and not written, and the frontier transfers are taken (the finer
+// level's sums at the covered box's faces) and accumulated (this level's own
+// at faces 0 and n) as k_xpass does.
+template <typename T, int R>
+__global__ void __launch_bounds__(BX * BY) k_xrow_fine(Geo G, Phys P, PassArgs<T> A, int xs) {
+  int lane, j, k;
+  if (!thread_cell_flat(xrow_box(A.b), lane, j, k)) return;
+  const int n = G.n[0];
+  const int x0 = xs + R * lane;
+  // the lane's cells lie within the row's padded storage, which starts px
+  // entries before x = 0 (loads past it are not made; the padding is read as
+  // the neighbours of cells outside the range the update reads)
+  const int px = (int)(G.off - (long)G.g * (G.sy + G.sz));
+  const bool live = x0 >= -px && x0 + R <= (int)G.sy - px;
+  const idx_t c = lin(G, x0, j, k);
+  XRow<T, R> X;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    X.dr[r] = T(0);
+    X.da[r] = T(0);
+  }
+  if (live) {
+    row_load<T, R>(A.qi[0], c, X.dr);
+    row_load<T, R>(A.v[0], c, X.da);
+  }
+  X.begin(G, P, (T)(A.fac * A.dtp[0]));
+  const bool ov = A.facc && j - G.co[1] >= 0 && k - G.co[2] >= 0 && j - G.co[1] < G.cn[1] && k - G.co[2] < G.cn[2];
+  const int flo = G.co[0], fhi = G.co[0] + G.cn[0];
+  const long fnt = (long)A.fn[1] * A.fn[2];
+  const long fbase = (long)(2 * (k - G.co[2])) * A.fn[1] + 2 * (j - G.co[1]);
+  const bool accrow = A.acc && j >= 0 && k >= 0 && j < G.n[1] && k < G.n[2];
+  const long acc_nt = (long)G.n[1] * G.n[2], acc_i = (long)k * G.n[1] + j;
+  // the lane's cells all inside the updated range: one vector store
+  const bool inner = x0 >= A.b.lo[0] && x0 + R <= A.b.hi[0];
+  auto finish = [&](int m, const T (&own)[R], T (&FL)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int x = x0 + r;
+      if (ov && (x == flo || x == fhi)) {
+        const T *f = A.facc + ((long)(x == fhi) * NQ + m) * fnt + fbase;
+        FL[r] = (f[0] + f[1]) + (f[A.fn[1]] + f[A.fn[1] + 1]);
+      }
+      if (accrow && (x == 0 || x == n)) A.acc[((long)(x == n) * NQ + m) * acc_nt + acc_i] += FL[r];
+    }
+    T out[R];
+    X.update(own, FL, out);
+    if (inner) {
+      row_store<T, R>(A.qo[m], c, out);
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (x0 + r >= A.b.lo[0] && x0 + r < A.b.hi[0]) A.qo[m][c + r] = out[r];
+    }
+  };
+  {
+    T F[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) F[r] = X.dM[r];
+    finish(0, X.dr, F);
+  }
+
+#pragma unroll 1
+  for (int m = 1; m < NQ; ++m) {
+    T in[R], sv[R], own[R], F[R];
+    xrow_input<T, R>(G, A, m, c, live, X.da, in);
+    X.quantity(P, m, in, sv, own);
+    X.transfers(P, m, sv, F);
+    finish(m, own, F);
+  }
+}
+
 // Streaming form of the y and z passes.  A thread owns one column segment
 // [c0, c1) along DIR (lanes along x, so every load is coalesced) and walks it
 // once: each cell is loaded once (one iteration ahead of its use), each limited
@@ -3589,7 +3665,20 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
     else if (G.bc && n <= 2 * BX && n % 2 == 0) DFK_LAUNCH((k_xrow<T, 2>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc && n <= 4 * BX && n % 4 == 0) DFK_LAUNCH((k_xrow<T, 4>), grid_of(xrow_box(A.b)), bl, st, G, P, A);
     else if (G.bc) DFK_LAUNCH((k_xpass<T, 1>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
-    else DFK_LAUNCH((k_xpass<T, 0>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    else {
+      // finer levels: a row per wave when the cells the update reads, from an
+      // aligned start, fit 64 R of them (in FP64 R <= 2: four cells per lane
+      // take 138 registers, and the overlapping tiles were faster); else the
+      // overlapping tiles
+      const int x1 = A.b.hi[0] + 2;
+      auto start = [&](int R) { return A.b.lo[0] - 2 - (((A.b.lo[0] - 2) % R) + R) % R; };
+      if (x1 - start(1) <= BX) DFK_LAUNCH((k_xrow_fine<T, 1>), grid_of_flat(xrow_box(A.b)), bl, st, G, P, A, start(1));
+      else if (x1 - start(2) <= 2 * BX)
+        DFK_LAUNCH((k_xrow_fine<T, 2>), grid_of_flat(xrow_box(A.b)), bl, st, G, P, A, start(2));
+      else if (sizeof(T) == 4 && x1 - start(4) <= 4 * BX)
+        DFK_LAUNCH((k_xrow_fine<T, 4>), grid_of_flat(xrow_box(A.b)), bl, st, G, P, A, start(4));
+      else DFK_LAUNCH((k_xpass<T, 0>), grid_of(xtile_box(A.b)), bl, st, G, P, A);
+    }
     return;
   }
   MarchArgs<T> M;
