@@ -1871,6 +1871,12 @@ struct UpArgs {
   const T *Q[NSTATE];  // coarse fields: rho, e, vx, vy, vz
   T *out[NSTATE];      // fine fields
   Box b;               // coarse hosts of the fine entries (every field)
+  // hosts whose eight children are all active fine cells ([0, n/2) along each
+  // axis, relative to b.lo) are not enumerated: the shell around them is, in
+  // three parts -- the planes outside them (all rows), the rows outside them
+  // in their planes, the hosts outside them in their rows
+  int in_lo[3], in_n[3];
+  unsigned c1, c2, nshell;
   unsigned nb;         // blocks per field
 };
 
@@ -1911,7 +1917,33 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> UA
     int stag;
   } A{pick5(UA.Q, fld), pick5(UA.out, fld), fld >= 2 ? fld - 2 : -1};
   int h[3];
-  if (!thread_cell_flat(UA.b, h[0], h[1], h[2], Blk{blockIdx.x % UA.nb, UA.nb})) return;
+  {
+    const unsigned f = (blockIdx.x % UA.nb) * (BX * BY) + threadIdx.y * BX + threadIdx.x;
+    if (f >= UA.nshell) return;
+    const unsigned X = (unsigned)(UA.b.hi[0] - UA.b.lo[0]), Y = (unsigned)(UA.b.hi[1] - UA.b.lo[1]);
+    unsigned x, y, z;
+    if (f < UA.c1) {
+      z = f / (X * Y);
+      y = (f % (X * Y)) / X;
+      x = f % X;
+      if ((int)z >= UA.in_lo[2]) z += UA.in_n[2];
+    } else if (f < UA.c2) {
+      const unsigned g = f - UA.c1, ny = Y - UA.in_n[1];
+      z = UA.in_lo[2] + g / (ny * X);
+      y = (g % (ny * X)) / X;
+      x = g % X;
+      if ((int)y >= UA.in_lo[1]) y += UA.in_n[1];
+    } else {
+      const unsigned g = f - UA.c2, nx = X - UA.in_n[0];
+      z = UA.in_lo[2] + g / (UA.in_n[1] * nx);
+      y = UA.in_lo[1] + (g % (UA.in_n[1] * nx)) / nx;
+      x = g % nx;
+      if ((int)x >= UA.in_lo[0]) x += UA.in_n[0];
+    }
+    h[0] = UA.b.lo[0] + (int)x;
+    h[1] = UA.b.lo[1] + (int)y;
+    h[2] = UA.b.lo[2] + (int)z;
+  }
   // children 2h, 2h+1 along each axis; the host is skipped when all eight are
   // active entries (which the fine level owns)
   bool inner = true;
@@ -3934,7 +3966,19 @@ static void commup_t(hipStream_t st, const Geo &Gc, LevBufs &Bc, int curc, const
     A.b.lo[d] = Gf.anch[d] ? 0 : fdiv2_host(-Gf.g);
     A.b.hi[d] = fdiv2_host(Gf.s[d] - Gf.g - 1) + 1;
   }
-  A.nb = grid_of_flat(A.b).x;
+  // the inner hosts, relative to b.lo (every fine child an active cell)
+  unsigned ext[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = (unsigned)(A.b.hi[d] - A.b.lo[d]);
+    const int lo = std::max(0, -A.b.lo[d]), hi = std::min((int)ext[d], Gf.n[d] / 2 - A.b.lo[d]);
+    A.in_lo[d] = lo;
+    A.in_n[d] = std::max(0, hi - lo);
+  }
+  if (A.in_n[0] == 0 || A.in_n[1] == 0 || A.in_n[2] == 0) A.in_n[0] = A.in_n[1] = A.in_n[2] = 0;
+  A.c1 = (ext[2] - A.in_n[2]) * ext[0] * ext[1];
+  A.c2 = A.c1 + A.in_n[2] * (ext[1] - A.in_n[1]) * ext[0];
+  A.nshell = A.c2 + A.in_n[2] * A.in_n[1] * (ext[0] - A.in_n[0]);
+  A.nb = (A.nshell + BX * BY - 1) / (BX * BY);
   const dim3 gr(A.nb * NSTATE);
   if (Gc.bc == 2) DFK_LAUNCH((k_commup<T, 2>), gr, dim3(BX, BY), st, Gc, Gf, A);
   else if (Gc.bc) DFK_LAUNCH((k_commup<T, 1>), gr, dim3(BX, BY), st, Gc, Gf, A);
