@@ -716,17 +716,6 @@ __global__ void __launch_bounds__(BX * BY) k_diffuse_heat2(Geo G, Phys P, DiffAr
 
 // -------------------------------------------------------------- transport
 
-// upwind van Leer face value from the values of the cells -2..+1 around the
-// face: a > 0 takes the low-side cell, else the high-side cell, each with its
-// limited difference and the Courant-number correction (the weights
-// (1 - nu)/2 and (1 + nu)/2 are exact halvings, so that each side is one
-// rounding of s + d w)
-template <typename T>
-__device__ __forceinline__ T face_value(T sm2, T sm1, T s0, T sp1, T a, T nu) {
-  if (a > T(0)) return sm1 + vleer(s0 - sm1, sm1 - sm2) * (T(0.5) * (T(1) - nu));
-  return s0 - vleer(sp1 - s0, s0 - sm1) * (T(0.5) * (T(1) + nu));
-}
-
 template <typename T>
 struct PassArgs {
   Box b;
@@ -1887,19 +1876,6 @@ __device__ __forceinline__ P pick5(const P (&a)[NSTATE], int f) {
   return f == 0 ? a[0] : f == 1 ? a[1] : f == 2 ? a[2] : f == 3 ? a[3] : a[4];
 }
 
-// One 1-D step of the prolongation: the value at the fine position from three
-// consecutive coarse values around the host.  Centred axes: a quarter coarse
-// cell either side of the host centre with van Leer's limited slope.  Along a
-// face field's own axis: an even fine face is the host coarse face, an odd one
-// the mean of the host face and the next.
-template <typename T>
-__device__ __forceinline__ T up1d(bool stag_axis, int odd, T m, T c, T p) {
-  if (stag_axis) return odd ? T(0.5) * (c + p) : c;
-  return c + vleer(p - c, c - m) * (odd ? T(0.25) : T(-0.25));
-}
-
-__device__ __forceinline__ int fdiv2(int i) { return (i >= 0) ? i / 2 : -((1 - i) / 2); }
-
 // CommUp (Sect. 3.2.1, Fig. 2): every fine entry outside the fine active set
 // from the 27 coarse entries around its host, interpolating along z, then y,
 // then x.  The background is uniform, so departures interpolate like values.
@@ -1962,7 +1938,11 @@ __global__ void __launch_bounds__(BX * BY) k_commup(Geo Gc, Geo Gf, UpArgs<T> UA
     }
     return A.Q[lin(Gc, ci, cj, ck)];
   };
-  // both children of one 1-D step
+  // both children of one 1-D step of the prolongation, from three
+  // consecutive coarse values around the host: on centred axes a quarter
+  // coarse cell either side of the host centre with van Leer's limited slope;
+  // along a face field's own axis the even child is the host face, the odd
+  // one the mean of the host face and the next
   auto up2 = [&](bool stag_axis, T m, T c, T p, T &lo, T &hi) {
     if (stag_axis) {
       lo = c;
