@@ -3,7 +3,8 @@ lengths the workloads use: the 128^3 single-level workload over 100 steps in
 FP64 (every field within 1e-11 of its scale, the force within 1e-9) and with
 FP32 departure storage (force within 1e-4, totals within 1e-6); four nested
 levels of 32^3 (the nested workload at reduced size) over 20 coarse steps in
-both precisions; and runs at every column-segment length the autotuner can
+both precisions; two levels of 128^3 (the nested workload's level shape)
+over 2 coarse steps in both precisions; and runs at every column-segment length the autotuner can
 choose, against the default length and the oracle."""
 import sys
 
@@ -124,6 +125,40 @@ def test_nested_four_levels_fp32_against_oracle(dfm, nested_ref):
     _say("[full parity] 4 x 32^3 FP32 x 20")
     g = _gpu(dfm, cfg, 20, dfm.DF_FP32)
     _check_fp32(g, ref, "4 x 32^3")
+
+
+@pytest.fixture(scope="module")
+def nested128_ref():
+    # the nested workload's level shape itself, at two levels and two coarse
+    # steps: the finer level's rows with their margins are 130-148 cells, so
+    # its x pass takes the wave-row form with four cells per lane (FP32) or the
+    # overlapping tiles (FP64), and its walks rows longer than a wave
+    cfg, _ = inputs.config3()
+    cfg = dict(cfg, nlevels=2, dx0=cfg["dx0"] / 4)
+    _say("[full parity] oracle: 2 levels of 128^3 x 2 coarse steps")
+    return cfg, _oracle(cfg, 2)
+
+
+def test_nested_128_levels_parity_fp64(dfm, nested128_ref):
+    cfg, ref = nested128_ref
+    _say("[full parity] 2 x 128^3 FP64 x 2")
+    g = _gpu(dfm, cfg, 2, dfm.DF_FP64)
+    _check_fp64(g, ref, 2, "2 x 128^3 FP64")
+
+
+def test_nested_128_levels_fp32_against_oracle(dfm, nested128_ref):
+    cfg, ref = nested128_ref
+    _say("[full parity] 2 x 128^3 FP32 x 2")
+    g = _gpu(dfm, cfg, 2, dfm.DF_FP32)
+    _check_fp32(g, ref, "2 x 128^3")
+    # every field of both levels against the oracle, in units of its scale:
+    # FP32 holds the departures from the background, which stay below 6e-4 of
+    # the scale over these two steps, so each store rounds by at most
+    # 2^-24 * 6e-4; a few tens of such roundings bound the error (2.3e-9)
+    worst = max(float(np.max(np.abs(g.field(lev, name) - ref["fields"][(lev, name)]))) / SCALE[name]
+                for lev in range(2) for name in FIELD_NAMES)
+    _say(f"[2 x 128^3] FP32 worst field error {worst:.2e}")
+    assert worst < 64 * 2.0 ** -24 * 6e-4
 
 
 # column-segment lengths (tile_chunk) of the streaming y and z passes and of
