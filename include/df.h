@@ -72,7 +72,8 @@ typedef struct df_run df_run;
  *  seed, noise_amp : every active density is multiplied by 1 + noise_amp (2U-1),
  *               U uniform in [0,1) from a counter-based SplitMix64 stream;
  *  tile_chunk : cells per column segment of the streaming y and z transport
- *               passes (0 selects 32 for FP64 and 16 for FP32 storage; 2..256),
+ *               passes (0 selects 16 for FP32 storage, and for FP64 32 on one
+ *               level and 8 on nested meshes; 2..256),
  *               a launch-shape parameter that does not change results;
  *  nx1, ny1, nz1 : cells of every level >= 1 (0: those of level 0), each a
  *               multiple of 4, >= 16 and at most twice level 0's count.  Level

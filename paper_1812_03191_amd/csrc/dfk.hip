@@ -161,6 +161,12 @@ struct lanes_of<float, 2> {
   using type = float __attribute__((ext_vector_type(2)));
 };
 
+// a * b + c with one rounding, per element of a lane vector
+template <typename V>
+__device__ __forceinline__ V fmav(V a, V b, V c) {
+  return __builtin_elementwise_fma(a, b, c);
+}
+
 template <typename V, typename T>
 __device__ __forceinline__ V gldv(const T *p, idx_t i) {
   return *reinterpret_cast<const V *>(reinterpret_cast<const char *>(p) + (unsigned)i * (unsigned)sizeof(T));
@@ -961,6 +967,7 @@ struct XRow {
 
   // face velocities and Courant numbers of the row
   __device__ __forceinline__ void flow(const Geo &G, const Phys &P, T dt_) {
+#pragma clang fp contract(off)
     dt = dt_;
     dx = (T)G.dx;
     mfac = dt * dx * dx;
@@ -973,12 +980,13 @@ struct XRow {
     for (int r = 0; r < R; ++r) {
       a[r] = vb + da[r];
       const T nu = a[r] * cour;
-      hl[r] = T(0.5) * (T(1) - nu);
-      hh[r] = T(0.5) * (T(1) + nu);
+      hl[r] = fmav<T>(T(-0.5), nu, T(0.5));  // (1 -+ nu)/2, exact halvings of the rounded 1 -+ nu
+      hh[r] = fmav<T>(T(0.5), nu, T(0.5));
     }
   }
   // the mass transfers through the left faces (departures dm_)
   __device__ __forceinline__ void take_mass(const T (&dm_)[R]) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       dM[r] = dm_[r];
@@ -986,13 +994,15 @@ struct XRow {
     }
   }
   __device__ __forceinline__ void mass() {
+#pragma clang fp contract(off)
     T fv[R], dm_[R];
     left_faces(dr, fv);
 #pragma unroll
-    for (int r = 0; r < R; ++r) dm_[r] = (rho0 * da[r] + fv[r] * a[r]) * mfac;
+    for (int r = 0; r < R; ++r) dm_[r] = fmav<T>(fv[r], a[r], rho0 * da[r]) * mfac;
     take_mass(dm_);
   }
   __device__ __forceinline__ void recip() {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int r = 0; r < R; ++r) irr[r] = qdiv(T(1), rho0 * (rho0 + dr[r]));
   }
@@ -1003,6 +1013,7 @@ struct XRow {
   }
   // left-face value of the upwind van Leer reconstruction of s, per cell
   __device__ __forceinline__ void left_faces(const T (&sv)[R], T (&fv)[R]) const {
+#pragma clang fp contract(off)
     T sl[R], sr[R], d[R], dl[R];
     row_left<T, R>(sv, sl, sv[0]);
     row_right<T, R>(sv, sr, T(0));
@@ -1012,7 +1023,7 @@ struct XRow {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       // both upwind values, then a select (a branch per face costs more)
-      const T lo = sl[r] + dl[r] * hl[r], hi = sv[r] - d[r] * hh[r];
+      const T lo = fmav<T>(dl[r], hl[r], sl[r]), hi = fmav<T>(-d[r], hh[r], sv[r]);
       fv[r] = a[r] > T(0) ? lo : hi;
     }
   }
@@ -1020,37 +1031,40 @@ struct XRow {
   // energy departure (m = 1) or the face velocity whose momentum it is
   __device__ __forceinline__ void quantity(const Phys &P, int m, const T (&in)[R], T (&sv)[R],
                                            T (&own)[R]) const {
+#pragma clang fp contract(off)
     if (m >= 2) {
       // momentum P = rho v of a face velocity: its specific value is v itself
       const T vbd = (T)vback(P, (m - 2) >> 1);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         sv[r] = in[r];
-        own[r] = rho0 * sv[r] + dr[r] * (vbd + sv[r]);
+        own[r] = fmav<T>(dr[r], vbd + sv[r], rho0 * sv[r]);
       }
     } else {
       const T q0 = (T)qback(P, m);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        sv[r] = (rho0 * in[r] - q0 * dr[r]) * irr[r];
+        sv[r] = fmav<T>(rho0, in[r], -(q0 * dr[r])) * irr[r];
         own[r] = in[r];
       }
     }
   }
   // transfers of quantity m through the left faces
   __device__ __forceinline__ void transfers(const Phys &P, int m, const T (&sv)[R], T (&F)[R]) const {
+#pragma clang fp contract(off)
     T fv[R];
     left_faces(sv, fv);
     const T s0 = (T)sback(P, m);
 #pragma unroll
-    for (int r = 0; r < R; ++r) F[r] = s0 * dM[r] + fv[r] * M[r];
+    for (int r = 0; r < R; ++r) F[r] = fmav<T>(s0, dM[r], fv[r] * M[r]);
   }
   // updated departures from the left-face transfers (none through x_max)
   __device__ __forceinline__ void update(const T (&own)[R], const T (&FL)[R], T (&out)[R]) const {
+#pragma clang fp contract(off)
     T FR[R];
     row_right<T, R>(FL, FR, T(0));
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = own[r] - (FR[r] - FL[r]) * ivol;
+    for (int r = 0; r < R; ++r) out[r] = fmav<T>(-(FR[r] - FL[r]), ivol, own[r]);
   }
 };
 
@@ -1292,6 +1306,11 @@ struct ColSrc {
 template <typename T, int DIR, int BC, int GRP, bool FRONT, int W, int NG, typename Src, typename Sink>
 __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const MarchArgs<T> &A,
                                              int i, int t, int c0, int c1, Src &src, Sink &snk, bool live) {
+  // the transfer through a segment's first face is formed before the walk and
+  // again, by the segment below, inside it: with no implicit contraction and
+  // the fused products written out, both give the same value, so the results
+  // do not depend on where segments start
+#pragma clang fp contract(off)
   static_assert(W == 1 || !FRONT, "frontier transfers are per column");
   using V = typename lanes_of<T, W>::type;  // the W adjacent columns of a lane
   constexpr int TD = (DIR == 1) ? 2 : 1;
@@ -1359,11 +1378,22 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   };
   // the face's weights hl = (1 - nu)/2, hh = (1 + nu)/2 are exact halvings
   auto upwind = [&](V sl, V dl, V sr, V dr, V a, V hl, V hh) -> V {
-    const V lo = sl + dl * hl, hi = sr - dr * hh;
+    const V lo = fmav<V>(dl, hl, sl), hi = fmav<V>(-dr, hh, sr);
     return a > T(0) ? lo : hi;
   };
-  // departure of the specific value of quantity u from raw departures (q, rho)
-  auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
+  // numerator of the departure of quantity u's specific value from raw
+  // departures (q, rho): times 1/(rho0 rho) it is the value
+  auto numer = [&](int u, V q, V r) -> V { return zq[u] ? rho0 * q : fmav<V>(V(rho0), q, -(q0[u] * r)); };
+  // limited difference at a cell of value s from its left neighbour's value sl
+  // and its right neighbour's numerator and reciprocal (xr, ir): the right
+  // difference takes the neighbour's value unrounded, the left one the values
+  auto limited = [&](V xr, V ir, V s, V sl) -> V { return vleer(fmav<V>(xr, ir, -s), s - sl); };
+  // Courant weights of a face: (1 -+ nu)/2, exact halvings of the rounded 1 -+ nu
+  auto weights = [&](V a, V &hl, V &hh) {
+    const V nu = a * cour;
+    hl = fmav<V>(V(-0.5), nu, V(0.5));
+    hh = fmav<V>(V(0.5), nu, V(0.5));
+  };
   // velocity departure on face c (normal to DIR)
   auto face = [&](int c) -> V { return live ? gldv<V>(A.v, base + c * st) : V(0); };
 
@@ -1375,38 +1405,43 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
   V s0[5], s1[5], d0[5], F0[5], w0[5], w1[5], w2[5];
   V va;
   {
-    V rm2[5], rm1[5], sm2[5], sm1[5];
+    // the density (u = 0) is its own value: numerator the raw departure,
+    // reciprocal 1
+    V rm2[5], rm1[5], sm2[5], sm1[5], x0[5], x1[5];
     src.get(c0 - 2, rm2);
     src.get(c0 - 1, rm1);
     src.get(c0, w0);
     src.get(c0 + 1, w1);
     const V ir_m2 = qdiv(V(1), rho0 * (rho0 + rm2[0])), ir_m1 = qdiv(V(1), rho0 * (rho0 + rm1[0]));
     const V ir_0 = qdiv(V(1), rho0 * (rho0 + w0[0])), ir_p1 = qdiv(V(1), rho0 * (rho0 + w1[0]));
-    sm2[0] = rm2[0]; sm1[0] = rm1[0]; s0[0] = w0[0]; s1[0] = w1[0];
+    sm2[0] = rm2[0]; sm1[0] = rm1[0]; s0[0] = x0[0] = w0[0]; s1[0] = x1[0] = w1[0];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       if (u >= nq) break;
-      sm2[u + 1] = spec(u, rm2[u + 1], rm2[0], ir_m2);
-      sm1[u + 1] = spec(u, rm1[u + 1], rm1[0], ir_m1);
-      s0[u + 1] = spec(u, w0[u + 1], w0[0], ir_0);
-      s1[u + 1] = spec(u, w1[u + 1], w1[0], ir_p1);
+      sm2[u + 1] = numer(u, rm2[u + 1], rm2[0]) * ir_m2;
+      sm1[u + 1] = numer(u, rm1[u + 1], rm1[0]) * ir_m1;
+      x0[u + 1] = numer(u, w0[u + 1], w0[0]);
+      x1[u + 1] = numer(u, w1[u + 1], w1[0]);
+      s0[u + 1] = x0[u + 1] * ir_0;
+      s1[u + 1] = x1[u + 1] * ir_p1;
     }
     const V da = face(c0);
-    const V a = wind ? vb + da : da, nu = a * cour;
-    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
+    const V a = wind ? vb + da : da;
+    V hl, hh;
+    weights(a, hl, hh);
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
       if (u > nq) break;
-      const V dm1 = vleer(s0[u] - sm1[u], sm1[u] - sm2[u]);
-      d0[u] = vleer(s1[u] - s0[u], s0[u] - sm1[u]);
+      const V dm1 = limited(x0[u], u ? ir_0 : V(1), sm1[u], sm2[u]);
+      d0[u] = limited(x1[u], u ? ir_p1 : V(1), s0[u], sm1[u]);
       const V fv = upwind(sm1[u], dm1, s0[u], d0[u], a, hl, hh);
       if (u == 0) {
-        dM = (rho0 * da + fv * a) * mfac;
+        dM = fmav<V>(fv, a, rho0 * da) * mfac;
         M = wind ? M0 + dM : dM;
         F0[0] = GRP ? dM : fix(c0, 0, dM);  // the density belongs to the first group
       } else {
-        F0[u] = fix(c0, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
+        F0[u] = fix(c0, mq[u - 1], zq[u - 1] ? fv * M : fmav<V>(V(sb[u - 1]), dM, fv * M));
       }
     }
     src.get(c0 + 2, w2);
@@ -1420,29 +1455,34 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
     src.get(c + 3, nn);
     const V vn = face(min(c + 2, c1));
     const V ir2 = qdiv(V(1), rho0 * (rho0 + w2[0]));
-    V s2[5];
-    s2[0] = w2[0];
+    V s2[5], x2[5];
+    s2[0] = x2[0] = w2[0];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (u < nq) s2[u + 1] = spec(u, w2[u + 1], w2[0], ir2);
+    for (int u = 0; u < 4; ++u) {
+      if (u < nq) {
+        x2[u + 1] = numer(u, w2[u + 1], w2[0]);
+        s2[u + 1] = x2[u + 1] * ir2;
+      }
+    }
     const V da = va;
-    const V a = wind ? vb + da : da, nu = a * cour;
-    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
+    const V a = wind ? vb + da : da;
+    V hl, hh;
+    weights(a, hl, hh);
     V dM = V(0), M = V(0);
 #pragma unroll
     for (int u = 0; u < 5; ++u) {
       if (u > nq) break;
-      const V d1 = vleer(s2[u] - s1[u], s1[u] - s0[u]);
+      const V d1 = limited(x2[u], u ? ir2 : V(1), s1[u], s0[u]);
       const V fv = upwind(s0[u], d0[u], s1[u], d1, a, hl, hh);
       V F1;
       if (u == 0) {
-        dM = (rho0 * da + fv * a) * mfac;
+        dM = fmav<V>(fv, a, rho0 * da) * mfac;
         M = wind ? M0 + dM : dM;
         F1 = GRP ? dM : fix(c + 1, 0, dM);
       } else {
-        F1 = fix(c + 1, mq[u - 1], zq[u - 1] ? fv * M : sb[u - 1] * dM + fv * M);
+        F1 = fix(c + 1, mq[u - 1], zq[u - 1] ? fv * M : fmav<V>(V(sb[u - 1]), dM, fv * M));
       }
-      snk.put(u, ic, w0[u] - (F1 - F0[u]) * ivol);
+      snk.put(u, ic, fmav<V>(-(F1 - F0[u]), V(ivol), w0[u]));
       F0[u] = F1;
       d0[u] = d1;
       s0[u] = s1[u];
@@ -1686,6 +1726,10 @@ template <typename T, int W, int GRP, int NG, bool LEAD>
 __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, const PassArgs<T> &A,
                                                 const MarchArgs<T> &M, T dt, int t, int x0, bool live, bool put,
                                                 int c0, int c1, const XyShare<T, W> &S) {
+  // a segment's first face is formed here and, by the segment below, in its
+  // walk: as in march_column, no implicit contraction, the fused products
+  // written out, so that both give the same value
+#pragma clang fp contract(off)
   using V = typename lanes_of<T, W>::type;
   constexpr int nq = group_n(NG, GRP);
   constexpr int mq[4] = {group_q(NG, GRP, 0), group_q(NG, GRP, 1), group_q(NG, GRP, 2), group_q(NG, GRP, 3)};
@@ -1704,16 +1748,23 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
     qout[u] = M.qo[mq[u]];
   }
   // the face's weights hl = (1 - nu)/2, hh = (1 + nu)/2 are exact halvings
+  // of the rounded 1 -+ nu
   auto upwind = [&](V sl, V dl, V sr, V dr, V a) -> V {
     const V nu = a * cour;
-    const V hl = T(0.5) * (T(1) - nu), hh = T(0.5) * (T(1) + nu);
-    const V lo = sl + dl * hl, hi = sr - dr * hh;
+    const V hl = fmav<V>(V(-0.5), nu, V(0.5)), hh = fmav<V>(V(0.5), nu, V(0.5));
+    const V lo = fmav<V>(dl, hl, sl), hi = fmav<V>(-dr, hh, sr);
     return a > T(0) ? lo : hi;
   };
-  auto spec = [&](int u, V q, V r, V ir) -> V { return zq[u] ? rho0 * q * ir : (rho0 * q - q0[u] * r) * ir; };
+  // numerator of a specific value's departure (times 1/(rho0 rho) the value)
+  // and the limited difference at a cell from its right neighbour's numerator
+  // and reciprocal: the arithmetic of march_column
+  auto numer = [&](int u, V q, V r) -> V { return zq[u] ? rho0 * q : fmav<V>(V(rho0), q, -(q0[u] * r)); };
+  auto limited = [&](V xr, V ir, V s, V sl) -> V { return vleer(fmav<V>(xr, ir, -s), s - sl); };
   auto face = [&](int c) -> V { return live ? gldv<V>(M.v, base + c * st) : V(0); };
   // mass transfer through a y face from the density around it
-  auto mass_y = [&](V a, V sl, V dl, V sr, V dr) -> V { return (rho0 * a + upwind(sl, dl, sr, dr, a) * a) * mfac; };
+  auto mass_y = [&](V a, V sl, V dl, V sr, V dr) -> V {
+    return fmav<V>(upwind(sl, dl, sr, dr, a), a, rho0 * a) * mfac;
+  };
 
   // leader rings: x-updated density of rows c+1 .. c+3 (rr), its limited
   // difference at c+1 (rd), the mass transfers of faces c, c+1 (rm), the
@@ -1762,13 +1813,14 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
     const V dM = S.facev(c0);
 #pragma unroll
     for (int u = 0; u < nq; ++u) {
-      const V sm2 = spec(u, wm2[u], r_m2, i_m2), sm1 = spec(u, wm1[u], r_m1, i_m1);
-      ss[0][u] = spec(u, sw[0][u], r_0, i_0);
-      ss[1][u] = spec(u, sw[1][u], r_p1, i_p1);
-      const V dm1 = vleer(ss[0][u] - sm1, sm1 - sm2);
-      sd[0][u] = vleer(ss[1][u] - ss[0][u], ss[0][u] - sm1);
+      const V sm2 = numer(u, wm2[u], r_m2) * i_m2, sm1 = numer(u, wm1[u], r_m1) * i_m1;
+      const V x0 = numer(u, sw[0][u], r_0), x1 = numer(u, sw[1][u], r_p1);
+      ss[0][u] = x0 * i_0;
+      ss[1][u] = x1 * i_p1;
+      const V dm1 = limited(x0, i_0, sm1, sm2);
+      sd[0][u] = limited(x1, i_p1, ss[0][u], sm1);
       const V fv = upwind(sm1, dm1, ss[0][u], sd[0][u], a);
-      sF[0][u] = zq[u] ? fv * dM : sb[u] * dM + fv * dM;
+      sF[0][u] = zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM);
     }
     src.get(c0 + 2, S, sw[2]);
     sv[0] = face(c0 + 1);
@@ -1786,11 +1838,12 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
       const V dM = S.facev(c + 1);
 #pragma unroll
       for (int u = 0; u < nq; ++u) {
-        ss[K2][u] = spec(u, sw[K2][u], r2, ir2);
-        sd[K1][u] = vleer(ss[K2][u] - ss[K1][u], ss[K1][u] - ss[K0][u]);
+        const V x2 = numer(u, sw[K2][u], r2);
+        ss[K2][u] = x2 * ir2;
+        sd[K1][u] = limited(x2, ir2, ss[K1][u], ss[K0][u]);
         const V fv = upwind(ss[K0][u], sd[K0][u], ss[K1][u], sd[K1][u], a);
-        sF[K1][u] = zq[u] ? fv * dM : sb[u] * dM + fv * dM;
-        if (put) gstv<V>(qout[u], ic, sw[K0][u] - (sF[K1][u] - sF[K0][u]) * ivol);
+        sF[K1][u] = zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM);
+        if (put) gstv<V>(qout[u], ic, fmav<V>(-(sF[K1][u] - sF[K0][u]), V(ivol), sw[K0][u]));
       }
       src.get(c + 3, S, sw[K0]);
     }
@@ -1801,7 +1854,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
       for (int q = 0; q < W; ++q) S.row(c + 3, 2, q) = qdiv(T(1), rho0 * (rho0 + S.row(c + 3, 1, q)));
     }
     if constexpr (LEAD) {
-      if (put) gstv<V>(M.qo[0], ic, S.rowv(c, 1) - (rm[K1] - rm[K0]) * ivol);
+      if (put) gstv<V>(M.qo[0], ic, fmav<V>(-(rm[K1] - rm[K0]), V(ivol), S.rowv(c, 1)));
       rd[K1] = vleer(rr[K2] - rr[K1], rr[K1] - rr[K0]);
       rm[K2] = mass_y(rv[K0], rr[K0], rd[K0], rr[K1], rd[K1]);
       S.put_face(c + 2, rm[K2]);

@@ -5,7 +5,8 @@ FP32 departure storage (force within 1e-4, totals within 1e-6); four nested
 levels of 32^3 (the nested workload at reduced size) over 20 coarse steps in
 both precisions; two levels of 128^3 (the nested workload's level shape)
 over 2 coarse steps in both precisions; and runs at every column-segment length the autotuner can
-choose, against the default length and the oracle."""
+choose, bitwise equal to the default length in both precisions and within the
+FP64 bar of the oracle."""
 import sys
 
 import numpy as np
@@ -191,5 +192,8 @@ def test_segment_length_does_not_change_results(dfm, case):
             same = same and np.array_equal(fa, fb)
             assert np.max(np.abs(fa[:3] - fb[:3])) <= 1e2 * tol * np.linalg.norm(fb[:3]), (ch, fa, fb)
             _say(f"[segments] tile_chunk {ch}: {'bitwise equal' if same else 'equal to rounding'} to the default")
+            # a segment's first face is formed as the segment below forms it,
+            # with the same roundings: the segment length changes no bit
+            assert same, (prec, ch)
             if prec == dfm.DF_FP64:
                 _check_fp64(g, ref, nl, f"{nl} levels, tile_chunk {ch}")
