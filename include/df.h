@@ -198,9 +198,11 @@ int df_set_viscosity(df_run *run, double c2);
 /* Launch shape of the transport step (the x, y, z passes of T in eq. 15,
  * Sect. 3.2.3 and 3.3): on (1, default) the x and y passes of level 0 run
  * as one launch when level 0 has no finer level, uses the default boundaries
- * and has at most 128 cells along x (an even count above 64): each row's x
- * pass is taken in registers and fed to the y pass, so the x pass's results
- * never reach device memory.  off (0): every pass is a launch of its own.  The
+ * and has at most 128 cells along x (an even count above 64), and those of
+ * every finer level (in the quadrant, of a finer level with no finer one):
+ * each row's x pass is taken in registers and fed to the y pass, so the x
+ * pass's results never reach device memory.  off (0): every pass is a launch
+ * of its own.  The
  * results agree to rounding either way (the same operations in the same order;
  * the compiler may pair a product and a sum into one fused multiply-add
  * differently); DF_EINVAL for other values. */

@@ -299,7 +299,7 @@ class Run:
         _ck(_load().df_set_boundaries(self._h, int(mode)))
 
     def set_transport_fusion(self, on: bool) -> None:
-        """fuse level 0's x and y transport passes where they qualify (default on)"""
+        """fuse the x and y transport passes of level 0 and of the finer levels where they qualify (default on)"""
         _ck(_load().df_set_transport_fusion(self._h, int(bool(on))))
 
     def set_kick_fusion(self, on: bool) -> None:

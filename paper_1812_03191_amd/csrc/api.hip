@@ -262,9 +262,15 @@ void level_step(df_run *R, int l, const double *dtp, double scale, int rem) {
   if (!kc) Bx.q[c][1] = B.etmp;
   // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
   const bool fused = R->fuse_xy && dfk::transport_xy_fits(G);
+  // a finer level: its x and y passes in one launch too, unless the
+  // quadrant's images must be set between them (a middle level)
+  const bool fused_fine = R->fuse_xy && !G.bc && !(R->quad && Gf);
   if (fused) {
     TScope t(R, K_PASSXY);
     dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
+  } else if (fused_fine) {
+    TScope t(R, K_PASSXY);
+    dfk::transport_xy_fine(st, Gy, P, Bx, c, dtp, scale, Gf, facc, R->chunk);
   } else {
     // quadrant: a middle level takes the finer level's frontier transfers,
     // whose images lie beyond the planes: the transported set's images are
@@ -277,7 +283,7 @@ void level_step(df_run *R, int l, const double *dtp, double scale, int rem) {
   }
   // the z pass and the rebuild take the set the y pass wrote (q[c] after
   // separate passes, q[1-c] after the fused ones)
-  const int cy = fused ? 1 - c : c;
+  const int cy = (fused || fused_fine) ? 1 - c : c;
   // a single-level step ends here: the same launch forms the force and the
   // next step's signal-speed partials; on level 0 without a finer level the z
   // pass joins them (only the new density, energy and face velocities are

@@ -137,6 +137,12 @@ void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBuf
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
                   double fac, int chunk);
 bool transport_xy_fits(const Geo &G);
+// fused x and y passes q[src] -> q[1-src] of a finer level (no boundary
+// conditions): G carries the y pass's margins; the entries written and the
+// frontier transfers taken and accumulated are those of the separate x and y
+// passes (x with G's x margin and y, z margins two cells wider)
+void transport_xy_fine(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
+                       double fac, const Geo *Gf, const void *fine_acc, int chunk);
 // the z pass q[src] -> q[1-src] (face velocities vin[2]) fused with the
 // velocity rebuild, the kick (fac kfac) into B.v and the end-of-step partials
 // of post_partials (as rebuild_kick with post S) on level 0 without a finer

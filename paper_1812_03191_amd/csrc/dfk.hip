@@ -19,7 +19,9 @@
 // levels advance their whole ghost shell, filled once per parent step.
 #include "dfk.h"
 
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 namespace dfk {
 
@@ -1359,7 +1361,7 @@ __device__ __forceinline__ void march_column(const Geo &G, const Phys &P, const 
       fhi = G.co[DIR] + G.cn[DIR];
     }
   }
-  const bool acc_col = FRONT && A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
+  const bool acc_col = FRONT && live && A.acc && tv1 >= 0 && tv2 >= 0 && tv1 < G.n[T1] && tv2 < G.n[T2];
   const long acc_nt = (long)G.n[T1] * G.n[T2];
   const long acc_i = (long)tv2 * G.n[T1] + tv1;
   // final transfer of quantity m through face f, given the solver's value
@@ -1516,6 +1518,146 @@ struct OutSink {
   }
   __device__ __forceinline__ void done(int) {}
 };
+
+// Rows of a finer level's column for the y pass, x-updated on the fly: row r
+// of plane t comes from the x pass (XRow's arithmetic, that of k_xrow_fine)
+// of the density and the group's quantities on a tile of 64 consecutive x
+// cells, lane l the cell x0 = xa - 2 + l.  The tile's x pass is exact on the
+// lanes 2 .. 60, the ones the walk stores: their stencils lie in the tile
+// (P+x is read from the next lane's left face, which lane 63 has not).
+// The x faces take the finer level's sums on the frontier and add this
+// level's own transfers at faces 0 and n to the accumulators, as the separate
+// x pass does, once: on owned rows (those of the walk's segment) and interior
+// lanes, the density by the first group only.
+template <typename T, int GRP, int NG>
+struct XFineSrc {
+  const Geo *G;
+  const Phys *P;
+  const PassArgs<T> *A;
+  T dt;
+  int t, x0, c0, c1, rmax;
+  bool in_row, own;  // the lane's cell lies in the stored row; it is an interior lane
+  // inputs of the next row (loaded while the walk uses this one): density,
+  // left x-face velocity, the group's own inputs
+  T ndr, nda, nin[4];
+  int nrow;
+  // the row fetched past the last one needed is not used: kept in storage
+  __device__ __forceinline__ idx_t at(int r) const { return lin(*G, x0, min(r, rmax), t); }
+  __device__ __forceinline__ void load(int r) {
+    const PassArgs<T> &a = *A;
+    const idx_t c = at(r);
+    nrow = r;
+    ndr = in_row ? a.qi[0][c] : T(0);
+    nda = in_row ? a.v[0][c] : T(0);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      nin[u] = T(0);
+      if (u < group_n(NG, GRP)) {
+        const int m = group_q(NG, GRP, u);
+        if (m == 1) {
+          nin[u] = in_row ? a.qi[1][c] : T(0);
+        } else if (m >= 4) {
+          const int d = (m - 2) >> 1;
+          nin[u] = in_row ? a.v[d][c + ((m & 1) ? dstride(*G, d) : 0)] : T(0);
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void get(int r, T (&w)[5]) {
+    const Geo &g = *G;
+    const PassArgs<T> &a = *A;
+    const int rr = min(r, rmax);
+    XRow<T, 1> X;
+    X.dr[0] = ndr;
+    X.da[0] = nda;
+    T in0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) in0[u] = nin[u];
+    load(r + 1);
+    X.begin(g, *P, dt);
+    const int n = g.n[0];
+    const bool ov = a.facc && rr - g.co[1] >= 0 && t - g.co[2] >= 0 && rr - g.co[1] < g.cn[1] &&
+                    t - g.co[2] < g.cn[2] && (x0 == g.co[0] || x0 == g.co[0] + g.cn[0]);
+    const bool acc = a.acc && own && rr >= c0 && rr < c1 && rr >= 0 && t >= 0 && rr < g.n[1] && t < g.n[2] &&
+                     (x0 == 0 || x0 == n);
+    auto finish = [&](int m, const T (&own_)[1], T (&FL)[1]) -> T {
+      if (ov) {
+        const long fnt = (long)a.fn[1] * a.fn[2];
+        const long fbase = (long)(2 * (t - g.co[2])) * a.fn[1] + 2 * (rr - g.co[1]);
+        const T *f = a.facc + ((long)(x0 != g.co[0]) * NQ + m) * fnt + fbase;
+        FL[0] = (f[0] + f[1]) + (f[a.fn[1]] + f[a.fn[1] + 1]);
+      }
+      if (acc && (m > 0 || GRP == 0))
+        a.acc[((long)(x0 == n) * NQ + m) * ((long)g.n[1] * g.n[2]) + (long)t * g.n[1] + rr] += FL[0];
+      T out[1];
+      X.update(own_, FL, out);
+      return out[0];
+    };
+    {
+      T F[1] = {X.dM[0]};
+      w[0] = finish(0, X.dr, F);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < group_n(NG, GRP)) {
+        const int m = group_q(NG, GRP, u);
+        T in[1], sv[1], own_[1], F[1];
+        if (m == 3) row_right<T, 1>(X.da, in, T(0));
+        else if (m == 2) in[0] = X.da[0];
+        else in[0] = in0[u];
+        X.quantity(*P, m, in, sv, own_);
+        X.transfers(*P, m, sv, F);
+        w[u + 1] = finish(m, own_, F);
+      }
+    }
+  }
+};
+
+// Fused x and y passes of a finer level: one block per (x tile, y segment,
+// plane), one wave per quantity group, each walking the y pass of its tile's
+// 64 columns over rows that its own source x-updates on the fly (the density
+// is x-passed and walked by every group; a row's inputs are loaded one row
+// ahead).  Only the y pass's results reach HBM, on interior lanes within the
+// updated box; the frontier transfers of both passes are taken and
+// accumulated as by the separate passes.
+constexpr int XF_TILE = BX - 5;  // x cells a tile stores
+template <typename T, int NG>
+__global__ void __launch_bounds__(64 * NG) k_xyfine(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M, int ntiles,
+                                                   int nseg) {
+  const int lane = threadIdx.x;
+  const int grp = __builtin_amdgcn_readfirstlane(threadIdx.y);
+  const unsigned h = blockIdx.x;
+  const int xt = (int)(h % (unsigned)ntiles);
+  const unsigned r1 = h / (unsigned)ntiles;
+  const int seg = (int)(r1 % (unsigned)nseg);
+  const int t = M.lo[2] + (int)(r1 / (unsigned)nseg);
+  const int c0 = M.lo[1] + seg * M.chunk;
+  const int c1 = min(c0 + M.chunk, M.hi[1]);
+  const int xa = M.lo[0] + XF_TILE * xt;
+  const int x0 = xa - 2 + lane;
+  const int px = (int)(G.off - (long)G.g * (G.sy + G.sz));
+  const bool in_row = x0 >= -px && x0 < (int)G.sy - px;
+  const bool own = lane >= 2 && lane < 2 + XF_TILE && x0 < M.hi[0];
+  const T dt = (T)(A.fac * A.dtp[0]);
+  // rows past the last one the walk reads stay in the stored box
+  const int rmax = G.n[1] + G.g - 2;
+  auto walk = [&](auto gc) {
+    constexpr int g = decltype(gc)::value;
+    XFineSrc<T, g, NG> src{&G, &P, &A, dt, t, x0, c0, c1, rmax, in_row, own};
+    src.load(c0 - 2);
+    OutSink<T, T, g, NG> snk(M, own);
+    march_column<T, 1, 0, g, true, 1, NG>(G, P, M, x0, t, c0, c1, src, snk, own);
+  };
+  if constexpr (NG == 2) {
+    if (grp == 0) walk(std::integral_constant<int, 0>{});
+    else walk(std::integral_constant<int, 1>{});
+  } else {
+    if (grp == 0) walk(std::integral_constant<int, 0>{});
+    else if (grp == 1) walk(std::integral_constant<int, 1>{});
+    else if (grp == 2) walk(std::integral_constant<int, 2>{});
+    else walk(std::integral_constant<int, 3>{});
+  }
+}
 
 template <typename T, int DIR, int BC, bool FRONT, int W>
 __global__ void __launch_bounds__(256) k_march(Geo G, Phys P, MarchArgs<T> A) {
@@ -3844,6 +3986,60 @@ bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int s
                   int chunk) {
   if (P.fp32) return transport_xy_t<float>(st, G, P, B, src, dtp, fac, chunk);
   return transport_xy_t<double>(st, G, P, B, src, dtp, fac, chunk);
+}
+
+template <typename T>
+static void transport_xy_fine_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src,
+                                const double *dtp, double fac, const Geo *Gf, const void *fine_acc, int chunk) {
+  PassArgs<T> A;
+  // the y pass's box (x, y two cells inside the stored box, z all of it),
+  // within G's margins
+  for (int d = 0; d < 3; ++d) {
+    A.b.lo[d] = d < 2 ? -G.g + 2 : -G.g;
+    A.b.hi[d] = d < 2 ? G.n[d] + G.g - 3 : G.n[d] + G.g - 1;
+  }
+  A.b = clip_cells(G, A.b);
+  for (int m = 0; m < NQ; ++m) {
+    A.qi[m] = tp<T>(B.q[src][m]);
+    A.qo[m] = tp<T>(B.q[1 - src][m]);
+  }
+  for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
+  A.dtp = dtp;
+  A.fac = fac;
+  A.acc = tp<T>(B.acc);
+  A.facc = (G.has_fine && fine_acc) ? reinterpret_cast<const T *>(fine_acc) : nullptr;
+  for (int d = 0; d < 3; ++d) A.fn[d] = Gf ? Gf->n[d] : 0;
+  MarchArgs<T> M;
+  for (int d = 0; d < 3; ++d) {
+    M.lo[d] = A.b.lo[d];
+    M.hi[d] = A.b.hi[d];
+    M.fn[d] = A.fn[d];
+  }
+  const int ext = M.hi[1] - M.lo[1];
+  if (ext <= 0 || M.hi[0] <= M.lo[0] || M.hi[2] <= M.lo[2]) return;
+  // each segment x-updates two rows past either end of its own: at least 16
+  // rows per segment (on 4 levels of 128^3, 16 ran 2 % faster than 32 and 8
+  // suits the other walks)
+  chunk = chunk < 16 ? 16 : chunk;
+  M.chunk = ext <= chunk ? ext : chunk;
+  for (int m = 0; m < NQ; ++m) {
+    M.qi[m] = A.qi[m];
+    M.qo[m] = A.qo[m];
+  }
+  M.v = A.v[1];
+  M.dtp = dtp;
+  M.fac = fac;
+  M.acc = A.acc;
+  M.facc = A.facc;
+  const int ntiles = (M.hi[0] - M.lo[0] + XF_TILE - 1) / XF_TILE;
+  const int nseg = (ext + M.chunk - 1) / M.chunk;
+  const dim3 gr((unsigned)((long)ntiles * nseg * (M.hi[2] - M.lo[2]))), bl(64, 2);
+  DFK_LAUNCH((k_xyfine<T, 2>), gr, bl, st, G, P, A, M, ntiles, nseg);
+}
+void transport_xy_fine(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
+                       double fac, const Geo *Gf, const void *fine_acc, int chunk) {
+  if (P.fp32) transport_xy_fine_t<float>(st, G, P, B, src, dtp, fac, Gf, fine_acc, chunk);
+  else transport_xy_fine_t<double>(st, G, P, B, src, dtp, fac, Gf, fine_acc, chunk);
 }
 
 bool transport_z_finish_fits(const Geo &G) {

@@ -155,6 +155,40 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
     assert fa[3] == fb[3]
 
 
+# Fused x and y passes of the finer levels against separate ones: finer rows
+# (with their margins) in one 64-lane tile (16^3 levels), two (64^3) and three
+# (128^3 with one finer level, both sub-steps' margins), y extents of one
+# 32-row segment and of several, a middle level taking a finer level's
+# frontier transfers, and the quadrant's finest level.
+FINE_XY_CASES = [((16, 16, 16), 3, False, 4), ((64, 64, 64), 2, False, 3), ((32, 32, 32), 3, False, 2),
+                 ((128, 128, 128), 2, False, 1), ((32, 16, 16), 2, True, 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", range(len(FINE_XY_CASES)))
+def test_fused_xy_fine_levels_equal_separate_passes(dfm, case, prec):
+    (nx, ny, nz), nl, quad, steps = FINE_XY_CASES[case]
+    _say(f"[fused xy fine] {nx}x{ny}x{nz}, {nl} levels, quadrant {quad}, {prec}")
+    p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
+    runs = []
+    for fuse in (False, True):
+        g = dfm.Run(nx, ny, nz, nlevels=nl, dx0=0.16, seed=33, noise_amp=1e-3, precision=p, quadrant=quad)
+        if quad:
+            g.set_boundaries(1)
+        g.set_perturber(0.01, 0.05, 2e-3, 0.9, 0.1)
+        g.set_transport_fusion(fuse)
+        g.step(steps)
+        runs.append(g)
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    for lev in range(nl):
+        for name in FIELD_NAMES:
+            a, b = runs[0].field(lev, name), runs[1].field(lev, name)
+            assert np.max(np.abs(a - b)) <= tol * SCALE[name], (lev, name, float(np.max(np.abs(a - b))))
+    fa, fb = runs[0].force(), runs[1].force()
+    assert np.max(np.abs(fa[:3] - fb[:3])) <= 1e2 * tol * np.linalg.norm(fa[:3]), (fa, fb)
+    assert fa[3] == fb[3]
+
+
 KC_CASES = [((32, 16, 8), 1, 0), ((64, 12, 6), 1, 1), ((128, 20, 6), 1, 0), ((16, 16, 16), 2, 0),
             ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((16, 2, 4), 1, 1), ((8, 4, 2), 1, 1)]
 
