@@ -1619,10 +1619,11 @@ struct XFineSrc {
 // is x-passed and walked by every group; a row's inputs are loaded one row
 // ahead).  Only the y pass's results reach HBM, on interior lanes within the
 // updated box; the frontier transfers of both passes are taken and
-// accumulated as by the separate passes.
+// accumulated as by the separate passes.  Held to three waves per SIMD (in
+// FP64 a few registers spill; two waves ran the pass 2 % slower).
 constexpr int XF_TILE = BX - 5;  // x cells a tile stores
 template <typename T, int NG>
-__global__ void __launch_bounds__(64 * NG) k_xyfine(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M, int ntiles,
+__global__ void __launch_bounds__(64 * NG) __attribute__((amdgpu_waves_per_eu(3))) k_xyfine(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M, int ntiles,
                                                    int nseg) {
   const int lane = threadIdx.x;
   const int grp = __builtin_amdgcn_readfirstlane(threadIdx.y);
