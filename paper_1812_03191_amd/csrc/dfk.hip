@@ -434,7 +434,7 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
       const T *pm = A.q[2 + 2 * d], *pp = A.q[3 + 2 * d];
       const T ppm = pp[m], pmc = pm[c];
       const T vb = (T)vback(P, d);
-      vf = (ppm + pmc - vb * (drm + drc)) / (T(2) * rho0 + drm + drc);
+      vf = qdiv(ppm + pmc - vb * (drm + drc), T(2) * rho0 + drm + drc);
     } else {
       vf = A.v[d][c];
     }
