@@ -249,12 +249,27 @@ __device__ __forceinline__ V qsqrtv(V x) {
   return r;
 }
 
+// The limiter's quotient: in FP64 the hardware reciprocal (relative error
+// up to 4.6e-8 measured on gfx950) with one Newton step, within 2.2e-15 of the
+// quotient (measured; two steps reach about an ulp), enough for a limited
+// slope; in FP32 the quotient above.
+__device__ __forceinline__ double qdiv_lim(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return a * r;
+}
+__device__ __forceinline__ float qdiv_lim(float a, float b) { return qdiv(a, b); }
+template <typename V>
+__device__ __forceinline__ V qdiv_lim(V a, V b) {
+  return V{qdiv_lim(a.x, b.x), qdiv_lim(a.y, b.y)};  // two-element vectors, per element
+}
+
 // van Leer's harmonic limited difference; evaluated without a branch (the
 // quotient of the discarded side is selected away)
 template <typename T>
 __device__ __forceinline__ T vleer(T a, T b) {
   const T p = a * b;
-  const T r = qdiv(T(2) * p, a + b);
+  const T r = qdiv_lim(T(2) * p, a + b);
   return p > T(0) ? r : T(0);
 }
 
