@@ -4,7 +4,8 @@ FP64 (every field within 1e-11 of its scale, the force within 1e-9) and with
 FP32 departure storage (force within 1e-4, totals within 1e-6); four nested
 levels of 32^3 (the nested workload at reduced size) over 20 coarse steps in
 both precisions; two levels of 128^3 (the nested workload's level shape)
-over 2 coarse steps in both precisions; and runs at every column-segment length the autotuner can
+and the nested workload itself (four levels of 128^3) over 2 coarse steps
+in both precisions; and runs at every column-segment length the autotuner can
 choose, bitwise equal to the default length in both precisions and within the
 FP64 bar of the oracle."""
 import sys
@@ -160,6 +161,38 @@ def test_nested_128_levels_fp32_against_oracle(dfm, nested128_ref):
                 for lev in range(2) for name in FIELD_NAMES)
     _say(f"[2 x 128^3] FP32 worst field error {worst:.2e}")
     assert worst < 64 * 2.0 ** -24 * 6e-4
+
+
+@pytest.fixture(scope="module")
+def nested4x128_ref():
+    cfg, _ = inputs.config3()
+    _say("[full parity] oracle: 4 levels of 128^3 x 2 coarse steps")
+    return cfg, _oracle(cfg, 2)
+
+
+def test_nested_workload_parity_fp64(dfm, nested4x128_ref):
+    # the nested workload itself (4 levels of 128^3) over two coarse steps
+    cfg, ref = nested4x128_ref
+    _say("[full parity] 4 x 128^3 FP64 x 2")
+    g = _gpu(dfm, cfg, 2, dfm.DF_FP64)
+    _check_fp64(g, ref, 4, "4 x 128^3 FP64")
+
+
+def test_nested_workload_fp32_against_oracle(dfm, nested4x128_ref):
+    cfg, ref = nested4x128_ref
+    _say("[full parity] 4 x 128^3 FP32 x 2")
+    g = _gpu(dfm, cfg, 2, dfm.DF_FP32)
+    _check_fp32(g, ref, "4 x 128^3")
+    # FP32 holds departures from the background: each store rounds by at most
+    # 2^-24 of the largest departure; a few tens of roundings bound the error
+    gamma = cfg["gamma"]
+    back = {"rho": 1.0, "e": 1.0 / (gamma * (gamma - 1.0)), "vx": -cfg["mach"], "vy": 0.0, "vz": 0.0}
+    dep = max(float(np.max(np.abs(ref["fields"][(lev, name)] - back[name]))) / SCALE[name]
+              for lev in range(4) for name in FIELD_NAMES)
+    worst = max(float(np.max(np.abs(g.field(lev, name) - ref["fields"][(lev, name)]))) / SCALE[name]
+                for lev in range(4) for name in FIELD_NAMES)
+    _say(f"[4 x 128^3] FP32 worst field error {worst:.2e} (largest departure {dep:.2e})")
+    assert worst < 64 * 2.0 ** -24 * dep
 
 
 # column-segment lengths (tile_chunk) of the streaming y and z passes and of
