@@ -1555,13 +1555,11 @@ struct XFineSrc {
   // inputs of the next row (loaded while the walk uses this one): density,
   // left x-face velocity, the group's own inputs
   T ndr, nda, nin[4];
-  int nrow;
   // the row fetched past the last one needed is not used: kept in storage
   __device__ __forceinline__ idx_t at(int r) const { return lin(*G, x0, min(r, rmax), t); }
   __device__ __forceinline__ void load(int r) {
     const PassArgs<T> &a = *A;
     const idx_t c = at(r);
-    nrow = r;
     ndr = in_row ? a.qi[0][c] : T(0);
     nda = in_row ? a.v[0][c] : T(0);
 #pragma unroll
