@@ -2,8 +2,8 @@
 lengths the workloads use: the 128^3 single-level workload over 100 steps in
 FP64 (every field within 1e-11 of its scale, the force within 1e-9) and with
 FP32 departure storage (force within 1e-4, totals within 1e-6); four nested
-levels of 32^3 (the nested workload at reduced size) over 20 coarse steps in
-both precisions; two levels of 128^3 (the nested workload's level shape)
+levels of 32^3 (the nested workload at reduced size) over 20 coarse steps and
+of 64^3 over 10 in both precisions; two levels of 128^3 (the nested workload's level shape)
 and the nested workload itself (four levels of 128^3) over 2 coarse steps
 in both precisions; and runs at every column-segment length the autotuner can
 choose, bitwise equal to the default length in both precisions and within the
@@ -161,6 +161,29 @@ def test_nested_128_levels_fp32_against_oracle(dfm, nested128_ref):
                 for lev in range(2) for name in FIELD_NAMES)
     _say(f"[2 x 128^3] FP32 worst field error {worst:.2e}")
     assert worst < 64 * 2.0 ** -24 * 6e-4
+
+
+@pytest.fixture(scope="module")
+def nested64_ref():
+    cfg, _ = inputs.config3(n=64)
+    _say("[full parity] oracle: 4 levels of 64^3 x 10 coarse steps")
+    return cfg, _oracle(cfg, 10)
+
+
+def test_nested_64_levels_parity_fp64(dfm, nested64_ref):
+    # finer rows of 66-84 cells with their margins: two x tiles in the fused
+    # x + y pass, over ten coarse steps
+    cfg, ref = nested64_ref
+    _say("[full parity] 4 x 64^3 FP64 x 10")
+    g = _gpu(dfm, cfg, 10, dfm.DF_FP64)
+    _check_fp64(g, ref, 4, "4 x 64^3 FP64")
+
+
+def test_nested_64_levels_fp32_against_oracle(dfm, nested64_ref):
+    cfg, ref = nested64_ref
+    _say("[full parity] 4 x 64^3 FP32 x 10")
+    g = _gpu(dfm, cfg, 10, dfm.DF_FP32)
+    _check_fp32(g, ref, "4 x 64^3")
 
 
 @pytest.fixture(scope="module")
