@@ -209,16 +209,17 @@ __device__ __forceinline__ T xcen(const Geo &G, int d, int i) {
 
 // Quotient and square root in the storage type, from the hardware reciprocal
 // and reciprocal square root instead of the correctly rounded expansions: in
-// FP64 the reciprocal takes two Newton steps and the quotient is the dividend
-// times it (within about an ulp of the rounded quotient), the square root two
-// Goldschmidt steps and one residual correction (within an ulp); in FP32 both
-// are the single hardware instructions (about 1 ulp each).  Every use has a normal
+// FP64 the hardware reciprocal (relative error up to 4.6e-8, measured on
+// gfx950) takes one Newton step and the quotient is the dividend times it
+// (within 2.2e-15 of the quotient, measured over 4 M divisors; a second step
+// would reach about an ulp), the square root two Goldschmidt steps and one
+// residual correction (within an ulp); in FP32 both are the single hardware
+// instructions (about 1 ulp each).  Every use has a normal
 // positive operand or divisor (densities and energies near their background,
 // squared distances of at least a quarter cell, sums of two slopes of one
 // sign; a van Leer quotient of slopes of opposite signs is selected away).
 __device__ __forceinline__ double qdiv(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
   r = fma(r, fma(-b, r, 1.0), r);
   return a * r;
 }
@@ -249,27 +250,12 @@ __device__ __forceinline__ V qsqrtv(V x) {
   return r;
 }
 
-// The limiter's quotient: in FP64 the hardware reciprocal (relative error
-// up to 4.6e-8 measured on gfx950) with one Newton step, within 2.2e-15 of the
-// quotient (measured; two steps reach about an ulp), enough for a limited
-// slope; in FP32 the quotient above.
-__device__ __forceinline__ double qdiv_lim(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  return a * r;
-}
-__device__ __forceinline__ float qdiv_lim(float a, float b) { return qdiv(a, b); }
-template <typename V>
-__device__ __forceinline__ V qdiv_lim(V a, V b) {
-  return V{qdiv_lim(a.x, b.x), qdiv_lim(a.y, b.y)};  // two-element vectors, per element
-}
-
 // van Leer's harmonic limited difference; evaluated without a branch (the
 // quotient of the discarded side is selected away)
 template <typename T>
 __device__ __forceinline__ T vleer(T a, T b) {
   const T p = a * b;
-  const T r = qdiv_lim(T(2) * p, a + b);
+  const T r = qdiv(T(2) * p, a + b);
   return p > T(0) ? r : T(0);
 }
 
