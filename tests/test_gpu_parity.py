@@ -159,23 +159,28 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
 # (with their margins) in one 64-lane tile (16^3 levels), two (64^3) and three
 # (128^3 with one finer level, both sub-steps' margins), y extents of one
 # 32-row segment and of several, a middle level taking a finer level's
-# frontier transfers, and the quadrant's finest level.
-FINE_XY_CASES = [((16, 16, 16), 3, False, 4), ((64, 64, 64), 2, False, 3), ((32, 32, 32), 3, False, 2),
-                 ((128, 128, 128), 2, False, 1), ((32, 16, 16), 2, True, 3)]
+# frontier transfers, the quadrant's finest level, and a supersonic run with
+# the artificial viscosity.
+FINE_XY_CASES = [((16, 16, 16), 3, False, 4, 0.0), ((64, 64, 64), 2, False, 3, 0.0),
+                 ((32, 32, 32), 3, False, 2, 0.0), ((128, 128, 128), 2, False, 1, 0.0),
+                 ((32, 16, 16), 2, True, 3, 0.0), ((48, 48, 48), 2, False, 3, 2.0)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("case", range(len(FINE_XY_CASES)))
 def test_fused_xy_fine_levels_equal_separate_passes(dfm, case, prec):
-    (nx, ny, nz), nl, quad, steps = FINE_XY_CASES[case]
-    _say(f"[fused xy fine] {nx}x{ny}x{nz}, {nl} levels, quadrant {quad}, {prec}")
+    # (the last case: Mach 2 with the artificial viscosity, one more cell of margin)
+    (nx, ny, nz), nl, quad, steps, visc = FINE_XY_CASES[case]
+    _say(f"[fused xy fine] {nx}x{ny}x{nz}, {nl} levels, quadrant {quad}, viscosity {visc}, {prec}")
     p = dfm.DF_FP32 if prec == "fp32" else dfm.DF_FP64
     runs = []
     for fuse in (False, True):
         g = dfm.Run(nx, ny, nz, nlevels=nl, dx0=0.16, seed=33, noise_amp=1e-3, precision=p, quadrant=quad)
         if quad:
             g.set_boundaries(1)
-        g.set_perturber(0.01, 0.05, 2e-3, 0.9, 0.1)
+        if visc:
+            g.set_viscosity(visc)
+        g.set_perturber(0.01, 0.05, 2e-3, 2.0 if visc else 0.9, 0.1)
         g.set_transport_fusion(fuse)
         g.step(steps)
         runs.append(g)
