@@ -128,7 +128,10 @@ void carve(df_run *R, char *base) {
     for (int s = 0; s < 2; ++s)
       for (int m = 0; m < NQ; ++m) B.q[s][m] = c.take<char>(v);
     for (int d = 0; d < 3; ++d) B.v[d] = c.take<char>(v);
-    for (int d = 0; d < 3; ++d) B.vk[d] = l == 0 ? (void *)c.take<char>(v) : nullptr;
+    // the kicked faces of a fused kick and compression (level 0; the finer
+    // levels in FP32, where the fused launch is the faster)
+    const bool kcl = l == 0 || R->esz == 4;
+    for (int d = 0; d < 3; ++d) B.vk[d] = kcl ? (void *)c.take<char>(v) : nullptr;
     B.etmp = c.take<char>(v);
     B.acc = R->acc_n[l] ? (void *)c.take<char>(R->acc_n[l] * e) : nullptr;
     const Geo &G = R->geo[l];
@@ -238,17 +241,24 @@ void level_step(df_run *R, int l, const double *dtp, double scale, int rem) {
   // single level: the kick sets this step's length from the last end-of-step
   // pass's signal speeds, and the compression logs that pass's force
   Scal *slots = R->slot_mode ? R->scal : nullptr;
-  // level 0 may kick and compress in one launch; the transport passes then
-  // read the kicked velocities from vk, and the energy goes q[c][1] -> etmp
+  // the first kick and the compression may run as one launch (level 0, and
+  // the finer levels in FP32: in FP64 their fused launch, which kicks the
+  // high y and z faces of each cell again, made a run of 4 levels of 128^3
+  // 0.5-2 % slower than the two launches); the transport passes then read
+  // the kicked velocities from vk, and the energy goes q[c][1] -> etmp
   // (compression) -> q[c][1] (diffusion)
-  const bool kc = R->fuse_kc && G.level == 0 && B.vk[0] && !(P.visc > 0.0);
+  const bool kc = R->fuse_kc && B.vk[0] && !(P.visc > 0.0);
   LevBufs Bt = B;  // buffers the transport passes read
   if (kc) {
-    { TScope t(R, K_KICKCOMP); dfk::kick_compress(st, G, P, B, c, dtp, 0.5 * scale, scale, slots, R->flog); }
+    {
+      TScope t(R, K_KICKCOMP);
+      if (G.bc) dfk::kick_compress(st, G, P, B, c, dtp, 0.5 * scale, scale, slots, R->flog);
+      else dfk::kick_compress_fine(st, Gk, Gc, P, B, c, dtp, 0.5 * scale, scale);
+    }
     LevBufs Bd = B;
     Bd.q[c][1] = B.etmp;
     Bd.etmp = B.q[c][1];
-    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G, P, Bd, c, dtp, scale, true, true, slots); }
+    { TScope t(R, K_DIFFUSE); dfk::diffuse_heat(st, G.bc ? G : Gd, P, Bd, c, dtp, scale, true, true, slots); }
     for (int d = 0; d < 3; ++d) Bt.v[d] = B.vk[d];
   } else {
     { TScope t(R, K_KICK); dfk::kick(st, Gk, P, B, c, dtp, 0.5 * scale, slots); }

@@ -125,6 +125,11 @@ void diffuse_heat(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int c
 // compress with log do; the slots are left for diffuse_heat to clear.
 void kick_compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp,
                    double kfac, double cfac, Scal *slots, double *flog);
+// the same on a finer level: the kick (fac kfac, face ranges within Gk's
+// margins) reads B.v and writes B.vk, the compression (fac cfac, cells within
+// Gc's margins) writes B.etmp
+void kick_compress_fine(hipStream_t st, const Geo &Gk, const Geo &Gc, const Phys &P, LevBufs &B, int cur,
+                        const double *dtp, double kfac, double cfac);
 // one transport pass q[src] -> q[1-src]; dir 0 builds the momenta from the
 // face velocities; a fine level adds its frontier transfers into B.acc; a
 // level with a finer one (Gf, fine_acc) takes that level's sums on the frontier

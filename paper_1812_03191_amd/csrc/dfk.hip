@@ -88,16 +88,19 @@ __device__ __forceinline__ bool thread_cell(const Box &b, int &i, int &j, int &k
 // thread_cell); blocks of four waves go to the XCDs in bands through all
 // planes as there.  A lane's previous lane then holds the previous entry of
 // its row unless the lane is the first of its wave or its entry the first of
-// its row.
+// its row.  With WS = BX - 1 entries per wave, the waves overlap by one entry:
+// the last lane holds the entry after the wave's own (the next wave's first).
+template <int WS = BX>
 inline dim3 grid_of_flat(const Box &b) {
   const long ex = b.hi[0] - b.lo[0], ey = b.hi[1] - b.lo[1], ez = b.hi[2] - b.lo[2];
   if (ex <= 0 || ey <= 0 || ez <= 0) return dim3(0, 1, 1);
-  return dim3((unsigned)((ex * ey + BX * BY - 1) / (BX * BY) * ez), 1, 1);
+  return dim3((unsigned)((ex * ey + WS * BY - 1) / (WS * BY) * ez), 1, 1);
 }
 
+template <int WS = BX>
 __device__ __forceinline__ bool thread_cell_flat(const Box &b, int &i, int &j, int &k, Blk bk = grid_blk()) {
   const unsigned ex = (unsigned)(b.hi[0] - b.lo[0]), ey = (unsigned)(b.hi[1] - b.lo[1]);
-  const unsigned nby = (ex * ey + BX * BY - 1) / (BX * BY);  // blocks per plane
+  const unsigned nby = (ex * ey + WS * BY - 1) / (WS * BY);  // blocks per plane
   const unsigned N = bk.n, h = bk.id;
   const unsigned nbz = N / nby;
   const unsigned q = N / 8, r = N % 8, x = h % 8, s = h / 8;
@@ -112,7 +115,7 @@ __device__ __forceinline__ bool thread_cell_flat(const Box &b, int &i, int &j, i
     y0 += hb;
   }
   const unsigned by = y0 + L % hb, bz = L / hb;
-  const unsigned f = by * (BX * BY) + threadIdx.y * BX + threadIdx.x;
+  const unsigned f = by * (WS * BY) + threadIdx.y * WS + threadIdx.x;
   i = b.lo[0] + (int)(f % ex);
   j = b.lo[1] + (int)(f / ex);
   k = b.lo[2] + (int)bz;
@@ -330,6 +333,34 @@ __device__ __forceinline__ double sback(const Phys &P, int m) {
   return m == 1 ? P.e0 / P.rho0 : ((m == 2 || m == 3) ? -P.V : 0.0);
 }
 
+// Neighbour exchange inside a wave through the data-parallel-primitive lane
+// shifts: from_left gives every lane the value of the lane below it, from_right
+// that of the lane above it (the end lanes receive 0).
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
+
+template <typename T>
+__device__ __forceinline__ T from_left(T v) { return dpp_t<DPP_WAVE_SHR1>(v); }
+
+template <typename T>
+__device__ __forceinline__ T from_right(T v) { return dpp_t<DPP_WAVE_SHL1>(v); }
+
 // ------------------------------------------------------------------ init
 
 // SplitMix64 finaliser (Steele, Lea & Flood 2014); output n of the stream
@@ -446,6 +477,86 @@ __global__ void __launch_bounds__(BX * BY) k_kick(Geo G, Phys P, KickArgs<T> A) 
       vf = vf - h * (gradp + gradphi);
     }
     A.v[d][c] = vf;
+  }
+}
+
+// The first kick and the compression of a finer level in one launch (as
+// kick_compress on level 0): a cell of the kick's union box kicks its low
+// faces that lie in their ranges into A.v, reading the faces from A.vin; a
+// cell of the compression box cb also compresses its energy into A.eo, from
+// the six kicked faces around it.  The waves take 63 cells of the box's flat
+// numbering each and their last lane the cell after them, so that the high x
+// face of a cell is the low face its next lane kicked (a cell of cb is never
+// the last of its row); the high y and z faces the cell kicks again, by the
+// expression of the cell above, with every distance formed from the cells'
+// own coordinates (the same value).  A face of the union box outside its
+// range is copied unkicked (what the separate kick leaves there).
+template <typename T>
+__global__ void __launch_bounds__(BX * BY) k_kick_compress_fine(Geo G, Phys P, KickArgs<T> A, Box cb, Box ub) {
+#pragma clang fp contract(off)
+  int i, j, k;
+  // no lane leaves before the exchange along x: a lane past the box takes
+  // the box's first cell and writes nothing
+  const bool inb = thread_cell_flat<BX - 1>(ub, i, j, k);
+  const bool own = inb && threadIdx.x < BX - 1;
+  if (!inb) {
+    i = ub.lo[0];
+    j = ub.lo[1];
+    k = ub.lo[2];
+  }
+  const T h = (T)(A.fac * A.dtp[0]);
+  const T rho0 = (T)P.rho0, gm1 = (T)P.gm1, GM = (T)P.GM, eps2 = (T)P.eps2, dx = (T)G.dx;
+  const T *rho = A.q[0], *e = A.q[1];
+  const idx_t c = lin(G, i, j, k);
+  const int id[3] = {i, j, k};
+  auto in_range = [&](int d, int a, int b, int cc) {
+    return a >= A.flo[d][0] && a < A.fhi[d][0] && b >= A.flo[d][1] && b < A.fhi[d][1] && cc >= A.flo[d][2] &&
+           cc < A.fhi[d][2];
+  };
+  const bool comp =
+      own && i >= cb.lo[0] && i < cb.hi[0] && j >= cb.lo[1] && j < cb.hi[1] && k >= cb.lo[2] && k < cb.hi[2];
+  const T xc[3] = {xcen<T>(G, 0, i), xcen<T>(G, 1, j), xcen<T>(G, 2, k)};
+  // distance of the cell whose coordinate along d is xd (the others the cell's)
+  auto dist = [&](int d, T xd) -> T {
+    const T x = d == 0 ? xd : xc[0], y = d == 1 ? xd : xc[1], z = d == 2 ? xd : xc[2];
+    return qsqrt(fmav<T>(x, x, fmav<T>(y, y, fmav<T>(z, z, eps2))));
+  };
+  // the face between cells m (below) and u (above) along d
+  auto kicked = [&](T vf, T drm, T dem, T dru, T deu, T xm, T xu, T dm, T du) -> T {
+    const T rface = fmav<T>(T(0.5), drm + dru, rho0);
+    const T gradp = qdiv(gm1 * (deu - dem), dx * rface);
+    const T gradphi = qdiv(GM * (xu + xm), dm * du * (dm + du));
+    return fmav<T>(-h, gradp + gradphi, vf);
+  };
+  const T drc = rho[c], dec = e[c];
+  const T dcen = dist(0, xc[0]);
+  T vlo[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const idx_t s = dstride(G, d);
+    vlo[d] = A.vin[d][c];
+    if (inb && in_range(d, i, j, k)) {
+      const T xm = xcen<T>(G, d, id[d] - 1);
+      vlo[d] = kicked(vlo[d], rho[c - s], e[c - s], drc, dec, xm, xc[d], dist(d, xm), dcen);
+    }
+    if (own) A.v[d][c] = vlo[d];
+  }
+  const T vhx = from_right(vlo[0]);
+  if (comp) {
+    T divv = T(0) + (vhx - vlo[0]);
+#pragma unroll
+    for (int d = 1; d < 3; ++d) {
+      const idx_t s = dstride(G, d);
+      T vhi = A.vin[d][c + s];
+      if (in_range(d, id[0], id[1] + (d == 1), id[2] + (d == 2))) {
+        const T xu = xcen<T>(G, d, id[d] + 1);
+        vhi = kicked(vhi, drc, dec, rho[c + s], e[c + s], xc[d], xu, dcen, dist(d, xu));
+      }
+      divv += vhi - vlo[d];
+    }
+    const T dt = (T)(A.cfac * A.dtp[0]);
+    const T a = T(0.5) * (T)P.gm1 * dt * qdiv(divv, dx);
+    A.eo[c] = qdiv(fmav<T>(dec, T(1) - a, -(T(2) * a * (T)P.e0)), T(1) + a);
   }
 }
 
@@ -748,34 +859,6 @@ __device__ __forceinline__ bool xcell_at(const Geo &G, int x, int j, int k, idx_
   c = lin(G, x, j, k);
   return true;
 }
-
-// Neighbour exchange inside a wave through the data-parallel-primitive lane
-// shifts: from_left gives every lane the value of the lane below it, from_right
-// that of the lane above it (the end lanes receive 0).
-template <int CTRL>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
-}
-
-template <int CTRL>
-__device__ __forceinline__ float dpp_t(float v) {
-  return __builtin_bit_cast(float, dpp_i<CTRL>(__builtin_bit_cast(int, v)));
-}
-
-template <int CTRL>
-__device__ __forceinline__ double dpp_t(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = dpp_i<CTRL>((int)b), hi = dpp_i<CTRL>((int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
-constexpr int DPP_WAVE_SHL1 = 0x130, DPP_WAVE_SHR1 = 0x138;
-
-template <typename T>
-__device__ __forceinline__ T from_left(T v) { return dpp_t<DPP_WAVE_SHR1>(v); }
-
-template <typename T>
-__device__ __forceinline__ T from_right(T v) { return dpp_t<DPP_WAVE_SHL1>(v); }
 
 // Wave-tiled form of the x pass.  A wave holds 64 consecutive cells of one
 // row, of which lanes 2..61 own their cell (tiles overlap by 4 cells): every
@@ -3697,6 +3780,45 @@ static void kick_compress_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs
   if (G.bc == 2) DFK_LAUNCH((k_kick0p<T, 2, false, true, false, true>), gr, bl, st, G, P, A, R);
   else DFK_LAUNCH((k_kick0p<T, 1, false, true, false, true>), gr, bl, st, G, P, A, R);
 }
+template <typename T>
+static void kick_compress_fine_t(hipStream_t st, const Geo &Gk, const Geo &Gc, const Phys &P, LevBufs &B, int cur,
+                                 const double *dtp, double kfac, double cfac) {
+  KickArgs<T> A{};
+  // the kick's face ranges within Gk's margins (as kick_t), the compression's
+  // cells within Gc's (as compress_t)
+  for (int d = 0; d < 3; ++d)
+    for (int e = 0; e < 3; ++e) {
+      A.flo[d][e] = -Gk.g + (d == e ? 1 : 0);
+      A.fhi[d][e] = Gk.n[e] + Gk.g;
+      clip_margin(Gk, e, d == e, A.flo[d][e], A.fhi[d][e]);
+    }
+  Box ub;
+  for (int e = 0; e < 3; ++e) {
+    ub.lo[e] = min(A.flo[0][e], min(A.flo[1][e], A.flo[2][e]));
+    ub.hi[e] = max(A.fhi[0][e], max(A.fhi[1][e], A.fhi[2][e]));
+  }
+  const Box cb = clip_cells(Gc, uniform_box(Gc, 0, 1));
+  for (int e = 0; e < 3; ++e) {
+    ub.lo[e] = min(ub.lo[e], cb.lo[e]);
+    ub.hi[e] = max(ub.hi[e], cb.hi[e]);
+  }
+  for (int m = 0; m < NQ; ++m) A.q[m] = tp<T>(B.q[cur][m]);
+  for (int d = 0; d < 3; ++d) {
+    A.v[d] = tp<T>(B.vk[d]);
+    A.vin[d] = tp<T>(B.v[d]);
+  }
+  A.dtp = dtp;
+  A.fac = kfac;
+  A.eo = tp<T>(B.etmp);
+  A.cfac = cfac;
+  DFK_LAUNCH(k_kick_compress_fine<T>, grid_of_flat<BX - 1>(ub), dim3(BX, BY), st, Gk, P, A, cb, ub);
+}
+void kick_compress_fine(hipStream_t st, const Geo &Gk, const Geo &Gc, const Phys &P, LevBufs &B, int cur,
+                        const double *dtp, double kfac, double cfac) {
+  if (P.fp32) kick_compress_fine_t<float>(st, Gk, Gc, P, B, cur, dtp, kfac, cfac);
+  else kick_compress_fine_t<double>(st, Gk, Gc, P, B, cur, dtp, kfac, cfac);
+}
+
 void kick_compress(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int cur, const double *dtp, double kfac,
                    double cfac, Scal *slots, double *flog) {
   if (P.fp32) kick_compress_t<float>(st, G, P, B, cur, dtp, kfac, cfac, slots, flog);

@@ -194,8 +194,10 @@ def test_fused_xy_fine_levels_equal_separate_passes(dfm, case, prec):
     assert fa[3] == fb[3]
 
 
+# (in FP32 the finer levels of the nested cases take the fused launch as well)
 KC_CASES = [((32, 16, 8), 1, 0), ((64, 12, 6), 1, 1), ((128, 20, 6), 1, 0), ((16, 16, 16), 2, 0),
-            ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((16, 2, 4), 1, 1), ((8, 4, 2), 1, 1)]
+            ((16, 16, 16), 3, 1), ((16, 2, 4), 1, 0), ((16, 2, 4), 1, 1), ((8, 4, 2), 1, 1),
+            ((24, 24, 24), 4, 0), ((32, 16, 24), 2, 1)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
