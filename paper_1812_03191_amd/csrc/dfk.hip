@@ -2909,11 +2909,17 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
     }
     if (COMP) {
       // x face i+2: the injection face (a zero departure) at x_max, else the
-      // first face of the next pair, kicked as its thread does (lane x)
+      // first face of the next pair: the next lane's (it holds that pair
+      // unless this is the wave's last lane; a lane past the box holds none,
+      // but then this pair is the row's last), else kicked here as the next
+      // pair's thread does
+      const T vnext = dpp_fill<DPP_WAVE_SHL1>(vlo[0].x, T(0));
       V vx1;
       vx1.x = vlo[0].y;
       if (i + 2 == G.n[0]) {
         vx1.y = T(0);
+      } else if (lane < BX - 1) {
+        vx1.y = vnext;
       } else {
         const idx_t cn = c + 2;
         const T xn = xcen<T>(G, 0, i + 2);
