@@ -270,14 +270,15 @@ void level_step(df_run *R, int l, const double *dtp, double scale, int rem) {
   // keeps its role, so the launches of two consecutive steps repeat exactly
   LevBufs Bx = Bt;
   if (!kc) Bx.q[c][1] = B.etmp;
-  // level 0 without a finer level: the x and y passes in one launch, q[c] -> q[1-c]
+  // level 0: the x and y passes in one launch, q[c] -> q[1-c] (under a finer
+  // level with flux matching on its frontier)
   const bool fused = R->fuse_xy && dfk::transport_xy_fits(G);
   // a finer level: its x and y passes in one launch too, unless the
   // quadrant's images must be set between them (a middle level)
   const bool fused_fine = R->fuse_xy && !G.bc && !(R->quad && Gf);
   if (fused) {
     TScope t(R, K_PASSXY);
-    dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk);
+    dfk::transport_xy(st, G, P, Bx, c, dtp, scale, R->chunk, Gf, facc);
   } else if (fused_fine) {
     TScope t(R, K_PASSXY);
     dfk::transport_xy_fine(st, Gy, P, Bx, c, dtp, scale, Gf, facc, R->chunk);

@@ -136,11 +136,12 @@ void kick_compress_fine(hipStream_t st, const Geo &Gk, const Geo &Gc, const Phys
 // chunk: cells per column segment of the streaming y and z passes
 void transport_pass(hipStream_t st, int dir, const Geo &G, const Phys &P, LevBufs &B, int src,
                     const double *dtp, double fac, const Geo *Gf, const void *fine_acc, int chunk);
-// fused x and y passes q[src] -> q[1-src] of level 0 without a finer level
-// (bc 1, at most 128 cells along x, an even count above 64); false, launching
-// nothing, when the level does not qualify
+// fused x and y passes q[src] -> q[1-src] of level 0 (bc 1, at most 128
+// cells along x, an even count above 64); under a finer level Gf, the
+// transfers through its frontier faces are its sums from fine_acc; false,
+// launching nothing, when the level does not qualify
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
-                  double fac, int chunk);
+                  double fac, int chunk, const Geo *Gf, const void *fine_acc);
 bool transport_xy_fits(const Geo &G);
 // fused x and y passes q[src] -> q[1-src] of a finer level (no boundary
 // conditions): G carries the y pass's margins; the entries written and the

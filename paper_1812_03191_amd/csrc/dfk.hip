@@ -1880,12 +1880,37 @@ __device__ __forceinline__ idx_t xy_row_in(const Geo &G, const PassArgs<T> &A, i
   return c;
 }
 
-// the leader's x pass of the density of row r: left-face mass transfers and
-// x-updated departure into the row's slot, with ir also the reciprocal
+// Flux matching under a finer level (FR): the transfers of quantity m
+// through the x faces of row r (the row the pass reads: clamped to the active
+// range) of plane t that lie on the finer level's frontier become the sums of
+// its four fine faces' transfers, as k_xrow takes them.
 template <typename T, int W>
+__device__ __forceinline__ void xy_front_x(const Geo &G, const PassArgs<T> &A, int m, int r, int t, int x0,
+                                           T (&FL)[W]) {
+  const int j = clampi(r, 0, G.n[1] - 1);
+  if (!(j - G.co[1] >= 0 && t - G.co[2] >= 0 && j - G.co[1] < G.cn[1] && t - G.co[2] < G.cn[2])) return;
+  const int flo = G.co[0], fhi = G.co[0] + G.cn[0];
+  const long fnt = (long)A.fn[1] * A.fn[2];
+  const long fbase = (long)(2 * (t - G.co[2])) * A.fn[1] + 2 * (j - G.co[1]);
+#pragma unroll
+  for (int q = 0; q < W; ++q) {
+    const int x = x0 + q;
+    if (x == flo || x == fhi) {
+      const T *f = A.facc + ((long)(x == fhi) * NQ + m) * fnt + fbase;
+      FL[q] = (f[0] + f[1]) + (f[A.fn[1]] + f[A.fn[1] + 1]);
+    }
+  }
+}
+
+// the leader's x pass of the density of row r: left-face mass transfers and
+// x-updated departure into the row's slot, with ir also the reciprocal (FR:
+// the update takes the frontier's transfers, the slot the pass's own, which
+// the other quantities' transfers are formed from)
+template <typename T, int W, bool FR>
 __device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &G, const Phys &P, T dt,
                                                                      const XyShare<T, W> &S, int r,
                                                                      const T (&dr)[W], const T (&da)[W],
+                                                                     const PassArgs<T> &A, int t, int x0,
                                                                      bool ir = true) {
   XRow<T, W> X;
 #pragma unroll
@@ -1896,7 +1921,15 @@ __device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &
   X.flow(G, P, dt);
   X.mass();
   T out[W];
-  X.update(X.dr, X.dM, out);
+  if constexpr (FR) {
+    T F[W];
+#pragma unroll
+    for (int q = 0; q < W; ++q) F[q] = X.dM[q];
+    xy_front_x<T, W>(G, A, 0, r, t, x0, F);
+    X.update(X.dr, F, out);
+  } else {
+    X.update(X.dr, X.dM, out);
+  }
 #pragma unroll
   for (int q = 0; q < W; ++q) {
     S.row(r, 0, q) = X.dM[q];
@@ -1910,7 +1943,7 @@ __device__ __forceinline__ typename lanes_of<T, W>::type xy_lead_row(const Geo &
 // those quantities on whole level-0 rows, with the row's mass transfers taken
 // from the leader; the inputs of the next row are loaded while the y pass uses
 // this one.
-template <typename T, int W, int GRP, int NG>
+template <typename T, int W, int GRP, int NG, bool FR>
 struct XyOwn {
   using V = typename lanes_of<T, W>::type;
   const Geo *G;
@@ -1955,6 +1988,7 @@ struct XyOwn {
           for (int q = 0; q < W; ++q) inq[q] = in[u][q];
         X.quantity(*P, m, inq, sv, own);
         X.transfers(*P, m, sv, F);
+        if constexpr (FR) xy_front_x<T, W>(*G, *A, m, r, t, x0, F);
         X.update(own, F, out);
         w[u] = to_lanes<V, T, W>(out);
       }
@@ -1971,7 +2005,7 @@ struct XyOwn {
 // (its row's distance from c0, mod 3), so that no value is copied from step
 // to step.  put: the lane writes its results (it is live and the plane
 // exists).
-template <typename T, int W, int GRP, int NG, bool LEAD>
+template <typename T, int W, int GRP, int NG, bool LEAD, bool FR>
 __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, const PassArgs<T> &A,
                                                 const MarchArgs<T> &M, T dt, int t, int x0, bool live, bool put,
                                                 int c0, int c1, const XyShare<T, W> &S) {
@@ -2014,6 +2048,42 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
   auto mass_y = [&](V a, V sl, V dl, V sr, V dr) -> V {
     return fmav<V>(upwind(sl, dl, sr, dr, a), a, rho0 * a) * mfac;
   };
+  // flux matching under a finer level (FR): the transfer of quantity m
+  // through y face f of the lane's columns, where that face lies on the finer
+  // level's frontier, becomes the sum of its four fine faces' transfers (as in
+  // march_column); the mass transfers handed to the other waves stay the
+  // pass's own, which their transfers are formed from
+  bool ovy[W];
+  long fby[W];
+  bool anyov = false;
+  if constexpr (FR) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int a1 = x0 + q - G.co[0], a2 = t - G.co[2];
+      ovy[q] = live && a1 >= 0 && a2 >= 0 && a1 < G.cn[0] && a2 < G.cn[2];
+      fby[q] = (long)(2 * a2) * A.fn[0] + 2 * a1;
+      anyov |= ovy[q];
+    }
+  }
+  auto fixy = [&](int f, int m, V F) -> V {
+    if constexpr (FR) {
+      const int fylo = G.co[1], fyhi = G.co[1] + G.cn[1];
+      if (anyov && (f == fylo || f == fyhi)) {
+        const long fnt = (long)A.fn[0] * A.fn[2];
+        T a[W];
+        from_lanes<V, T, W>(F, a);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          if (ovy[q]) {
+            const T *p = A.facc + ((long)(2 + (f == fyhi)) * NQ + m) * fnt + fby[q];
+            a[q] = (p[0] + p[1]) + (p[A.fn[0]] + p[A.fn[0] + 1]);
+          }
+        }
+        return to_lanes<V, T, W>(a);
+      }
+    }
+    return F;
+  };
 
   // leader rings: x-updated density of rows c+1 .. c+3 (rr), its limited
   // difference at c+1 (rd), the mass transfers of faces c, c+1 (rm), the
@@ -2022,15 +2092,15 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
   T ldr[W], lda[W];
   if constexpr (LEAD) {
     xy_row_in<T, W>(G, A, c0 - 2, t, x0, live, ldr, lda);
-    const V r_m2 = xy_lead_row<T, W>(G, P, dt, S, c0 - 2, ldr, lda);
+    const V r_m2 = xy_lead_row<T, W, FR>(G, P, dt, S, c0 - 2, ldr, lda, A, t, x0);
     xy_row_in<T, W>(G, A, c0 - 1, t, x0, live, ldr, lda);
-    const V r_m1 = xy_lead_row<T, W>(G, P, dt, S, c0 - 1, ldr, lda);
+    const V r_m1 = xy_lead_row<T, W, FR>(G, P, dt, S, c0 - 1, ldr, lda, A, t, x0);
     xy_row_in<T, W>(G, A, c0, t, x0, live, ldr, lda);
-    const V r_0 = xy_lead_row<T, W>(G, P, dt, S, c0, ldr, lda);
+    const V r_0 = xy_lead_row<T, W, FR>(G, P, dt, S, c0, ldr, lda, A, t, x0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       xy_row_in<T, W>(G, A, c0 + 1 + k, t, x0, live, ldr, lda);
-      rr[k] = xy_lead_row<T, W>(G, P, dt, S, c0 + 1 + k, ldr, lda, k < 2);
+      rr[k] = xy_lead_row<T, W, FR>(G, P, dt, S, c0 + 1 + k, ldr, lda, A, t, x0, k < 2);
     }
     xy_row_in<T, W>(G, A, c0 + 4, t, x0, live, ldr, lda);
     const V d_m1 = vleer(r_0 - r_m1, r_m1 - r_m2);
@@ -2047,7 +2117,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
   // own rings: specific values at c, c+1 (ss), limited difference at c (sd),
   // transfer through face c (sF), x-updated departures of rows c .. c+2 (sw),
   // velocity departure of face c+1 (sv)
-  XyOwn<T, W, GRP, NG> src{&G, &P, &A, dt, t, x0, live};
+  XyOwn<T, W, GRP, NG, FR> src{&G, &P, &A, dt, t, x0, live};
   V ss[3][4], sd[3][4], sF[3][4], sw[3][4], sv[3];
   if constexpr (nq > 0) {
     V wm2[4], wm1[4];
@@ -2069,7 +2139,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
       const V dm1 = limited(x0, i_0, sm1, sm2);
       sd[0][u] = limited(x1, i_p1, ss[0][u], sm1);
       const V fv = upwind(sm1, dm1, ss[0][u], sd[0][u], a);
-      sF[0][u] = zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM);
+      sF[0][u] = fixy(c0, mq[u], zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM));
     }
     src.get(c0 + 2, S, sw[2]);
     sv[0] = face(c0 + 1);
@@ -2091,7 +2161,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
         ss[K2][u] = x2 * ir2;
         sd[K1][u] = limited(x2, ir2, ss[K1][u], ss[K0][u]);
         const V fv = upwind(ss[K0][u], sd[K0][u], ss[K1][u], sd[K1][u], a);
-        sF[K1][u] = zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM);
+        sF[K1][u] = fixy(c + 1, mq[u], zq[u] ? fv * dM : fmav<V>(V(sb[u]), dM, fv * dM));
         if (put) gstv<V>(qout[u], ic, fmav<V>(-(sF[K1][u] - sF[K0][u]), V(ivol), sw[K0][u]));
       }
       src.get(c + 3, S, sw[K0]);
@@ -2103,12 +2173,12 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
       for (int q = 0; q < W; ++q) S.row(c + 3, 2, q) = qdiv(T(1), rho0 * (rho0 + S.row(c + 3, 1, q)));
     }
     if constexpr (LEAD) {
-      if (put) gstv<V>(M.qo[0], ic, fmav<V>(-(rm[K1] - rm[K0]), V(ivol), S.rowv(c, 1)));
+      if (put) gstv<V>(M.qo[0], ic, fmav<V>(-(fixy(c + 1, 0, rm[K1]) - fixy(c, 0, rm[K0])), V(ivol), S.rowv(c, 1)));
       rd[K1] = vleer(rr[K2] - rr[K1], rr[K1] - rr[K0]);
       rm[K2] = mass_y(rv[K0], rr[K0], rd[K0], rr[K1], rd[K1]);
       S.put_face(c + 2, rm[K2]);
       rv[K1] = face(min(c + 3, c1));
-      rr[K0] = xy_lead_row<T, W>(G, P, dt, S, c + 4, ldr, lda, false);
+      rr[K0] = xy_lead_row<T, W, FR>(G, P, dt, S, c + 4, ldr, lda, A, t, x0, false);
       xy_row_in<T, W>(G, A, c + 5, t, x0, live, ldr, lda);
     }
     __syncthreads();
@@ -2126,7 +2196,7 @@ __device__ __forceinline__ void xy_shared_group(const Geo &G, const Phys &P, con
 // leads the density.  Only the y pass's results reach HBM.  Results are those
 // of the separate passes up to the pairing of products and sums into fused
 // multiply-adds.
-template <typename T, int W, bool FULL>
+template <typename T, int W, bool FULL, bool FR>
 __device__ __forceinline__ void xyshared_body(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M, Blk bk) {
   constexpr int NG = 4;
   __shared__ T rows[XY_RS * 3 * W * 64];
@@ -2141,16 +2211,16 @@ __device__ __forceinline__ void xyshared_body(Geo G, Phys P, PassArgs<T> A, Marc
   const bool live = FULL || x0 < G.n[0];  // FULL: the rows fill the wave exactly
   const T dt = (T)(A.fac * A.dtp[0]);
   const XyShare<T, W> S{rows, faces, lane};
-  if (grp == 0) xy_shared_group<T, W, 0, NG, true>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
-  else if (grp == 1) xy_shared_group<T, W, 1, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
-  else if (grp == 2) xy_shared_group<T, W, 2, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
-  else xy_shared_group<T, W, 3, NG, false>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  if (grp == 0) xy_shared_group<T, W, 0, NG, true, FR>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else if (grp == 1) xy_shared_group<T, W, 1, NG, false, FR>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else if (grp == 2) xy_shared_group<T, W, 2, NG, false, FR>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
+  else xy_shared_group<T, W, 3, NG, false, FR>(G, P, A, M, dt, t, x0, live, live, c0, c1, S);
 }
 
-template <typename T, int W, bool FULL>
+template <typename T, int W, bool FULL, bool FR = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_xyshared(Geo G, Phys P, PassArgs<T> A, MarchArgs<T> M) {
-  xyshared_body<T, W, FULL>(G, P, A, M, grid_blk());
+  xyshared_body<T, W, FULL, FR>(G, P, A, M, grid_blk());
 }
 
 // ------------------------------------------------------------ CommUp
@@ -3675,7 +3745,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   Blk bk;
   if (!job_of(t, blockIdx.x, r, bk)) return;
   const XyJob<T> &J = t.e[r];
-  xyshared_body<T, W, FULL>(J.G, J.P, J.A, J.M, bk);
+  xyshared_body<T, W, FULL, false>(J.G, J.P, J.A, J.M, bk);
 }
 
 template <typename T>
@@ -4088,12 +4158,12 @@ static void transport_pass_t(hipStream_t st, int dir, const Geo &G, const Phys &
 }
 bool transport_xy_fits(const Geo &G) {
   const int n = G.n[0];
-  return G.bc == 1 && !G.has_fine && n <= 2 * BX && (n <= BX || n % 2 == 0);
+  return G.bc == 1 && n <= 2 * BX && (n <= BX || n % 2 == 0);
 }
 
 template <typename T>
 static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp,
-                           double fac, int chunk) {
+                           double fac, int chunk, const Geo *Gf, const void *fine_acc) {
   const int n = G.n[0];
   if (!transport_xy_fits(G)) return false;
   PassArgs<T> A;
@@ -4105,14 +4175,16 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   for (int d = 0; d < 3; ++d) A.v[d] = tp<T>(B.v[d]);
   A.dtp = dtp;
   A.fac = fac;
+  // under a finer level: flux matching on its frontier (level 0 accumulates
+  // nothing)
   A.acc = nullptr;
-  A.facc = nullptr;
-  for (int d = 0; d < 3; ++d) A.fn[d] = 0;
+  A.facc = (G.has_fine && fine_acc) ? reinterpret_cast<const T *>(fine_acc) : nullptr;
+  for (int d = 0; d < 3; ++d) A.fn[d] = A.facc ? Gf->n[d] : 0;
   MarchArgs<T> M;
   for (int d = 0; d < 3; ++d) {
     M.lo[d] = A.b.lo[d];
     M.hi[d] = A.b.hi[d];
-    M.fn[d] = 0;
+    M.fn[d] = A.fn[d];
   }
   M.chunk = G.n[1] <= chunk ? G.n[1] : chunk;
   for (int m = 0; m < NQ; ++m) {
@@ -4123,10 +4195,17 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   M.dtp = dtp;
   M.fac = fac;
   M.acc = nullptr;
-  M.facc = nullptr;
+  M.facc = A.facc;
   // one block of four waves per (plane, y segment)
   const long nch = (G.n[1] + M.chunk - 1) / M.chunk;
   const dim3 gr((unsigned)(G.n[2] * nch)), bl(64, 4);
+  if (A.facc) {
+    if (n == BX) DFK_LAUNCH((k_xyshared<T, 1, true, true>), gr, bl, st, G, P, A, M);
+    else if (n < BX) DFK_LAUNCH((k_xyshared<T, 1, false, true>), gr, bl, st, G, P, A, M);
+    else if (n == 2 * BX) DFK_LAUNCH((k_xyshared<T, 2, true, true>), gr, bl, st, G, P, A, M);
+    else DFK_LAUNCH((k_xyshared<T, 2, false, true>), gr, bl, st, G, P, A, M);
+    return true;
+  }
   if (record(jk_xy<T>(n), XyJob<T>{G, P, A, M, gr.x})) return true;
   if (n == BX) DFK_LAUNCH((k_xyshared<T, 1, true>), gr, bl, st, G, P, A, M);
   else if (n < BX) DFK_LAUNCH((k_xyshared<T, 1, false>), gr, bl, st, G, P, A, M);
@@ -4135,9 +4214,9 @@ static bool transport_xy_t(hipStream_t st, const Geo &G, const Phys &P, LevBufs 
   return true;
 }
 bool transport_xy(hipStream_t st, const Geo &G, const Phys &P, LevBufs &B, int src, const double *dtp, double fac,
-                  int chunk) {
-  if (P.fp32) return transport_xy_t<float>(st, G, P, B, src, dtp, fac, chunk);
-  return transport_xy_t<double>(st, G, P, B, src, dtp, fac, chunk);
+                  int chunk, const Geo *Gf, const void *fine_acc) {
+  if (P.fp32) return transport_xy_t<float>(st, G, P, B, src, dtp, fac, chunk, Gf, fine_acc);
+  return transport_xy_t<double>(st, G, P, B, src, dtp, fac, chunk, Gf, fine_acc);
 }
 
 template <typename T>

@@ -155,7 +155,9 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
     assert fa[3] == fb[3]
 
 
-# Fused x and y passes of the finer levels against separate ones: finer rows
+# Fused x and y passes of the finer levels, and of level 0 under them (with
+# flux matching on their frontier; rows of 16 to 128 cells), against separate
+# ones: finer rows
 # (with their margins) in one 64-lane tile (16^3 levels), two (64^3) and three
 # (128^3 with one finer level, both sub-steps' margins), y extents of one
 # 32-row segment and of several, a middle level taking a finer level's
