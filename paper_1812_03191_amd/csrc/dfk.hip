@@ -2780,6 +2780,15 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
   using V = typename lanes_of<T, 2>::type;
   int p, j, k;
   const bool ok = thread_cell_flat(A.b, p, j, k, bk);
+  // with COMP in FP64, a block whose threads all hold pairs (the same for
+  // all its threads) hands each pair's low y faces to the pairs below them in
+  // the block, which then need not kick their high y faces again (128^3: the
+  // FP64 step 0.7 % faster; in FP32, where the kick is cheap, no faster)
+  const int tid = threadIdx.y * BX + threadIdx.x;
+  const int exb = A.b.hi[0] - A.b.lo[0];
+  const long fl = (long)(j - A.b.lo[1]) * exb + (p - A.b.lo[0]);
+  const bool full = COMP && sizeof(T) == 8 && fl - tid + BX * BY <= (long)exb * (A.b.hi[1] - A.b.lo[1]);
+  const bool yx = full && tid + exb < BX * BY;
   double fx = 0.0, fy = 0.0, fz = 0.0;
   T sig = T(0);
   int bad = 0;
@@ -2788,7 +2797,6 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
   double dtk = 0.0;
   if (A.slots) {
     __shared__ double shs[BX * BY / 64];
-    const int tid = threadIdx.y * BX + threadIdx.x;
     double m = 0.0;
     for (int q = tid; q < NSLOT; q += BX * BY) m = fmax(m, __longlong_as_double((long long)A.slots->smax[q]));
     m = wave_max(m);
@@ -2967,7 +2975,7 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
           vhi[d] = vf;
           if (POST) vmax(vabs((T)vback(P, d) + vf) + cs_own);
         }
-      } else if (COMP) {
+      } else if (COMP && !(d == 1 && yx)) {
         // face id+1: the low face of the next cells, kicked as their thread
         // does (the own cells below it)
         const idx_t cn = c + sd;
@@ -2976,6 +2984,14 @@ __device__ __forceinline__ void kick0p_body(Geo G, Phys P, KickArgs<T> A, RedArg
         vhi[d] = kickv(d, gldv<V>(A.vin[d], cn), drc, dec, gldv<V>(rho, cn), gldv<V>(e, cn), V(xn), dcen,
                        qsqrtv(r2n));
       }
+    }
+    if (COMP && full) {
+      // the pairs above in the block: their low y faces (every thread of a
+      // full block is here)
+      __shared__ V ylo[BX * BY];
+      ylo[tid] = vlo[1];
+      __syncthreads();
+      if (yx && id[1] != G.n[1] - 1) vhi[1] = ylo[tid + exb];
     }
     if (COMP) {
       // x face i+2: the injection face (a zero departure) at x_max, else the
