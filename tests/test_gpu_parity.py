@@ -157,19 +157,19 @@ def test_fused_xy_equals_separate_passes(dfm, n, prec):
 
 # Fused x and y passes of the finer levels, and of level 0 under them (with
 # flux matching on their frontier; rows of 16 to 128 cells), against separate
-# ones: finer rows
-# (with their margins) in one 64-lane tile (16^3 levels), two (64^3) and three
+# ones: finer rows (with their margins) in one 64-lane tile (16^3 levels), two (64^3) and three
 # (128^3 with one finer level, both sub-steps' margins), y extents of one
 # 32-row segment and of several, a middle level taking a finer level's
 # frontier transfers, the quadrant's finest level, and supersonic runs with
 # the artificial viscosity.  Rows whose last cells take half-wave tiles (FP64): 18
 # and 26 cells (16^3), 76 and 66 (64^3), 140 and 130 (128^3), 62 (48^3 with
 # the viscosity), and 63 over an odd number of planes (the middle level of the
-# last case, whose last half-wave tile has no second plane).
+# last case but one, whose last half-wave tile has no second plane); level 0
+# with two cells per lane on rows that fill part of the wave (96 cells).
 FINE_XY_CASES = [((16, 16, 16), 3, False, 4, 0.0), ((64, 64, 64), 2, False, 3, 0.0),
                  ((32, 32, 32), 3, False, 2, 0.0), ((128, 128, 128), 2, False, 1, 0.0),
                  ((32, 16, 16), 2, True, 3, 0.0), ((48, 48, 48), 2, False, 3, 2.0),
-                 ((48, 48, 48), 3, False, 2, 2.0)]
+                 ((48, 48, 48), 3, False, 2, 2.0), ((96, 80, 64), 2, False, 2, 0.0)]
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
