@@ -197,23 +197,25 @@ int df_set_viscosity(df_run *run, double c2);
 
 /* Launch shape of the transport step (the x, y, z passes of T in eq. 15,
  * Sect. 3.2.3 and 3.3): on (1, default) the x and y passes of level 0 run
- * as one launch when level 0 has no finer level, uses the default boundaries
- * and has at most 128 cells along x (an even count above 64), and those of
- * every finer level (in the quadrant, of a finer level with no finer one):
- * each row's x pass is taken in registers and fed to the y pass, so the x
- * pass's results never reach device memory.  off (0): every pass is a launch
- * of its own.  The
+ * as one launch when level 0 uses the default boundaries and has at most 128
+ * cells along x (an even count above 64; under a finer level, with the flux
+ * matching on its frontier inside the launch), and those of every finer level
+ * (in the quadrant, of a finer level with no finer one): each row's x pass is
+ * taken in registers and fed to the y pass, so the x pass's results never
+ * reach device memory.  off (0): every pass is a launch of its own.  The
  * results agree to rounding either way (the same operations in the same order;
  * the compiler may pair a product and a sum into one fused multiply-add
  * differently); DF_EINVAL for other values. */
 int df_set_transport_fusion(df_run *run, int32_t on);
 
-/* Launch shape of the first two sub-steps of a level-0 step (the velocity
+/* Launch shape of the first two sub-steps of a level step (the velocity
  * source S(dt/2) of eq. 15 and the compressional heating of Sect. 3.3, as
- * SubStep1 and SubStep3): on (1, default) one launch when the artificial
- * viscosity is off, whose threads kick their cells' faces and then compress
- * their cells from the kicked velocities of all six faces (the faces of
- * neighbouring cells are kicked again with the same arithmetic, not stored);
+ * SubStep1 and SubStep3): on (1, default) one launch on level 0, and on the
+ * finer levels of an FP32 run, when the artificial viscosity is off, whose
+ * threads kick their cells' faces and then compress their cells from the
+ * kicked velocities of all six faces (the faces of neighbouring cells are
+ * taken from the neighbouring threads or kicked again with the same
+ * arithmetic, not stored);
  * the kicked velocities and the compressed energy go to buffers of their own,
  * so that every thread reads the state before the step.  off (0): two
  * launches.  The results agree to rounding either way; DF_EINVAL for other

@@ -303,7 +303,7 @@ class Run:
         _ck(_load().df_set_transport_fusion(self._h, int(bool(on))))
 
     def set_kick_fusion(self, on: bool) -> None:
-        """kick and compress level 0 in one launch where it qualifies (default on)"""
+        """kick and compress in one launch where it qualifies: level 0, and the finer levels in FP32 (default on)"""
         _ck(_load().df_set_kick_fusion(self._h, int(bool(on))))
 
     def set_finish_fusion(self, on: bool) -> None:
