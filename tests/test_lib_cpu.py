@@ -121,3 +121,15 @@ def test_force_density_validates_before_any_device_call():
     assert lib.df_force_density(rho, big, big, big, 0.1, 0.01, 0.0, 1.0, out, None) == -1
     assert "MAX_CELLS" in lib.df_last_error().decode()
     assert dfm.DFError
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the measurement runs on one GPU: asking for more exits with a message
+    # before any device work
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2, (r.returncode, r.stderr)
+    assert "one GPU" in r.stderr and not r.stdout.strip()
