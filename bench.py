@@ -193,6 +193,7 @@ def nested(steps=None, warm=2):
         ms = e0.elapsed_time(e1)
         forces[name] = run.force()
         out[name] = {"cell_updates_per_s": cells * K / (ms / 1e3), "ms_per_coarse_step": ms / K}
+        print(f"[bench] nested {name}: {K} coarse steps, {ms / K:.3f} ms each", file=sys.stderr, flush=True)
         del run
         torch.cuda.empty_cache()
     f64, f32 = forces["fp64"], forces["fp32"]
@@ -410,6 +411,8 @@ def main():
                     help="run the workload this long before the warmup steps (GPU clock ramp; 0: off)")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--nested-steps", type=int, default=None,
+                    help="coarse steps of the nested leg (default 100; fewer under a counter profiler)")
     ap.add_argument("--no-batched", action="store_true", help="run none of the extra legs")
     ap.add_argument("--legs", default="fp32,batched,nested",
                     help="extra legs to run: any of fp32, batched, nested (comma separated)")
@@ -535,7 +538,7 @@ def main():
         extra["batched"] = batched_sweep()
     if "nested" in legs:
         print("[bench] nested 4 x 128^3 (FP64 and FP32)", file=sys.stderr, flush=True)
-        extra["nested"] = nested()
+        extra["nested"] = nested(args.nested_steps)
     if args.serve_jobs > 0:
         print(f"[bench] serving {args.serve_jobs} jobs", file=sys.stderr, flush=True)
         extra["serving"] = serving(args.serve_jobs)
