@@ -177,7 +177,7 @@ def nested(steps=None, warm=2):
     cfg, K = inputs.config3()
     K = steps or K
     cells = cfg["nx"] * cfg["ny"] * cfg["nz"] * sum(2 ** l for l in range(cfg["nlevels"]))
-    out = {"workload": "4 levels of 128^3, Mach 0.3, GM 1e-3, chi 0.1, L 1e-3, 100 coarse steps, seed 3"}
+    out = {"workload": f"4 levels of 128^3, Mach 0.3, GM 1e-3, chi 0.1, L 1e-3, {K} coarse steps, seed 3"}
     forces = {}
     for name, prec in (("fp64", dfm.DF_FP64), ("fp32", dfm.DF_FP32)):
         run = dfm.Run(cfg["nx"], cfg["ny"], cfg["nz"], nlevels=cfg["nlevels"], dx0=cfg["dx0"],
